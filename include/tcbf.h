@@ -1,0 +1,177 @@
+/*
+ * tcbf.h -- batched complex beamforming product on AMD MI355X (gfx950).
+ *
+ * The library computes, for every channel (or frame) c of a batch,
+ *
+ *     B[c] = W[c] . X[c]          W: M x K,  X: K x N,  B: M x N, all complex
+ *
+ * i.e. Eq. (3) of the Tensor-Core Beamformer paper (each beam output is the
+ * weighted sum of the K receiver signals) evaluated for N samples at once,
+ * which Sec. II maps to a matrix product with M = beams, N = samples and
+ * K = receivers.  There is no conjugation.  Two input precisions exist, as in
+ * Sec. III: 16-bit float and 1-bit (sign only, Sec. III-D).
+ *
+ * Every entry point is a plain C function over plain pointers and sizes.
+ * Device pointers are HIP device (or managed) allocations; `stream` is a
+ * hipStream_t passed as void* (NULL = the default stream).  No entry point
+ * throws, aborts or allocates device memory in the execution calls.
+ *
+ * Ownership: the caller owns every buffer.  The library never frees, retains
+ * or caches a user pointer after a call returns.  A plan owns only host
+ * memory and is released with tcbf_plan_destroy.
+ *
+ * Errors: invalid sizes, NULL or misaligned pointers and unsupported
+ * combinations are rejected synchronously, before anything is enqueued, with
+ * TCBF_ERROR_INVALID_VALUE or TCBF_ERROR_NOT_SUPPORTED.  A failed launch returns
+ * TCBF_ERROR_DEVICE.  Faults while a kernel runs surface at the caller's next
+ * synchronisation with the stream, as with any HIP launch.
+ */
+#ifndef TCBF_H
+#define TCBF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TCBF_VERSION 1
+
+typedef enum tcbf_status {
+    TCBF_SUCCESS = 0,
+    TCBF_ERROR_INVALID_VALUE = 1, /* bad size, pointer, alignment or enum value  */
+    TCBF_ERROR_NOT_SUPPORTED = 2, /* valid request this build/device cannot run  */
+    TCBF_ERROR_OUT_OF_MEMORY = 3, /* host allocation for a plan failed           */
+    TCBF_ERROR_DEVICE = 4,        /* HIP runtime error (no device, launch failed) */
+    TCBF_ERROR_INTERNAL = 5
+} tcbf_status;
+
+/* Input precision of W and X (Sec. III: 16-bit float and 1-bit). */
+typedef enum tcbf_dtype {
+    TCBF_F16 = 0,  /* fp16 in, fp32 accumulate, fp32 complex out              */
+    TCBF_INT1 = 1  /* packed sign bits in, exact int32 complex out            */
+} tcbf_dtype;
+
+/* Complex storage.  PLANAR keeps a real plane then an imaginary plane for each
+ * batch entry; INTERLEAVED stores (re, im) pairs (the "usual interleaved
+ * format" of Sec. VI). */
+typedef enum tcbf_layout {
+    TCBF_PLANAR = 0,
+    TCBF_INTERLEAVED = 1
+} tcbf_layout;
+
+/* Element type of a source array for tcbf_pack1bit. */
+typedef enum tcbf_src_type {
+    TCBF_SRC_I8 = 0,
+    TCBF_SRC_F16 = 1,
+    TCBF_SRC_F32 = 2
+} tcbf_src_type;
+
+/*
+ * Problem description.  Sizes are element counts (complex elements).
+ *
+ * TCBF_F16 buffer layouts (fp16 = IEEE binary16, fp32 = IEEE binary32):
+ *   A = W   planar      [batch][2][M][K]   K contiguous
+ *           interleaved [batch][M][K][2]
+ *   B = X   planar      [batch][2][K][N]   N contiguous
+ *           interleaved [batch][K][N][2]
+ *   C = out planar      [batch][2][M][N]   fp32
+ *           interleaved [batch][M][N][2]   fp32
+ *
+ * TCBF_INT1 buffer layouts (packed as tcbf_pack1bit writes them; kw = ceil(K/32)):
+ *   A = W   [batch][2][M][kw]  uint32, sample k in bit k%32 of word k/32
+ *   B = X   [batch][2][N][kw]  uint32, packed along K for each sample n
+ *   C = out planar [batch][2][M][N] or interleaved [batch][M][N][2], int32
+ *   a_layout and b_layout must be TCBF_PLANAR (the packed form).  Bits past K
+ *   in the last word must be 0 (tcbf_pack1bit guarantees it).
+ *
+ * a_shared != 0: W holds a single batch entry that every channel uses.
+ * C is always overwritten (the output starts from zero, as in Sec. III-B).
+ */
+typedef struct tcbf_plan_desc {
+    uint32_t struct_size; /* sizeof(tcbf_plan_desc), for ABI growth            */
+    int32_t device;       /* HIP device ordinal the plan executes on           */
+    int64_t batch;        /* >= 1                                              */
+    int64_t M;            /* beams, >= 1                                       */
+    int64_t N;            /* samples, >= 1                                     */
+    int64_t K;            /* receivers, >= 1                                   */
+    int32_t dtype;        /* tcbf_dtype                                        */
+    int32_t a_layout;     /* tcbf_layout of W                                  */
+    int32_t b_layout;     /* tcbf_layout of X                                  */
+    int32_t c_layout;     /* tcbf_layout of the output                         */
+    int32_t a_shared;     /* nonzero: one W for all batch entries              */
+    int32_t variant;      /* 0 = automatic kernel choice; >0 forces a variant  */
+} tcbf_plan_desc;
+
+typedef struct tcbf_plan_s *tcbf_plan_t;
+
+/* What a plan chose; filled by tcbf_plan_query. */
+typedef struct tcbf_plan_info {
+    uint32_t struct_size;
+    int32_t variant;           /* kernel variant id actually used             */
+    int32_t tile_m, tile_n;    /* complex outputs per workgroup                */
+    int32_t tile_k;            /* K per main-loop stage                        */
+    int32_t threads;           /* threads per workgroup                        */
+    int64_t workgroups;        /* workgroups per launch                        */
+    double useful_ops;         /* 8*M*N*K*batch (Sec. IV-A op count)           */
+    double algorithmic_bytes;  /* each input read once, output written once    */
+    char kernel_name[64];      /* name of the main kernel (for profilers)      */
+} tcbf_plan_info;
+
+/*
+ * tcbf_plan -- validate a problem and choose the kernel configuration
+ * (Sec. III-C/IV-A: tile sizes are picked automatically for the device and
+ * shapes).  Host-only; enqueues nothing.
+ * Returns INVALID_VALUE for a NULL argument, a struct_size smaller than the
+ * version-1 struct, non-positive sizes, unknown enum values or layouts the
+ * dtype does not accept; NOT_SUPPORTED when `device` is not a gfx950 device
+ * (or sizes exceed the kernels' 32-bit index limits); DEVICE when the HIP
+ * runtime cannot report the device.  On success *plan owns host memory only.
+ */
+tcbf_status tcbf_plan(const tcbf_plan_desc *desc, tcbf_plan_t *plan);
+
+/*
+ * tcbf_execute -- enqueue B = W . X on `stream` (Sec. III-B: four real
+ * products per complex product, Im(X) negated in registers; Sec. III-D for
+ * TCBF_INT1).  A, B, C are device pointers in the plan's layouts, each 16-byte
+ * aligned; C must not overlap A or B.  a_scale and b_scale are reserved and
+ * must be NULL.  Asynchronous, allocation-free and graph-capturable.
+ * The device that is current on the calling thread must be the plan's device.
+ */
+tcbf_status tcbf_execute(tcbf_plan_t plan, const void *A, const void *B, void *C,
+                         const float *a_scale, const float *b_scale, void *stream);
+
+/*
+ * tcbf_pack1bit -- sign-pack complex data for TCBF_INT1 (Sec. III kernels
+ * paragraph: 32 consecutive 1-bit samples per 32-bit word; Sec. III-D and
+ * Fig. 1: per component bit 1 = +1, bit 0 = -1).
+ *   sign rule: integers: bit = (x >= 0); floats: bit = sign bit clear, so +0
+ *   gives +1 and -0 gives -1.
+ *   src (device), element type src_type, complex layout src_layout:
+ *     src_k_major != 0:  planar [batch][2][rows][K]   or interleaved [batch][rows][K][2]
+ *     src_k_major == 0:  planar [batch][2][K][rows]   or interleaved [batch][K][rows][2]
+ *   (W is K-major with rows = M; X as beamformer data [K][N] is not, rows = N.)
+ *   dst (device): [batch][2][rows][ceil(K/32)] uint32, LSB first, pad bits 0.
+ * src and dst must be 16-byte aligned device pointers that do not overlap.
+ */
+tcbf_status tcbf_pack1bit(const void *src, int32_t src_type, int32_t src_layout,
+                          int64_t batch, int64_t rows, int64_t K, int32_t src_k_major,
+                          uint32_t *dst, void *stream);
+
+/* Report the plan's choice.  info->struct_size must be set by the caller. */
+tcbf_status tcbf_plan_query(tcbf_plan_t plan, tcbf_plan_info *info);
+
+/* Release a plan (NULL is accepted).  Must not race with tcbf_execute on it. */
+tcbf_status tcbf_plan_destroy(tcbf_plan_t plan);
+
+/* Static, human-readable name of a status code. */
+const char *tcbf_status_string(tcbf_status status);
+
+/* TCBF_VERSION of the built library. */
+int32_t tcbf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TCBF_H */

@@ -47,8 +47,15 @@ def _load():
     lib.oracle_dot1bit_xor.restype = _i64
     lib.oracle_dot1bit_and.argtypes = [_i64, _p, _p]
     lib.oracle_dot1bit_and.restype = _i64
+    lib.oracle_num_threads.argtypes = []
+    lib.oracle_num_threads.restype = _int
     _lib = lib
     return lib
+
+
+def num_threads():
+    """Threads the oracle's parallel loops use."""
+    return int(_load().oracle_num_threads())
 
 
 def _c(a, dtype):

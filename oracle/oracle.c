@@ -21,6 +21,19 @@
 #include <math.h>
 #include <stdint.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Threads the parallel loops below will use (1 without OpenMP). */
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 #define ORACLE_W_OFF(c, w_shared, M, K) ((w_shared) ? (int64_t)0 : (int64_t)(c) * (M) * (K))
 

@@ -1,0 +1,216 @@
+"""tcbf -- batched complex beamforming product B[c] = W[c] X[c] on MI355X.
+
+Thin ctypes binding over the C ABI in ``include/tcbf.h`` (``libtcbf.so``).
+This module only marshals arguments: every step of the computation runs in
+the library's HIP kernels.  torch tensors are accepted for device memory and
+streams; the current torch stream is passed to the library.
+
+If the shared library is missing, importing works but every call raises
+``TcbfError``; there is no fallback implementation.
+"""
+import ctypes
+import os
+
+__all__ = [
+    "F16", "INT1", "PLANAR", "INTERLEAVED", "SRC_I8", "SRC_F16", "SRC_F32",
+    "TcbfError", "Plan", "pack1bit", "lib", "status_string", "EXPORTS",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtcbf.so")
+
+F16, INT1 = 0, 1
+PLANAR, INTERLEAVED = 0, 1
+SRC_I8, SRC_F16, SRC_F32 = 0, 1, 2
+
+# every symbol include/tcbf.h declares
+EXPORTS = ("tcbf_plan", "tcbf_execute", "tcbf_pack1bit", "tcbf_plan_query",
+           "tcbf_plan_destroy", "tcbf_status_string", "tcbf_version")
+
+_STATUS = {0: "TCBF_SUCCESS", 1: "TCBF_ERROR_INVALID_VALUE", 2: "TCBF_ERROR_NOT_SUPPORTED",
+           3: "TCBF_ERROR_OUT_OF_MEMORY", 4: "TCBF_ERROR_DEVICE", 5: "TCBF_ERROR_INTERNAL"}
+
+
+class TcbfError(RuntimeError):
+    def __init__(self, status, what=""):
+        self.status = status
+        super().__init__("%s%s" % (_STATUS.get(status, "status %d" % status), (": " + what) if what else ""))
+
+
+class PlanDesc(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("device", ctypes.c_int32),
+                ("batch", ctypes.c_int64), ("M", ctypes.c_int64), ("N", ctypes.c_int64),
+                ("K", ctypes.c_int64), ("dtype", ctypes.c_int32), ("a_layout", ctypes.c_int32),
+                ("b_layout", ctypes.c_int32), ("c_layout", ctypes.c_int32),
+                ("a_shared", ctypes.c_int32), ("variant", ctypes.c_int32)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("variant", ctypes.c_int32),
+                ("tile_m", ctypes.c_int32), ("tile_n", ctypes.c_int32), ("tile_k", ctypes.c_int32),
+                ("threads", ctypes.c_int32), ("workgroups", ctypes.c_int64),
+                ("useful_ops", ctypes.c_double), ("algorithmic_bytes", ctypes.c_double),
+                ("kernel_name", ctypes.c_char * 64)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libtcbf.so (raises TcbfError if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise TcbfError(4, "libtcbf.so not built (run python -m paper_2505_03269_amd.build)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+    L.tcbf_plan.argtypes = [ctypes.POINTER(PlanDesc), ctypes.POINTER(vp)]
+    L.tcbf_plan.restype = i32
+    L.tcbf_execute.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    L.tcbf_execute.restype = i32
+    L.tcbf_pack1bit.argtypes = [vp, i32, i32, i64, i64, i64, i32, vp, vp]
+    L.tcbf_pack1bit.restype = i32
+    L.tcbf_plan_query.argtypes = [vp, ctypes.POINTER(PlanInfo)]
+    L.tcbf_plan_query.restype = i32
+    L.tcbf_plan_destroy.argtypes = [vp]
+    L.tcbf_plan_destroy.restype = i32
+    L.tcbf_status_string.argtypes = [i32]
+    L.tcbf_status_string.restype = ctypes.c_char_p
+    L.tcbf_version.argtypes = []
+    L.tcbf_version.restype = i32
+    _lib = L
+    return L
+
+
+def status_string(status):
+    return lib().tcbf_status_string(status).decode()
+
+
+def _check(status, what=""):
+    if status != 0:
+        raise TcbfError(status, what)
+
+
+def _stream_handle(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_ptr(t, name):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % name)
+    if not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """A validated problem (tcbf_plan).  Shapes follow include/tcbf.h."""
+
+    def __init__(self, batch, M, N, K, dtype=F16, a_layout=PLANAR, b_layout=PLANAR,
+                 c_layout=PLANAR, a_shared=False, variant=0, device=0):
+        d = PlanDesc(ctypes.sizeof(PlanDesc), int(device), int(batch), int(M), int(N), int(K),
+                     int(dtype), int(a_layout), int(b_layout), int(c_layout), int(bool(a_shared)),
+                     int(variant))
+        h = ctypes.c_void_p()
+        self._h = None
+        _check(lib().tcbf_plan(ctypes.byref(d), ctypes.byref(h)), "tcbf_plan")
+        self._h = h
+        self.desc = d
+        self.batch, self.M, self.N, self.K = int(batch), int(M), int(N), int(K)
+        self.dtype, self.a_layout, self.b_layout, self.c_layout = dtype, a_layout, b_layout, c_layout
+        self.a_shared = bool(a_shared)
+        self.device = int(device)
+
+    def __del__(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.tcbf_plan_destroy(self._h)
+            self._h = None
+
+    def info(self):
+        i = PlanInfo()
+        i.struct_size = ctypes.sizeof(PlanInfo)
+        _check(lib().tcbf_plan_query(self._h, ctypes.byref(i)), "tcbf_plan_query")
+        return {"variant": i.variant, "tile_m": i.tile_m, "tile_n": i.tile_n, "tile_k": i.tile_k,
+                "threads": i.threads, "workgroups": i.workgroups, "useful_ops": i.useful_ops,
+                "algorithmic_bytes": i.algorithmic_bytes, "kernel_name": i.kernel_name.decode()}
+
+    # -- expected tensor shapes (element type, shape) ------------------------
+    def shape_a(self):
+        nb = 1 if self.a_shared else self.batch
+        if self.dtype == INT1:
+            return (nb, 2, self.M, (self.K + 31) // 32)
+        return (nb, 2, self.M, self.K) if self.a_layout == PLANAR else (nb, self.M, self.K, 2)
+
+    def shape_b(self):
+        if self.dtype == INT1:
+            return (self.batch, 2, self.N, (self.K + 31) // 32)
+        return (self.batch, 2, self.K, self.N) if self.b_layout == PLANAR else (self.batch, self.K, self.N, 2)
+
+    def shape_c(self):
+        return (self.batch, 2, self.M, self.N) if self.c_layout == PLANAR else (self.batch, self.M, self.N, 2)
+
+    def _dtypes(self):
+        import torch
+        if self.dtype == INT1:
+            return torch.int32, torch.int32, torch.int32  # packed words viewed as int32
+        return torch.float16, torch.float16, torch.float32
+
+    def empty_output(self):
+        import torch
+        return torch.empty(self.shape_c(), dtype=self._dtypes()[2], device="cuda:%d" % self.device)
+
+    def execute(self, A, B, C, stream=None):
+        """Enqueue C = A . B (W, X, output) on the current torch stream."""
+        import torch
+        ta, tb, tc = self._dtypes()
+        for t, dt, shp, nm in ((A, ta, self.shape_a(), "A"), (B, tb, self.shape_b(), "B"),
+                               (C, tc, self.shape_c(), "C")):
+            if t.dtype != dt and not (self.dtype == INT1 and t.dtype == torch.uint32 and nm != "C"):
+                raise ValueError("%s must be %s, got %s" % (nm, dt, t.dtype))
+            if tuple(t.shape) != tuple(shp):
+                raise ValueError("%s must have shape %s, got %s" % (nm, shp, tuple(t.shape)))
+        pa, pb, pc = _dev_ptr(A, "A"), _dev_ptr(B, "B"), _dev_ptr(C, "C")
+        _check(lib().tcbf_execute(self._h, pa, pb, pc, None, None, _stream_handle(stream)), "tcbf_execute")
+        return C
+
+
+def pack1bit(src, K=None, k_major=True, layout=PLANAR, out=None, stream=None):
+    """Sign-pack a device tensor (int8 / float16 / float32).
+
+    k_major=True : planar [batch, 2, rows, K] or interleaved [batch, rows, K, 2]
+    k_major=False: planar [batch, 2, K, rows] or interleaved [batch, K, rows, 2]
+    Returns (or fills) int32 words [batch, 2, rows, ceil(K/32)].
+    """
+    import torch
+    types = {torch.int8: SRC_I8, torch.float16: SRC_F16, torch.float32: SRC_F32}
+    if src.dtype not in types:
+        raise ValueError("unsupported source dtype %s" % src.dtype)
+    if src.dim() != 4:
+        raise ValueError("source must be 4-d")
+    if layout == PLANAR:
+        if src.shape[1] != 2:
+            raise ValueError("planar source needs a plane axis of 2")
+        batch = src.shape[0]
+        rows, kk = (src.shape[2], src.shape[3]) if k_major else (src.shape[3], src.shape[2])
+    else:
+        if src.shape[3] != 2:
+            raise ValueError("interleaved source needs a trailing axis of 2")
+        batch = src.shape[0]
+        rows, kk = (src.shape[1], src.shape[2]) if k_major else (src.shape[2], src.shape[1])
+    if K is not None and K != kk:
+        raise ValueError("K does not match the source")
+    kw = (kk + 31) // 32
+    if out is None:
+        out = torch.empty((batch, 2, rows, kw), dtype=torch.int32, device=src.device)
+    if tuple(out.shape) != (batch, 2, rows, kw) or out.dtype not in (torch.int32, torch.uint32):
+        raise ValueError("out must be int32 [batch, 2, rows, ceil(K/32)]")
+    _check(lib().tcbf_pack1bit(_dev_ptr(src, "src"), types[src.dtype], int(layout), int(batch), int(rows),
+                               int(kk), int(bool(k_major)), _dev_ptr(out, "out"), _stream_handle(stream)),
+           "tcbf_pack1bit")
+    return out

@@ -1,0 +1,137 @@
+// Sign packing for the 1-bit mode (Sec. III: 32 consecutive 1-bit samples per
+// 32-bit word; Sec. III-D / Fig. 1: bit 1 = +1, bit 0 = -1 per component).
+//
+// Sign rule: a value whose sign bit is clear becomes 1 (so integer 0 and +0.0
+// give +1, -0.0 gives -1).  For two's-complement int8 this is exactly x >= 0.
+// Destination: [batch][2][rows][kw] uint32, sample k in bit k % 32 of word
+// k / 32, bits past K zero.
+//
+// Both source orientations are memory-bound streaming kernels:
+//  * K-major (W-like, rows of K contiguous samples): one thread builds one
+//    word per plane from 32 consecutive samples of its row; consecutive
+//    threads take consecutive words, so the word stores are contiguous.
+//  * N-major (X-like, [K][rows] with rows contiguous): consecutive threads take
+//    consecutive rows so every sample row is read coalesced; each thread
+//    builds 4 consecutive words (128 samples along K) per plane and writes
+//    them as one 16-byte store.
+#include "tcbf_internal.h"
+
+namespace tcbf {
+namespace {
+
+template <typename T> struct Bits;
+template <> struct Bits<uint8_t> { static __device__ uint32_t pos(uint8_t v) { return (v >> 7) ^ 1u; } };
+template <> struct Bits<uint16_t> { static __device__ uint32_t pos(uint16_t v) { return (v >> 15) ^ 1u; } };
+template <> struct Bits<uint32_t> { static __device__ uint32_t pos(uint32_t v) { return (v >> 31) ^ 1u; } };
+
+constexpr int NT = 256;
+
+// K-major.  Thread -> (c, row, word); planar sources give plane stride rows*K,
+// interleaved sources hold (re, im) pairs.
+template <typename T, int IL>
+__global__ __launch_bounds__(NT) void pack_kmajor_kernel(const T *__restrict__ src, uint32_t *__restrict__ dst,
+                                                         int64_t batch, int64_t rows, int64_t K, int64_t kw) {
+    const int64_t gid = (int64_t)blockIdx.x * NT + threadIdx.x;
+    const int64_t total = batch * rows * kw;
+    if (gid >= total) return;
+    const int64_t w = gid % kw;
+    const int64_t r = (gid / kw) % rows;
+    const int64_t c = gid / (kw * rows);
+    const int64_t k0 = w * 32;
+    const int n = (int)((K - k0) < 32 ? (K - k0) : 32);
+    uint32_t wr = 0, wi = 0;
+    if (IL) {
+        const T *p = src + ((c * rows + r) * K + k0) * 2;
+        for (int e = 0; e < n; ++e) {
+            wr |= Bits<T>::pos(p[2 * e]) << e;
+            wi |= Bits<T>::pos(p[2 * e + 1]) << e;
+        }
+    } else {
+        const T *pr = src + ((c * 2 + 0) * rows + r) * K + k0;
+        const T *pi = src + ((c * 2 + 1) * rows + r) * K + k0;
+        for (int e = 0; e < n; ++e) {
+            wr |= Bits<T>::pos(pr[e]) << e;
+            wi |= Bits<T>::pos(pi[e]) << e;
+        }
+    }
+    dst[((c * 2 + 0) * rows + r) * kw + w] = wr;
+    dst[((c * 2 + 1) * rows + r) * kw + w] = wi;
+}
+
+// N-major.  Thread -> (c, word group of 4, row); rows fastest.
+template <typename T, int IL>
+__global__ __launch_bounds__(NT) void pack_nmajor_kernel(const T *__restrict__ src, uint32_t *__restrict__ dst,
+                                                         int64_t batch, int64_t rows, int64_t K, int64_t kw,
+                                                         int vec_store) {
+    const int64_t gid = (int64_t)blockIdx.x * NT + threadIdx.x;
+    const int64_t ngroups = (kw + 3) / 4;
+    const int64_t total = batch * ngroups * rows;
+    if (gid >= total) return;
+    const int64_t r = gid % rows;
+    const int64_t g = (gid / rows) % ngroups;
+    const int64_t c = gid / (rows * ngroups);
+    uint32_t wr[4] = {0u, 0u, 0u, 0u}, wi[4] = {0u, 0u, 0u, 0u};
+    const int64_t k0 = g * 128;
+    const int n = (int)((K - k0) < 128 ? (K - k0) : 128);
+    if (IL) {
+        const T *p = src + ((c * K + k0) * rows + r) * 2;
+        for (int e = 0; e < n; ++e) {
+            const T *q = p + (int64_t)e * rows * 2;
+            wr[e >> 5] |= Bits<T>::pos(q[0]) << (e & 31);
+            wi[e >> 5] |= Bits<T>::pos(q[1]) << (e & 31);
+        }
+    } else {
+        const T *pr = src + (c * 2 * K + k0) * rows + r;
+        const T *pi = pr + K * rows;
+        for (int e = 0; e < n; ++e) {
+            wr[e >> 5] |= Bits<T>::pos(pr[(int64_t)e * rows]) << (e & 31);
+            wi[e >> 5] |= Bits<T>::pos(pi[(int64_t)e * rows]) << (e & 31);
+        }
+    }
+    uint32_t *dr = dst + ((c * 2 + 0) * rows + r) * kw + g * 4;
+    uint32_t *di = dst + ((c * 2 + 1) * rows + r) * kw + g * 4;
+    if (vec_store && g * 4 + 4 <= kw) {
+        *reinterpret_cast<uint4 *>(dr) = make_uint4(wr[0], wr[1], wr[2], wr[3]);
+        *reinterpret_cast<uint4 *>(di) = make_uint4(wi[0], wi[1], wi[2], wi[3]);
+    } else {
+        for (int q = 0; q < 4 && g * 4 + q < kw; ++q) {
+            dr[q] = wr[q];
+            di[q] = wi[q];
+        }
+    }
+}
+
+template <typename T>
+hipError_t launch_typed(const void *src, int il, int64_t batch, int64_t rows, int64_t K, int kmajor,
+                        uint32_t *dst, hipStream_t stream) {
+    const int64_t kw = (K + 31) / 32;
+    const T *s = (const T *)src;
+    if (kmajor) {
+        const int64_t total = batch * rows * kw;
+        dim3 grid((uint32_t)((total + NT - 1) / NT));
+        if (il) hipLaunchKernelGGL((pack_kmajor_kernel<T, 1>), grid, dim3(NT), 0, stream, s, dst, batch, rows, K, kw);
+        else    hipLaunchKernelGGL((pack_kmajor_kernel<T, 0>), grid, dim3(NT), 0, stream, s, dst, batch, rows, K, kw);
+    } else {
+        const int64_t total = batch * ((kw + 3) / 4) * rows;
+        dim3 grid((uint32_t)((total + NT - 1) / NT));
+        const int vec = (kw % 4) == 0;
+        if (il) hipLaunchKernelGGL((pack_nmajor_kernel<T, 1>), grid, dim3(NT), 0, stream, s, dst, batch, rows, K, kw, vec);
+        else    hipLaunchKernelGGL((pack_nmajor_kernel<T, 0>), grid, dim3(NT), 0, stream, s, dst, batch, rows, K, kw, vec);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t pack1bit_launch(const void *src, int src_type, int src_layout, int64_t batch, int64_t rows,
+                           int64_t K, int src_k_major, uint32_t *dst, hipStream_t stream) {
+    const int il = src_layout == TCBF_INTERLEAVED;
+    switch (src_type) {
+    case TCBF_SRC_I8: return launch_typed<uint8_t>(src, il, batch, rows, K, src_k_major, dst, stream);
+    case TCBF_SRC_F16: return launch_typed<uint16_t>(src, il, batch, rows, K, src_k_major, dst, stream);
+    case TCBF_SRC_F32: return launch_typed<uint32_t>(src, il, batch, rows, K, src_k_major, dst, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace tcbf

@@ -1,0 +1,185 @@
+// C ABI of the beamforming library: plan creation (validation and kernel
+// choice, host only), execution (argument checks and one kernel launch), sign
+// packing.  No entry point throws, aborts or allocates device memory.
+#include <new>
+#include <stdio.h>
+#include <string.h>
+
+#include "tcbf_internal.h"
+
+struct tcbf_plan_s {
+    tcbf_plan_desc desc;
+    tcbf::Problem prob;
+    tcbf::F16Config f16;
+    tcbf::Int1Config int1;
+};
+
+namespace {
+
+constexpr uint32_t kDescV1 = (uint32_t)sizeof(tcbf_plan_desc);
+constexpr int64_t kMaxIndex = (int64_t)1 << 31;  // per-launch workgroup limit
+
+bool is_layout(int32_t v) { return v == TCBF_PLANAR || v == TCBF_INTERLEAVED; }
+bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+tcbf_status device_check(int device) {
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return TCBF_ERROR_DEVICE;
+    if (device < 0 || device >= count) return TCBF_ERROR_INVALID_VALUE;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return TCBF_ERROR_DEVICE;
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return TCBF_ERROR_NOT_SUPPORTED;
+    return TCBF_SUCCESS;
+}
+
+tcbf_status current_device_is(int device) {
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return TCBF_ERROR_DEVICE;
+    return cur == device ? TCBF_SUCCESS : TCBF_ERROR_INVALID_VALUE;
+}
+
+// Validate a descriptor without touching the HIP runtime.
+tcbf_status validate_desc(const tcbf_plan_desc *d) {
+    if (d->struct_size < kDescV1) return TCBF_ERROR_INVALID_VALUE;
+    if (d->batch < 1 || d->M < 1 || d->N < 1 || d->K < 1) return TCBF_ERROR_INVALID_VALUE;
+    if (!is_layout(d->a_layout) || !is_layout(d->b_layout) || !is_layout(d->c_layout))
+        return TCBF_ERROR_INVALID_VALUE;
+    if (d->variant < 0) return TCBF_ERROR_INVALID_VALUE;
+    if (d->dtype == TCBF_F16) {
+        // every per-channel plane must be indexable with 32-bit element counts
+        if (2 * d->M * d->K >= kMaxIndex || 2 * d->K * d->N >= kMaxIndex || 2 * d->M * d->N >= kMaxIndex)
+            return TCBF_ERROR_NOT_SUPPORTED;
+    } else if (d->dtype == TCBF_INT1) {
+        if (d->a_layout != TCBF_PLANAR || d->b_layout != TCBF_PLANAR) return TCBF_ERROR_INVALID_VALUE;
+        // int32 accumulators hold 4 * 2K: keep K well inside that range
+        if (d->K > ((int64_t)1 << 26)) return TCBF_ERROR_NOT_SUPPORTED;
+        if (2 * d->M * d->N >= kMaxIndex) return TCBF_ERROR_NOT_SUPPORTED;
+    } else {
+        return TCBF_ERROR_INVALID_VALUE;
+    }
+    return TCBF_SUCCESS;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *tcbf_status_string(tcbf_status s) {
+    switch (s) {
+    case TCBF_SUCCESS: return "TCBF_SUCCESS";
+    case TCBF_ERROR_INVALID_VALUE: return "TCBF_ERROR_INVALID_VALUE";
+    case TCBF_ERROR_NOT_SUPPORTED: return "TCBF_ERROR_NOT_SUPPORTED";
+    case TCBF_ERROR_OUT_OF_MEMORY: return "TCBF_ERROR_OUT_OF_MEMORY";
+    case TCBF_ERROR_DEVICE: return "TCBF_ERROR_DEVICE";
+    case TCBF_ERROR_INTERNAL: return "TCBF_ERROR_INTERNAL";
+    }
+    return "TCBF_UNKNOWN_STATUS";
+}
+
+int32_t tcbf_version(void) { return TCBF_VERSION; }
+
+tcbf_status tcbf_plan(const tcbf_plan_desc *desc, tcbf_plan_t *plan) {
+    if (desc == nullptr || plan == nullptr) return TCBF_ERROR_INVALID_VALUE;
+    *plan = nullptr;
+    tcbf_status st = validate_desc(desc);
+    if (st != TCBF_SUCCESS) return st;
+
+    tcbf::Problem p{desc->batch, desc->M, desc->N, desc->K,
+                    desc->a_layout, desc->b_layout, desc->c_layout, desc->a_shared != 0};
+    tcbf_plan_s tmp;
+    memset(&tmp, 0, sizeof(tmp));
+    memcpy(&tmp.desc, desc, kDescV1);
+    tmp.desc.struct_size = kDescV1;
+    tmp.prob = p;
+    int64_t wgs = 0;
+    if (desc->dtype == TCBF_F16) {
+        if (!tcbf::f16_select(p, desc->variant, &tmp.f16)) return TCBF_ERROR_INVALID_VALUE;
+        wgs = tcbf::f16_workgroups(p, tmp.f16);
+    } else {
+        if (!tcbf::int1_select(p, desc->variant, &tmp.int1)) return TCBF_ERROR_INVALID_VALUE;
+        wgs = tcbf::int1_workgroups(p, tmp.int1);
+    }
+    if (wgs >= kMaxIndex) return TCBF_ERROR_NOT_SUPPORTED;
+
+    st = device_check(desc->device);
+    if (st != TCBF_SUCCESS) return st;
+
+    tcbf_plan_s *out = new (std::nothrow) tcbf_plan_s(tmp);
+    if (out == nullptr) return TCBF_ERROR_OUT_OF_MEMORY;
+    *plan = out;
+    return TCBF_SUCCESS;
+}
+
+tcbf_status tcbf_plan_destroy(tcbf_plan_t plan) {
+    delete plan;
+    return TCBF_SUCCESS;
+}
+
+tcbf_status tcbf_plan_query(tcbf_plan_t plan, tcbf_plan_info *info) {
+    if (plan == nullptr || info == nullptr) return TCBF_ERROR_INVALID_VALUE;
+    if (info->struct_size < sizeof(tcbf_plan_info)) return TCBF_ERROR_INVALID_VALUE;
+    const tcbf::Problem &p = plan->prob;
+    tcbf_plan_info r;
+    memset(&r, 0, sizeof(r));
+    r.struct_size = sizeof(tcbf_plan_info);
+    const double cm = (double)p.batch * p.M * p.N * p.K;
+    r.useful_ops = 8.0 * cm;
+    const double nw = p.a_shared ? 1.0 : (double)p.batch;
+    if (plan->desc.dtype == TCBF_F16) {
+        r.variant = plan->f16.variant;
+        r.tile_m = plan->f16.tile_m;
+        r.tile_n = plan->f16.tile_n;
+        r.tile_k = plan->f16.tile_k;
+        r.threads = plan->f16.threads;
+        r.workgroups = tcbf::f16_workgroups(p, plan->f16);
+        r.algorithmic_bytes = 4.0 * nw * p.M * p.K + 4.0 * p.batch * p.K * p.N + 8.0 * p.batch * p.M * p.N;
+        snprintf(r.kernel_name, sizeof(r.kernel_name), "%s", tcbf::f16_kernel_name(plan->f16));
+    } else {
+        const double kw = (double)((p.K + 31) / 32);
+        r.variant = plan->int1.variant;
+        r.tile_m = plan->int1.tile_m;
+        r.tile_n = plan->int1.tile_n;
+        r.tile_k = plan->int1.tile_kw * 32;
+        r.threads = plan->int1.threads;
+        r.workgroups = tcbf::int1_workgroups(p, plan->int1);
+        r.algorithmic_bytes = 8.0 * nw * p.M * kw + 8.0 * p.batch * p.N * kw + 8.0 * p.batch * p.M * p.N;
+        snprintf(r.kernel_name, sizeof(r.kernel_name), "%s", tcbf::int1_kernel_name(plan->int1));
+    }
+    memcpy(info, &r, sizeof(r));
+    return TCBF_SUCCESS;
+}
+
+tcbf_status tcbf_execute(tcbf_plan_t plan, const void *A, const void *B, void *C, const float *a_scale,
+                         const float *b_scale, void *stream) {
+    if (plan == nullptr || A == nullptr || B == nullptr || C == nullptr) return TCBF_ERROR_INVALID_VALUE;
+    if (a_scale != nullptr || b_scale != nullptr) return TCBF_ERROR_INVALID_VALUE;
+    if (!aligned16(A) || !aligned16(B) || !aligned16(C)) return TCBF_ERROR_INVALID_VALUE;
+    tcbf_status st = current_device_is(plan->desc.device);
+    if (st != TCBF_SUCCESS) return st;
+    hipError_t e;
+    if (plan->desc.dtype == TCBF_F16) {
+        e = tcbf::f16_launch(plan->prob, plan->f16, A, B, C, (hipStream_t)stream);
+    } else {
+        e = tcbf::int1_launch(plan->prob, plan->int1, (const uint32_t *)A, (const uint32_t *)B, (int32_t *)C,
+                              (hipStream_t)stream);
+    }
+    return e == hipSuccess ? TCBF_SUCCESS : TCBF_ERROR_DEVICE;
+}
+
+tcbf_status tcbf_pack1bit(const void *src, int32_t src_type, int32_t src_layout, int64_t batch, int64_t rows,
+                          int64_t K, int32_t src_k_major, uint32_t *dst, void *stream) {
+    if (src == nullptr || dst == nullptr) return TCBF_ERROR_INVALID_VALUE;
+    if (src_type != TCBF_SRC_I8 && src_type != TCBF_SRC_F16 && src_type != TCBF_SRC_F32)
+        return TCBF_ERROR_INVALID_VALUE;
+    if (!is_layout(src_layout)) return TCBF_ERROR_INVALID_VALUE;
+    if (batch < 1 || rows < 1 || K < 1) return TCBF_ERROR_INVALID_VALUE;
+    if (!aligned16(src) || !aligned16(dst)) return TCBF_ERROR_INVALID_VALUE;
+    const int64_t kw = (K + 31) / 32;
+    const int64_t threads = src_k_major ? batch * rows * kw : batch * ((kw + 3) / 4) * rows;
+    if (threads / 256 + 1 >= kMaxIndex) return TCBF_ERROR_NOT_SUPPORTED;
+    hipError_t e = tcbf::pack1bit_launch(src, src_type, src_layout, batch, rows, K, src_k_major != 0, dst,
+                                         (hipStream_t)stream);
+    return e == hipSuccess ? TCBF_SUCCESS : TCBF_ERROR_DEVICE;
+}
+
+}  // extern "C"

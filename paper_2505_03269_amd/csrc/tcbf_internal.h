@@ -1,0 +1,56 @@
+// Internal declarations shared by the library's translation units (not part
+// of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tcbf.h"
+
+namespace tcbf {
+
+// Geometry a launcher needs; filled by the plan from the public descriptor.
+struct Problem {
+    int64_t batch, M, N, K;
+    int a_layout, b_layout, c_layout;  // tcbf_layout
+    int a_shared;
+};
+
+// FP16 mode (16-bit in, fp32 out).
+struct F16Config {
+    int variant;
+    int tile_m, tile_n, tile_k, threads;
+    bool a_vec, b_vec;  // 16-byte vector loads allowed for W / X rows
+};
+bool f16_select(const Problem &p, int forced_variant, F16Config *cfg);
+int64_t f16_workgroups(const Problem &p, const F16Config &cfg);
+const char *f16_kernel_name(const F16Config &cfg);
+hipError_t f16_launch(const Problem &p, const F16Config &cfg, const void *A, const void *B,
+                      void *C, hipStream_t stream);
+
+// 1-bit mode (packed sign bits in, int32 out).
+struct Int1Config {
+    int variant;  // 1 = int8 MFMA on unpacked bits, 2 = VALU xor/popcount
+    int tile_m, tile_n, tile_kw, threads;
+};
+bool int1_select(const Problem &p, int forced_variant, Int1Config *cfg);
+int64_t int1_workgroups(const Problem &p, const Int1Config &cfg);
+const char *int1_kernel_name(const Int1Config &cfg);
+hipError_t int1_launch(const Problem &p, const Int1Config &cfg, const uint32_t *A,
+                       const uint32_t *B, int32_t *C, hipStream_t stream);
+
+// Sign packing.
+hipError_t pack1bit_launch(const void *src, int src_type, int src_layout, int64_t batch,
+                           int64_t rows, int64_t K, int src_k_major, uint32_t *dst,
+                           hipStream_t stream);
+
+// Workgroup order: consecutive logical tiles land on the same XCD (each of the
+// 8 XCDs has its own L2).  Hardware hands workgroup ids to XCDs round-robin.
+__device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nblocks) {
+    constexpr int64_t kXcds = 8;
+    int64_t full = nblocks - nblocks % kXcds;
+    if (bid >= full) return bid;
+    return (bid % kXcds) * (full / kXcds) + bid / kXcds;
+}
+
+}  // namespace tcbf

@@ -1,0 +1,218 @@
+"""GPU parity of the FP16 mode against the FP64 oracle (through the C ABI).
+
+Gate: relative Frobenius error <= 2e-3 per channel plus the per-element fp32
+summation bound (see gpu_util).  Layout combinations must agree bitwise."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+from gpu_util import (c_inter_to_complex, c_planar_to_complex, check_fp_entries, check_fp_full, log,
+                      to_dev)
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_2505_03269_amd as tcbf  # noqa: E402
+
+
+def run_f16(W, X, a_layout=tcbf.PLANAR, b_layout=tcbf.PLANAR, c_layout=tcbf.PLANAR, shared=False, variant=0):
+    """W planar [nb,2,M,K], X planar [batch,2,K,N] (numpy fp16) -> complex128 [batch,M,N]."""
+    batch, _, K, N = X.shape
+    M = W.shape[2]
+    plan = tcbf.Plan(batch, M, N, K, tcbf.F16, a_layout, b_layout, c_layout, a_shared=shared, variant=variant)
+    Wd = W if a_layout == tcbf.PLANAR else np.ascontiguousarray(W.transpose(0, 2, 3, 1))
+    Xd = X if b_layout == tcbf.PLANAR else np.ascontiguousarray(X.transpose(0, 2, 3, 1))
+    A = to_dev(Wd)
+    B = to_dev(Xd)
+    C = plan.empty_output()
+    plan.execute(A, B, C)
+    torch.cuda.synchronize()
+    Ch = C.cpu().numpy()
+    return (c_planar_to_complex(Ch) if c_layout == tcbf.PLANAR else c_inter_to_complex(Ch)), Ch
+
+
+def oracle_ref(W, X, shared=False):
+    Wc = wl.planar_to_complex(W)
+    Xc = wl.planar_to_complex(X)
+    if shared:
+        Wc = Wc[0]
+    ref = oracle.cgemm(Wc, Xc)
+    absdot = np.matmul(np.abs(Wc), np.abs(Xc))
+    return ref, absdot
+
+
+def test_c1_full_output():
+    """Config 1 (4 channels, 128 x 64 x 512), every output entry."""
+    chans = [wl.c1_channel(c) for c in range(4)]
+    W = np.stack([w for w, _ in chans])
+    X = np.stack([x for _, x in chans])
+    log("c1: batch=4 M=128 N=512 K=64")
+    got, _ = run_f16(W, X)
+    ref, absdot = oracle_ref(W, X)
+    check_fp_full(got, ref, absdot, 64)
+
+
+EDGE_SHAPES = [
+    (1, 1, 1, 1), (1, 15, 17, 31), (2, 17, 15, 33), (1, 33, 129, 63), (3, 129, 33, 65),
+    (1, 16, 16, 16), (1, 32, 32, 32), (2, 31, 1, 64), (1, 1, 31, 8), (1, 128, 128, 32),
+    (1, 127, 256, 575), (1, 257, 130, 577), (2, 200, 64, 96), (1, 1000, 40, 24), (1, 64, 1000, 7),
+]
+
+
+@pytest.mark.parametrize("batch,M,N,K", EDGE_SHAPES)
+def test_edge_shapes(batch, M, N, K):
+    log("edge: batch=%d M=%d N=%d K=%d" % (batch, M, N, K))
+    W, X = wl.random_f16_case(7, batch, M, N, K)
+    got, _ = run_f16(W, X)
+    ref, absdot = oracle_ref(W, X)
+    check_fp_full(got, ref, absdot, K)
+
+
+@pytest.mark.parametrize("batch,M,N,K", [(2, 70, 90, 45), (2, 128, 256, 64), (1, 33, 20, 12)])
+def test_layouts_bitwise_identical(batch, M, N, K):
+    W, X = wl.random_f16_case(11, batch, M, N, K)
+    ref, absdot = oracle_ref(W, X)
+    base, _ = run_f16(W, X)
+    check_fp_full(base, ref, absdot, K)
+    for al in (0, 1):
+        for bl in (0, 1):
+            for cl in (0, 1):
+                log("layouts a=%d b=%d c=%d shape=%s" % (al, bl, cl, (batch, M, N, K)))
+                got, _ = run_f16(W, X, al, bl, cl)
+                assert np.array_equal(got, base), "layout (%d,%d,%d) differs from planar" % (al, bl, cl)
+
+
+def test_batch_independence_and_determinism():
+    W, X = wl.random_f16_case(3, 3, 150, 140, 100)
+    full, _ = run_f16(W, X)
+    again, _ = run_f16(W, X)
+    assert np.array_equal(full, again)
+    alone, _ = run_f16(W[1:2], X[1:2])
+    assert np.array_equal(alone[0], full[1])
+
+
+def test_shared_weights():
+    W, X = wl.random_f16_case(4, 3, 96, 80, 40, shared_w=True)
+    got, _ = run_f16(W, X, shared=True)
+    ref, absdot = oracle_ref(W, X, shared=True)
+    check_fp_full(got, ref, absdot, 40)
+
+
+def test_plane_wave_exact():
+    """Quarter-turn steering phases: the beam on the source sums coherently to
+    exactly K * a; the GPU result must be exact."""
+    K, N, M = 576, 256, 64
+    g = np.random.default_rng(1)
+    q = g.integers(0, 4, K)
+    a = 3.0
+    s = (1j) ** g.integers(0, 4, N)
+    Xc = a * np.outer((1j) ** (-q), s)
+    Wc = np.exp(1j * g.uniform(0, 2 * np.pi, (M, K)))
+    Wc[5] = (1j) ** q
+    W = np.stack([Wc.real, Wc.imag]).astype(np.float16)[None]
+    X = np.stack([Xc.real, Xc.imag]).astype(np.float16)[None]
+    got, _ = run_f16(W, X)
+    np.testing.assert_array_equal(np.abs(got[0, 5]), np.full(N, K * a))
+
+
+def test_orthogonal_phasors():
+    for K in (4, 64):
+        k = np.arange(K)
+        Wc = np.exp(-2j * np.pi * np.outer(k, k) / K)
+        Xc = np.exp(2j * np.pi * np.outer(k, k) / K)
+        if K == 4:
+            Wc = (1j) ** (-(np.outer(k, k) % 4))
+            Xc = (1j) ** (np.outer(k, k) % 4)
+        W = np.stack([Wc.real, Wc.imag]).astype(np.float16)[None]
+        X = np.stack([Xc.real, Xc.imag]).astype(np.float16)[None]
+        got, _ = run_f16(W, X)
+        if K == 4:
+            np.testing.assert_array_equal(got[0], 4 * np.eye(4))
+        else:
+            ref, absdot = oracle_ref(W, X)
+            check_fp_full(got, ref, absdot, K)
+            off = got[0] - np.diag(np.diag(got[0]))
+            assert np.max(np.abs(off)) < 0.05 * K  # fp16-rounded phasors: leakage far below the beam
+
+
+def _sample_indices(g, batch, M, N, count, tile=128):
+    cs = g.integers(0, batch, count)
+    ms = g.integers(0, M, count)
+    ns = g.integers(0, N, count)
+    # tile boundaries and corners, in every channel
+    edge_m = np.unique(np.clip([0, tile - 1, tile, M // 2, M - tile, M - 1], 0, M - 1))
+    edge_n = np.unique(np.clip([0, tile - 1, tile, N // 2, N - tile, N - 1], 0, N - 1))
+    ec, em, en = np.meshgrid(np.arange(batch), edge_m, edge_n, indexing="ij")
+    return (np.concatenate([cs, ec.ravel()]), np.concatenate([ms, em.ravel()]),
+            np.concatenate([ns, en.ravel()]))
+
+
+def _sampled_parity(W, X, C, K, shared=False, count=20000):
+    batch, _, M, N = C.shape
+    g = np.random.default_rng(123)
+    cs, ms, ns = _sample_indices(g, batch, M, N, count)
+    idx = [torch.from_numpy(v).to("cuda:0") for v in (cs, ms, ns)]
+    gr = C[idx[0], 0, idx[1], idx[2]].cpu().numpy().astype(np.float64)
+    gi = C[idx[0], 1, idx[1], idx[2]].cpu().numpy().astype(np.float64)
+    got = gr + 1j * gi
+    ref = np.empty(cs.size, complex)
+    absdot = np.empty(cs.size)
+    for c in np.unique(cs):
+        sel = np.nonzero(cs == c)[0]
+        Wc = wl.planar_to_complex(W[0 if shared else c])[None]
+        Xc = wl.planar_to_complex(X[c])[None]
+        z = np.zeros(sel.size, np.int64)
+        ref[sel] = oracle.cgemm_entries(Wc, Xc, z, ms[sel], ns[sel])
+        absdot[sel] = oracle.abs_dot_entries(Wc, Xc, z, ms[sel], ns[sel])
+    check_fp_entries(got, ref, absdot, K)
+    return got, ref
+
+
+def test_c2_full_size_sampled():
+    """Config 2 at its full size (256 x 1024 x 576 x 4096), the plan the
+    benchmark times; 20k random entries plus tile edges of every channel."""
+    cfg = wl.CONFIGS[2]
+    log("c2 full size: generating inputs")
+    W, X = wl.generate_c2()
+    plan = tcbf.Plan(cfg["batch"], cfg["M"], cfg["N"], cfg["K"], tcbf.F16)
+    A, B = to_dev(W), to_dev(X)
+    C = plan.empty_output()
+    log("c2 full size: execute")
+    plan.execute(A, B, C)
+    torch.cuda.synchronize()
+    del A, B
+    got, ref = _sampled_parity(W, X, C, cfg["K"])
+    log("c2 sampled rel Frobenius %.3e" % (np.linalg.norm(got - ref) / np.linalg.norm(ref)))
+
+
+def test_c4_full_size_sampled():
+    """Config 4 (1 x 32768 x 8192 x 256), fp16."""
+    cfg = wl.CONFIGS[4]
+    log("c4 full size: generating inputs")
+    W, X = wl.c4_channel(0)
+    W, X = W[None], X[None]
+    plan = tcbf.Plan(1, cfg["M"], cfg["N"], cfg["K"], tcbf.F16)
+    A, B = to_dev(W), to_dev(X)
+    C = plan.empty_output()
+    log("c4 full size: execute")
+    plan.execute(A, B, C)
+    torch.cuda.synchronize()
+    del A, B
+    got, ref = _sampled_parity(W, X, C, cfg["K"], count=5000)
+    log("c4 sampled rel Frobenius %.3e" % (np.linalg.norm(got - ref) / np.linalg.norm(ref)))
+
+
+def test_rejects_bad_tensors():
+    plan = tcbf.Plan(1, 32, 32, 32, tcbf.F16)
+    A = torch.zeros(plan.shape_a(), dtype=torch.float16, device="cuda:0")
+    B = torch.zeros(plan.shape_b(), dtype=torch.float16, device="cuda:0")
+    C = plan.empty_output()
+    with pytest.raises(ValueError):
+        plan.execute(A.float(), B, C)
+    with pytest.raises(ValueError):
+        plan.execute(A[..., :16], B, C)
+    # misaligned pointer: rejected by the library itself
+    flat = torch.zeros(A.numel() + 8, dtype=torch.float16, device="cuda:0")
+    st = tcbf.lib().tcbf_execute(plan._h, flat.data_ptr() + 2, B.data_ptr(), C.data_ptr(), None, None, None)
+    assert st == 1

@@ -157,3 +157,39 @@ def planar_to_complex(P):
     """[..., 2, r, c] planar (any float dtype) -> complex128 [..., r, c]."""
     P = np.asarray(P)
     return P[..., 0, :, :].astype(np.float64) + 1j * P[..., 1, :, :].astype(np.float64)
+
+
+# ---- whole configurations ------------------------------------------------------
+
+def _parallel(fn, n, threads):
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(fn, range(n)))
+
+
+def generate_c2(batch=256, threads=8):
+    """Config 2 inputs: W [batch, 2, 1024, 576], X [batch, 2, 576, 4096] fp16."""
+    cfg = CONFIGS[2]
+    M, K, N = cfg["M"], cfg["K"], cfg["N"]
+    geo = c2_geometry(K, M)
+    W = np.empty((batch, 2, M, K), np.float16)
+    X = np.empty((batch, 2, K, N), np.float16)
+
+    def one(c):
+        W[c], X[c] = c2_channel(c, geo, M, K, N)
+    _parallel(one, batch, threads)
+    return W, X
+
+
+def generate_c3(batch=64, threads=8):
+    """Config 3 inputs: packed W [batch, 2, 2048, 256], X [batch, 2, 8192, 256]."""
+    cfg = CONFIGS[3]
+    M, K, N = cfg["M"], cfg["K"], cfg["N"]
+    kw = (K + 31) // 32
+    W = np.empty((batch, 2, M, kw), np.uint32)
+    X = np.empty((batch, 2, N, kw), np.uint32)
+
+    def one(c):
+        W[c], X[c] = c3_channel(c, M, K, N)
+    _parallel(one, batch, threads)
+    return W, X
