@@ -1,42 +1,110 @@
 // FP16 batched complex product B[c] = W[c] . X[c] on gfx950 MFMA.
 //
-// Complex product as four real products with the imaginary part of X negated
-// in registers (Sec. III-B): Re += Wr.Xr + Wi.(-Xi), Im += Wr.Xi + Wi.Xr,
-// fp16 x fp16 products accumulated in fp32 by v_mfma_f32_32x32x16_f16.
+// Complex product as four real products with one imaginary part negated in
+// registers (Sec. III-B): Re += Wr.Xr + (-Wi).Xi, Im += Wr.Xi + Wi.Xr, fp16 x
+// fp16 products accumulated in fp32 by v_mfma_f32_32x32x16_f16.
 //
-// Design (one workgroup = 256 threads = 4 waves, 128 x 128 complex outputs):
-//  * per K stage (32 receivers) the workgroup loads the W tile (both planes,
-//    128 x 32) and the X tile (both planes, 32 x 128) once into LDS; the four
-//    real products of every wave read from that single copy (Sec. III-C data
-//    reuse, at the LDS level).
-//  * X arrives N-contiguous; MFMA wants 8 consecutive k per lane for both
-//    operands, so the X tile is transposed to [n][k] while it is written to
-//    LDS.  Interleaved (re, im) inputs are split into planes at the same
-//    point, so every layout feeds the identical MFMA sequence and gives
-//    bitwise-identical results.
-//  * LDS holds two stages (2 x 32 KiB): global loads for stage k+1 are in
-//    flight while stage k is multiplied; one barrier per stage.  Rows are
-//    grouped in 128-byte lines with an XOR swizzle of the 16-byte chunks so
-//    that neither the transposing writes nor the MFMA operand reads conflict.
-//  * each wave owns a 64 x 64 complex sub-tile: 2 x 2 MFMA tiles of 32 x 32,
-//    each with a real and an imaginary fp32 accumulator (128 registers).
-//  * two workgroups per CU (64 KiB LDS, <= 256 VGPRs each) so one can drain
-//    its fp32 stores while the other multiplies.
-//  * workgroup ids are remapped so consecutive tiles stay on one XCD's L2.
+// Tiling (both kernels): a workgroup of 256 threads (4 waves) owns 128 x 128
+// complex outputs; each wave owns 64 x 64 = 2 x 2 MFMA tiles of 32 x 32, with a
+// real and an imaginary fp32 accumulator each (128 registers).  Per K stage
+// the workgroup brings the W tile (both planes) and the X tile (both planes)
+// into LDS once, and all four real products of every wave read that single
+// copy (Sec. III-C data reuse).  In the accumulators, lanes 0..31 of a wave
+// hold 32 consecutive samples of one beam, so every output store instruction
+// writes whole 128-byte row segments.  Two workgroups fit on a CU (64 KiB LDS,
+// <= 256 VGPRs), so one drains its stores while the other multiplies.
+// Workgroup ids are remapped so consecutive tiles of a channel stay on one
+// XCD's L2.
+//
+// Two kernels share the exact same MFMA sequence (same 16-receiver steps in
+// increasing order, same k assignment per lane, same operand order and
+// accumulation order), so they produce bitwise-identical results:
+//  * cgemm_f16_fast_kernel: planar W and X, K and N multiples of 8.  Global
+//    tiles go straight into LDS with buffer_load ... lds (no registers, no
+//    ALU work per stage) through a ring of NS stage buffers; out-of-range rows,
+//    columns and the K tail read as zero through the buffer descriptor's range
+//    check.  X stays N-contiguous in LDS and its MFMA fragments are read with
+//    ds_read_b64_tr_b16, which transposes 4 x 16 blocks of 16-bit values
+//    across each 16-lane group.  Stores use scalar row offsets, so the
+//    epilogue spends no vector ALU work on addresses.
+//  * cgemm_f16_kernel: any layout and alignment.  Tiles go through registers,
+//    interleaved (re, im) data is split into planes and X is transposed while
+//    being written to LDS.
 #include "tcbf_internal.h"
 
 namespace tcbf {
 namespace {
 
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
+typedef short short4v __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+#define LDS_AS __attribute__((address_space(3)))
 
 constexpr int BM = 128, BN = 128, BK = 32, NT = 256;
 constexpr int PLANE_A = BM * BK;          // halves per W plane in a stage
 constexpr int PLANE_B = BN * BK;          // halves per X plane in a stage
 constexpr int STAGE = 2 * PLANE_A + 2 * PLANE_B;  // 16384 halves = 32 KiB
+constexpr uint32_t OOB = 0x80000000u;     // buffer offset past every range: reads 0, writes dropped
+constexpr int RSRC_FLAGS = 0x00020000;    // raw buffer, 32-bit data format (gfx9 family)
+
+__device__ __forceinline__ half8 negate(half8 v) {
+    u32x4 u = __builtin_bit_cast(u32x4, v);
+    u ^= 0x80008000u;  // flip both fp16 sign bits: exact negation
+    return __builtin_bit_cast(half8, u);
+}
+
+// Accumulators of one wave: [i: 32-beam sub-tile][j: 32-sample sub-tile].
+// Element r of lane l holds beam i*32 + l%32 and samples
+// j*32 + 8*(r/4) + 4*(l/32) + r%4: each lane owns runs of four consecutive
+// samples of one beam.
+struct Acc {
+    f32x16 re[2][2], im[2][2];
+    __device__ void zero() {
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                re[i][j] = (f32x16){};
+                im[i][j] = (f32x16){};
+            }
+    }
+};
+
+// One 16-receiver step.  w*: W fragments (lane l: beam l%32, receivers
+// 8*(l/32) + 0..7); x*: X fragments (lane l: sample l%32, same receivers).
+// X is the matrix unit's first operand, so the result comes out transposed
+// (samples along the accumulator's row index).
+__device__ __forceinline__ void mma_step(Acc &a, const half8 (&wr)[2], const half8 (&wi)[2],
+                                         const half8 (&xr)[2], const half8 (&xi)[2]) {
+    half8 wn[2] = {negate(wi[0]), negate(wi[1])};
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            a.re[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(xr[j], wr[i], a.re[i][j], 0, 0, 0);
+            a.im[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(xi[j], wr[i], a.im[i][j], 0, 0, 0);
+            a.re[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(xi[j], wn[i], a.re[i][j], 0, 0, 0);
+            a.im[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(xr[j], wi[i], a.im[i][j], 0, 0, 0);
+        }
+}
+
+// Four consecutive accumulator elements 4q..4q+3 (a sub-register view).
+__device__ __forceinline__ f32x4 quad(const f32x16 &v, int q) {
+    switch (q) {
+    case 0: return __builtin_shufflevector(v, v, 0, 1, 2, 3);
+    case 1: return __builtin_shufflevector(v, v, 4, 5, 6, 7);
+    case 2: return __builtin_shufflevector(v, v, 8, 9, 10, 11);
+    default: return __builtin_shufflevector(v, v, 12, 13, 14, 15);
+    }
+}
+
+// ===========================================================================
+// Generic kernel: register-staged loads (any layout, any alignment).
+// ===========================================================================
 
 // Offset in halves of 16-byte chunk `ch` (0..3, i.e. k = 8ch..8ch+7) of row
 // `row` inside a [rows][32] fp16 plane.  Two rows share a 128-byte line whose
@@ -236,10 +304,37 @@ __device__ __forceinline__ half8 lds_frag(const uint16_t *plane, int row, int ch
     return *reinterpret_cast<const half8 *>(plane + lds_off(row, ch));
 }
 
-__device__ __forceinline__ half8 negate(half8 v) {
-    u32x4 u = __builtin_bit_cast(u32x4, v);
-    u ^= 0x80008000u;  // flip both fp16 sign bits: exact negation
-    return __builtin_bit_cast(half8, u);
+// Store one lane's four consecutive samples (re[4], im[4]) of beam m starting
+// at sample n, masked to the problem.
+template <int CIL>
+__device__ __forceinline__ void store4(float *C, int64_t c, int64_t M, int64_t N, int64_t m, int64_t n,
+                                       const f32x4 &re, const f32x4 &im) {
+    if (m >= M || n >= N) return;
+    const bool whole = n + 4 <= N;
+    if (CIL) {
+        float *o = C + ((c * M + m) * N + n) * 2;
+        if (whole && (((uintptr_t)o & 15) == 0)) {
+            *reinterpret_cast<f32x4 *>(o) = (f32x4){re[0], im[0], re[1], im[1]};
+            *reinterpret_cast<f32x4 *>(o + 4) = (f32x4){re[2], im[2], re[3], im[3]};
+        } else {
+            for (int e = 0; e < 4 && n + e < N; ++e) {
+                o[2 * e] = re[e];
+                o[2 * e + 1] = im[e];
+            }
+        }
+    } else {
+        float *o = C + (c * 2 * M + m) * N + n;
+        float *oi = o + M * N;
+        if (whole && (((uintptr_t)o & 15) == 0) && (((uintptr_t)oi & 15) == 0)) {
+            *reinterpret_cast<f32x4 *>(o) = re;
+            *reinterpret_cast<f32x4 *>(oi) = im;
+        } else {
+            for (int e = 0; e < 4 && n + e < N; ++e) {
+                o[e] = re[e];
+                oi[e] = im[e];
+            }
+        }
+    }
 }
 
 template <int AIL, int BIL, int CIL>
@@ -269,14 +364,8 @@ __global__ __launch_bounds__(NT, 2) void cgemm_f16_kernel(
     const int wm = wave >> 1, wn = wave & 1;
     const int hl = lane >> 5, l32 = lane & 31;
 
-    f32x16 acc_r[2][2], acc_i[2][2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            acc_r[i][j] = (f32x16){};
-            acc_i[i][j] = (f32x16){};
-        }
+    Acc acc;
+    acc.zero();
 
     const int nk = (int)((K + BK - 1) / BK);
     u32x4 ra[4], rb[4];
@@ -296,29 +385,20 @@ __global__ __launch_bounds__(NT, 2) void cgemm_f16_kernel(
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
             const int ch = 2 * s + hl;
-            half8 ar[2], ai[2], br[2], bi[2], bn[2];
+            half8 wr[2], wi[2], xr[2], xi[2];
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
                 int row = wm * 64 + i * 32 + l32;
-                ar[i] = lds_frag(st, row, ch);
-                ai[i] = lds_frag(st + PLANE_A, row, ch);
+                wr[i] = lds_frag(st, row, ch);
+                wi[i] = lds_frag(st + PLANE_A, row, ch);
             }
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
                 int col = wn * 64 + j * 32 + l32;
-                br[j] = lds_frag(st + 2 * PLANE_A, col, ch);
-                bi[j] = lds_frag(st + 2 * PLANE_A + PLANE_B, col, ch);
-                bn[j] = negate(bi[j]);
+                xr[j] = lds_frag(st + 2 * PLANE_A, col, ch);
+                xi[j] = lds_frag(st + 2 * PLANE_A + PLANE_B, col, ch);
             }
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-                for (int j = 0; j < 2; ++j) {
-                    acc_r[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ar[i], br[j], acc_r[i][j], 0, 0, 0);
-                    acc_i[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ar[i], bi[j], acc_i[i][j], 0, 0, 0);
-                    acc_r[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ai[i], bn[j], acc_r[i][j], 0, 0, 0);
-                    acc_i[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(ai[i], br[j], acc_i[i][j], 0, 0, 0);
-                }
+            mma_step(acc, wr, wi, xr, xi);
         }
         if (more) {
             uint16_t *nx = lds + ((kt + 1) & 1) * STAGE;
@@ -328,33 +408,285 @@ __global__ __launch_bounds__(NT, 2) void cgemm_f16_kernel(
         __syncthreads();
     }
 
-    // Epilogue: 32x32 accumulator element r of lane l sits at
-    // row 8*(r/4) + 4*(l/32) + r%4, column l%32.
-    const bool full = (m0 + BM <= M) && (n0 + BN <= N);
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int64_t col = n0 + wn * 64 + j * 32 + l32;
+        for (int j = 0; j < 2; ++j)
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int64_t row = m0 + wm * 64 + i * 32 + (r >> 2) * 8 + hl * 4 + (r & 3);
-                if (full || (row < M && col < N)) {
-                    if (CIL) {
-                        float2 v = make_float2(acc_r[i][j][r], acc_i[i][j][r]);
-                        *reinterpret_cast<float2 *>(C + ((c * M + row) * N + col) * 2) = v;
-                    } else {
-                        float *o = C + c * 2 * M * N + row * N + col;
-                        o[0] = acc_r[i][j][r];
-                        o[M * N] = acc_i[i][j][r];
+            for (int q = 0; q < 4; ++q) {
+                const int64_t m = m0 + wm * 64 + i * 32 + l32;
+                const int64_t n = n0 + wn * 64 + j * 32 + 8 * q + 4 * hl;
+                store4<CIL>(C, c, M, N, m, n, quad(acc.re[i][j], q), quad(acc.im[i][j], q));
+            }
+}
+
+// ===========================================================================
+// Fast kernel: direct-to-LDS loads, transposing LDS reads, NS-deep ring.
+// ===========================================================================
+//
+// LDS stage (bytes), for a stage of BK receivers:
+//   W region [2 planes][128 beams][BK] fp16: rows of BK*2 bytes split in
+//     16-byte chunks; chunk ch of beam m sits at ch ^ swzW(m);
+//   X region [2 planes][BK][128 samples] fp16: rows of 256 bytes (16 chunks);
+//     chunk ch of row k sits at ch ^ swzX(k).
+// The swizzles keep the MFMA operand reads free of bank conflicts for 8- and
+// 16-lane access phases.
+template <int BK> struct FastGeo {
+    static constexpr int WCH = BK / 8;                 // chunks per W row
+    static constexpr int WREG = 2 * BM * BK * 2;       // W region bytes
+    static constexpr int XREG = 2 * BK * BN * 2;       // X region bytes
+    static constexpr int STAGE = WREG + XREG;          // stage bytes
+    static constexpr int LOADS = (WREG + XREG) / (NT * 16);  // 16-byte loads per thread per stage
+    // both use only beam bits 1..3, so beams 16 apart share a swizzle
+    __device__ static int swzW(int m) {
+        return BK == 32 ? (((m >> 1) ^ ((m >> 3) & 1)) & 3) : (((m >> 2) ^ (m >> 3)) & 1);
+    }
+    __device__ static int swzX(int k) { return 2 * (k & 3); }
+};
+
+__device__ __forceinline__ half8 tr_frag(const char *lds_bytes, int off0, int off1) {
+    short4v lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((LDS_AS short4v *)(lds_bytes + off0));
+    short4v hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((LDS_AS short4v *)(lds_bytes + off1));
+    typedef short short8v __attribute__((ext_vector_type(8)));
+    short8v v = (short8v){lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+    return __builtin_bit_cast(half8, v);
+}
+
+// s_waitcnt with only vmcnt constrained (gfx9 encoding: vmcnt low bits [3:0],
+// high bits [15:14]; expcnt and lgkmcnt left at their maxima).
+constexpr int vmcnt_imm(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4) | (15 << 8); }
+
+template <int BK, int NS, int CIL>
+__global__ __launch_bounds__(NT, 2) void cgemm_f16_fast_kernel(
+    const uint16_t *__restrict__ A, const uint16_t *__restrict__ B, float *__restrict__ C,
+    int M, int N, int K, int a_shared, int tiles_m, int tiles_n, int nblocks) {
+    typedef FastGeo<BK> G;
+    static_assert(NS >= 2 && NS <= 5, "ring depth");
+    static_assert(G::WREG % (64 * 16) == 0 && G::XREG % (64 * 16) == 0, "whole wave loads");
+    // every stage buffer is its own object, so the compiler can tell the
+    // direct-to-LDS writes into one from the fragment reads of another
+    __shared__ __attribute__((aligned(1024))) char lds0[G::STAGE];
+    __shared__ __attribute__((aligned(1024))) char lds1[G::STAGE];
+    __shared__ __attribute__((aligned(NS > 2 ? 1024 : 4))) char lds2[NS > 2 ? G::STAGE : 4];
+    __shared__ __attribute__((aligned(NS > 3 ? 1024 : 4))) char lds3[NS > 3 ? G::STAGE : 4];
+    __shared__ __attribute__((aligned(NS > 4 ? 1024 : 4))) char lds4[NS > 4 ? G::STAGE : 4];
+    char *const bufs[5] = {lds0, lds1, lds2, lds3, lds4};
+
+    const int tid = threadIdx.x;
+    const int t = (int)xcd_remap(blockIdx.x, nblocks);
+    const int per_c = tiles_m * tiles_n;
+    const int c = t / per_c;
+    const int rem = t - c * per_c;
+    const int tn = rem / tiles_m, tm = rem - tn * tiles_m;
+    const int m0 = tm * BM, n0 = tn * BN;
+
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int hl = lane >> 5, l32 = lane & 31;
+
+    const uint16_t *Wc = A + (a_shared ? (int64_t)0 : (int64_t)c * 2 * M * K);
+    const uint16_t *Xc = B + (int64_t)c * 2 * K * N;
+    const __amdgpu_buffer_rsrc_t rw = __builtin_amdgcn_make_buffer_rsrc((void *)Wc, 0, 4 * M * K, RSRC_FLAGS);
+    const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc((void *)Xc, 0, 4 * K * N, RSRC_FLAGS);
+
+    // The 16-byte chunks this lane moves into LDS per stage.  A wave load
+    // writes 1 KiB in lane order, so LDS slot s (16 B) = piece*64 + lane with
+    // the workgroup's pieces dealt to waves in consecutive runs.  Within a wave
+    // the pieces differ only by whole rows (same plane, same swizzle), so one
+    // per-lane offset plus a uniform row stride per piece addresses them all.
+    constexpr int WPIECES = G::WREG / 1024, XPIECES = G::XREG / 1024;
+    constexpr int WPW = WPIECES / 4, XPW = XPIECES / 4;  // pieces per wave
+    constexpr int WROWS = 64 / G::WCH, XROWS = 64 / 16;  // rows per piece
+    uint32_t va, vb;   // byte offsets of piece 0
+    int ka, kb, am;    // receiver offset of the W chunk, X row of piece 0, W beam of piece 0
+    {
+        const int s = wave * WPW * 64 + lane;
+        const int p = s / (BM * G::WCH), m = (s / G::WCH) % BM;
+        const int ch = (s % G::WCH) ^ G::swzW(m);
+        ka = ch * 8;
+        am = m;
+        va = (uint32_t)(((p * M + m0 + m) * K + ch * 8) * 2);
+    }
+    {
+        const int s = wave * XPW * 64 + lane;
+        const int p = s / (BK * 16), k = (s / 16) % BK, ch = (s & 15) ^ G::swzX(k);
+        kb = k;
+        vb = (n0 + ch * 8 < N) ? (uint32_t)(((p * K + k) * N + n0 + ch * 8) * 2) : OOB;
+    }
+    const bool rows_full = m0 + BM <= M;
+
+    // LDS byte offsets of this lane's MFMA fragments in a stage (plane 0):
+    // W fragment for 16-receiver step s: beam wm*64 + l32, chunk 2s + hl;
+    // X fragment for sample sub-tile j: this lane supplies row 8*(g/2) + (l%16)/4
+    // and samples wn*64 + 32j + 16*(g%2) + 4*(l%4), g = l/16 (the transposing
+    // read then hands lane l the 4 receivers of sample l%16 of its group).
+    constexpr int KS = BK / 16;  // 16-receiver steps per stage
+    int ow[2], ox[2];
+    static_assert(KS <= 2, "steps per stage");
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+        const int m = wm * 64 + l32;
+        ow[s] = m * (BK * 2) + (((2 * s + hl) ^ G::swzW(m)) * 16);
+    }
+    {
+        const int g = lane >> 4, j16 = lane & 15;
+        const int krow = 8 * (g >> 1) + (j16 >> 2);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int ns = wn * 64 + 32 * j + 16 * (g & 1) + 4 * (j16 & 3);
+            ox[j] = G::WREG + krow * 256 + (((ns >> 3) ^ G::swzX(krow)) * 16) + (ns & 7) * 2;
+        }
+    }
+
+    auto issue = [&](char *base, int k0) {
+        const bool tail = k0 + BK > K;
+#pragma unroll
+        for (int q = 0; q < WPW; ++q) {
+            uint32_t off = va;
+            if (!rows_full && m0 + am + q * WROWS >= M) off = OOB;  // beams past M
+            if (tail && k0 + ka >= K) off = OOB;                    // receivers past K
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rw, (LDS_AS void *)(base + (wave * WPW + q) * 1024), 16,
+                                                     off, k0 * 2 + q * WROWS * K * 2, 0, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < XPW; ++q) {
+            uint32_t off = vb;
+            if (tail && k0 + kb + q * XROWS >= K) off = OOB;        // rows past K
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rx, (LDS_AS void *)(base + G::WREG + (wave * XPW + q) * 1024),
+                                                     16, off, (k0 + q * XROWS) * N * 2, 0, 0);
+        }
+    };
+
+    Acc acc;
+    acc.zero();
+    auto compute = [&](const char *st) {
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            half8 wr[2], wi[2], xr[2], xi[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                wr[i] = *reinterpret_cast<const half8 *>(st + ow[s] + i * 32 * BK * 2);
+                wi[i] = *reinterpret_cast<const half8 *>(st + ow[s] + i * 32 * BK * 2 + BM * BK * 2);
+            }
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int o = ox[j] + s * 16 * 256;
+                xr[j] = tr_frag(st, o, o + 4 * 256);
+                xi[j] = tr_frag(st, o + BK * BN * 2, o + BK * BN * 2 + 4 * 256);
+            }
+            mma_step(acc, wr, wi, xr, xi);
+            // keep one step's fragments live at a time (two workgroups per CU
+            // leave 256 registers per lane)
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    };
+
+    // Ring: stage kt lives in buffer kt % NS; NS-1 stages are in flight.
+    constexpr int PER_STAGE = WPW + XPW;  // loads per wave per stage
+    static_assert((NS - 2) * PER_STAGE < 64, "vmcnt range");
+    constexpr int kWaitRing = vmcnt_imm((NS - 2) * PER_STAGE), kWaitAll = vmcnt_imm(0);
+    const int nk = (K + BK - 1) / BK;
+    auto stage_step = [&](int kt, int u) {
+        // stage kt's loads (issued NS-1 stages ago) must have landed; the NS-2
+        // younger stages may still be in flight
+        if (kt + NS - 2 < nk) __builtin_amdgcn_s_waitcnt(kWaitRing);
+        else __builtin_amdgcn_s_waitcnt(kWaitAll);
+        // Every wave's loads for stage kt landed; stage kt-1 fully read (its
+        // fragments fed MFMAs already issued).  A bare barrier: the release
+        // fence of __syncthreads would also wait for the younger stages'
+        // loads that the ring keeps in flight.  The clobber keeps the compiler
+        // from moving LDS accesses across it.
+        asm volatile("s_barrier" ::: "memory");
+        if (kt + NS - 1 < nk) issue(bufs[(u + NS - 1) % NS], (kt + NS - 1) * BK);
+        compute(bufs[u]);
+    };
+#pragma unroll
+    for (int s = 0; s < NS - 1; ++s)
+        if (s < nk) issue(bufs[s], s * BK);
+    // whole groups of NS stages, then the remainder; no early exits, so the
+    // accumulators keep a single home through the loop
+    int kt0 = 0;
+    for (; kt0 + NS <= nk; kt0 += NS) {
+#pragma unroll
+        for (int u = 0; u < NS; ++u) stage_step(kt0 + u, u);
+    }
+#pragma unroll
+    for (int u = 0; u < NS - 1; ++u)
+        if (kt0 + u < nk) stage_step(kt0 + u, u);
+
+    // Epilogue, staged through the (now idle) stage buffers so that every
+    // store instruction writes whole rows: a planar plane row is 128 samples x
+    // 4 B = 512 B, an interleaved row 128 x 8 B = 1 KiB.  Staged rows keep
+    // their 16-byte chunks XOR-swizzled by (row % 32) so both the writes (32
+    // beams, same samples) and the row reads are free of bank conflicts.
+    // Planar: round p stages plane p of the whole tile.  Interleaved: round h
+    // stages beams 64h..64h+63 (the waves with wm == h) with (re, im) pairs.
+    constexpr int PITCH = CIL ? 1024 : 512;           // staged row bytes
+    constexpr int ROWS_PER_BUF = G::STAGE / PITCH;
+    static_assert(ROWS_PER_BUF * (NS < 4 ? NS : 4) >= (CIL ? 64 : 128), "stage buffers hold a staging round");
+    auto row_ptr = [&](int row) -> char * {  // select chain: no dynamically indexed array
+        const int b = row / ROWS_PER_BUF;
+        char *base = b == 0 ? lds0 : b == 1 ? lds1 : b == 2 ? lds2 : lds3;
+        return base + (row % ROWS_PER_BUF) * PITCH;
+    };
+    float *Cc = C + (int64_t)c * 2 * M * N;
+    const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc((void *)Cc, 0, 8 * M * N, RSRC_FLAGS);
+#pragma unroll
+    for (int round = 0; round < 2; ++round) {
+        __syncthreads();  // stage buffers free (main loop or previous round done)
+        if (!CIL || wm == round) {
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int row = (CIL ? 0 : wm * 64) + 32 * i + l32;
+                char *rp = row_ptr(row);
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int n = wn * 64 + 32 * j + 8 * q + 4 * hl;  // first of 4 samples
+                        if (CIL) {
+                            const f32x4 re = quad(acc.re[i][j], q), im = quad(acc.im[i][j], q);
+                            const int ch = n >> 1;  // two 16-byte chunks: samples n, n+1 and n+2, n+3
+                            *reinterpret_cast<f32x4 *>(rp + ((ch ^ (row & 31)) * 16)) =
+                                (f32x4){re[0], im[0], re[1], im[1]};
+                            *reinterpret_cast<f32x4 *>(rp + (((ch + 1) ^ (row & 31)) * 16)) =
+                                (f32x4){re[2], im[2], re[3], im[3]};
+                        } else {
+                            const f32x4 v = round == 0 ? quad(acc.re[i][j], q) : quad(acc.im[i][j], q);
+                            *reinterpret_cast<f32x4 *>(rp + (((n >> 2) ^ (row & 31)) * 16)) = v;
+                        }
                     }
-                }
             }
         }
+        __syncthreads();  // round staged
+        if (CIL) {
+            // 64 rows of 1 KiB; wave w stores rows w, w+4, ...; lane l owns chunk l
+#pragma unroll 4
+            for (int t = 0; t < 16; ++t) {
+                const int row = wave + 4 * t;
+                const f32x4 v = *reinterpret_cast<const f32x4 *>(row_ptr(row) + ((lane ^ (row & 31)) * 16));
+                const int m = m0 + 64 * round + row, n = n0 + 2 * lane;
+                const uint32_t off = (m < M && n < N) ? (uint32_t)((m * N + n) * 8) : OOB;
+                __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), rc, off, 0, 0);
+            }
+        } else {
+            // 128 rows of 512 B; one instruction covers rows 2t' and 2t'+1
+#pragma unroll 4
+            for (int t = 0; t < 16; ++t) {
+                const int row = 32 * wave + 2 * t + hl;
+                const f32x4 v = *reinterpret_cast<const f32x4 *>(row_ptr(row) + ((l32 ^ (row & 31)) * 16));
+                const int m = m0 + row, n = n0 + 4 * l32;
+                const uint32_t off = (m < M && n < N) ? (uint32_t)((m * N + n) * 4) : OOB;
+                __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), rc, off, round * M * N * 4, 0);
+            }
+        }
+    }
 }
 
 typedef void (*KernFn)(const uint16_t *, const uint16_t *, float *, int64_t, int64_t, int64_t, int,
                        int, int, int64_t, int, int);
+typedef void (*FastFn)(const uint16_t *, const uint16_t *, float *, int, int, int, int, int, int, int);
 
 KernFn pick(int ail, int bil, int cil) {
     static const KernFn table[8] = {
@@ -365,14 +697,43 @@ KernFn pick(int ail, int bil, int cil) {
     return table[(ail << 2) | (bil << 1) | cil];
 }
 
+// Fast-kernel configurations: (receivers per stage, ring depth).
+constexpr int kFirstFast = 2;
+constexpr int kNumFast = 4;
+constexpr int kDefaultFast = 2;
+
+int fast_bk(int v) { return (v == 2 || v == 5) ? 32 : 16; }
+
+FastFn fast_fn(int v, bool cil) {
+    switch (v) {
+    case 2: return cil ? cgemm_f16_fast_kernel<32, 2, 1> : cgemm_f16_fast_kernel<32, 2, 0>;
+    case 3: return cil ? cgemm_f16_fast_kernel<16, 4, 1> : cgemm_f16_fast_kernel<16, 4, 0>;
+    case 4: return cil ? cgemm_f16_fast_kernel<16, 5, 1> : cgemm_f16_fast_kernel<16, 5, 0>;
+    default: return cil ? cgemm_f16_fast_kernel<32, 3, 1> : cgemm_f16_fast_kernel<32, 3, 0>;
+    }
+}
+
 }  // namespace
 
+// Variant 1: generic kernel.  Variants 2..: fast kernel (planar W and X, K and
+// N multiples of 8, every per-channel operand and output below 2 GiB so 32-bit
+// buffer offsets reach it).
+static bool fast_ok(const Problem &p) {
+    const int64_t lim = (int64_t)1 << 31;
+    return p.a_layout == TCBF_PLANAR && p.b_layout == TCBF_PLANAR && p.K % 8 == 0 && p.N % 8 == 0 &&
+           4 * p.M * p.K < lim && 4 * p.K * p.N < lim && 8 * p.M * p.N < lim && p.M < lim && p.N < lim &&
+           p.batch * ((p.M + BM - 1) / BM) * ((p.N + BN - 1) / BN) < lim;
+}
+
 bool f16_select(const Problem &p, int forced_variant, F16Config *cfg) {
-    if (forced_variant != 0 && forced_variant != 1) return false;
-    cfg->variant = 1;
+    int v = forced_variant;
+    if (v == 0) v = fast_ok(p) ? kDefaultFast : 1;
+    if (v < 1 || v >= kFirstFast + kNumFast) return false;
+    if (v >= kFirstFast && !fast_ok(p)) return false;
+    cfg->variant = v;
     cfg->tile_m = BM;
     cfg->tile_n = BN;
-    cfg->tile_k = BK;
+    cfg->tile_k = v >= kFirstFast ? fast_bk(v) : BK;
     cfg->threads = NT;
     // 16-byte loads need every row start 16-byte aligned (base pointers are
     // required to be 16-byte aligned by the ABI).
@@ -387,13 +748,22 @@ int64_t f16_workgroups(const Problem &p, const F16Config &cfg) {
     return p.batch * tm * tn;
 }
 
-const char *f16_kernel_name(const F16Config &) { return "cgemm_f16_kernel"; }
+const char *f16_kernel_name(const F16Config &cfg) {
+    return cfg.variant >= kFirstFast ? "cgemm_f16_fast_kernel" : "cgemm_f16_kernel";
+}
 
 hipError_t f16_launch(const Problem &p, const F16Config &cfg, const void *A, const void *B,
                       void *C, hipStream_t stream) {
     int tiles_m = (int)((p.M + BM - 1) / BM);
     int tiles_n = (int)((p.N + BN - 1) / BN);
     int64_t nblocks = p.batch * tiles_m * tiles_n;
+    if (cfg.variant >= kFirstFast) {
+        FastFn fn = fast_fn(cfg.variant, p.c_layout == TCBF_INTERLEAVED);
+        hipLaunchKernelGGL(fn, dim3((uint32_t)nblocks), dim3(NT), 0, stream, (const uint16_t *)A,
+                           (const uint16_t *)B, (float *)C, (int)p.M, (int)p.N, (int)p.K, p.a_shared,
+                           tiles_m, tiles_n, (int)nblocks);
+        return hipGetLastError();
+    }
     KernFn fn = pick(p.a_layout == TCBF_INTERLEAVED, p.b_layout == TCBF_INTERLEAVED,
                      p.c_layout == TCBF_INTERLEAVED);
     hipLaunchKernelGGL(fn, dim3((uint32_t)nblocks), dim3(NT), 0, stream,

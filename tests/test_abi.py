@@ -107,3 +107,10 @@ def test_valid_descriptor_without_gpu_reports_device():
     assert _plan_status() == 4
     with pytest.raises(tcbf.TcbfError):
         tcbf.Plan(1, 4, 4, 4)
+
+
+def test_no_undefined_internal_symbols():
+    """Every kernel the library launches has its host stub defined."""
+    out = subprocess.run(["nm", "-D", "--undefined-only", tcbf.LIB_PATH], capture_output=True, text=True).stdout
+    missing = [l.split()[-1] for l in out.splitlines() if "tcbf" in l]
+    assert not missing, missing

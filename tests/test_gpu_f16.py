@@ -216,3 +216,34 @@ def test_rejects_bad_tensors():
     flat = torch.zeros(A.numel() + 8, dtype=torch.float16, device="cuda:0")
     st = tcbf.lib().tcbf_execute(plan._h, flat.data_ptr() + 2, B.data_ptr(), C.data_ptr(), None, None, None)
     assert st == 1
+
+
+ALIGNED_SHAPES = [(1, 1, 8, 8), (1, 130, 136, 40), (2, 200, 264, 72), (1, 129, 8, 520), (3, 64, 128, 32),
+                  (1, 257, 392, 576), (2, 128, 128, 8)]
+
+
+FAST_VARIANTS = [2, 3, 4, 5]
+
+
+@pytest.mark.parametrize("batch,M,N,K", ALIGNED_SHAPES)
+def test_fast_and_generic_kernels_agree_bitwise(batch, M, N, K):
+    """Every fp16 kernel configuration feeds the matrix unit the same fragments
+    in the same order: outputs must be identical, and within the gate."""
+    W, X = wl.random_f16_case(13, batch, M, N, K)
+    ref, absdot = oracle_ref(W, X)
+    gen, _ = run_f16(W, X, variant=1)
+    check_fp_full(gen, ref, absdot, K)
+    for v in FAST_VARIANTS:
+        log("variant %d: batch=%d M=%d N=%d K=%d" % (v, batch, M, N, K))
+        fast, _ = run_f16(W, X, variant=v)
+        assert np.array_equal(fast, gen), "variant %d differs from the generic kernel" % v
+        fast_il, _ = run_f16(W, X, c_layout=tcbf.INTERLEAVED, variant=v)
+        assert np.array_equal(fast_il, fast), "variant %d interleaved output differs" % v
+
+
+def test_plan_picks_fast_kernel_for_aligned_planar():
+    assert tcbf.Plan(256, 1024, 4096, 576, tcbf.F16).info()["variant"] >= 2
+    assert tcbf.Plan(1, 64, 100, 64, tcbf.F16).info()["variant"] == 1          # N % 8 != 0
+    assert tcbf.Plan(1, 64, 64, 64, tcbf.F16, a_layout=tcbf.INTERLEAVED).info()["variant"] == 1
+    with pytest.raises(tcbf.TcbfError):
+        tcbf.Plan(1, 64, 100, 64, tcbf.F16, variant=2)
