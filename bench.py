@@ -43,18 +43,34 @@ def kernel_source_hash(name):
 
 
 def recorded_traffic(kernel, source):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None when there is none or the kernel source changed since it was taken."""
-    p = os.path.join(ROOT, "profiles", "traffic.json")
+    """HBM bytes per launch from the committed rocprofv3 counter summary
+    (profiles/hbm_traffic_<kernel>.txt, "key: value" lines), or None when there
+    is none or the kernel source changed since the counters were taken."""
+    p = os.path.join(ROOT, "profiles", "hbm_traffic_%s.txt" % kernel)
     if not os.path.exists(p):
         return None
+    rec = {}
+    for line in open(p):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            rec[k.strip()] = v.strip()
+    if rec.get("kernel_source_sha256_16") != kernel_source_hash(source):
+        return None
     try:
-        rec = json.load(open(p)).get(kernel)
-    except (ValueError, OSError):
+        return float(rec["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
         return None
-    if not rec or rec.get("source_sha") != kernel_source_hash(source):
-        return None
-    return rec.get("bytes_per_launch")
+
+
+def copy_calibration():
+    """A plain 1 GiB device-to-device copy, so counter runs of this script see a
+    copy kernel of known size (1 GiB read, 1 GiB written) beside the workload."""
+    import torch
+    src = torch.ones(1 << 29, dtype=torch.float16, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
 
 
 def time_launches(fn, steps, warmup):
@@ -184,6 +200,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a 1 GiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the beamforming product shards over channels with no "
@@ -199,11 +217,15 @@ def main():
         print("bench.py needs an MI355X GPU", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        copy_calibration()
 
     W, X, info, ms, tops = bench_c2(args.steps, args.warmup)
     log("c2: %.4f ms/launch, %.1f TeraOps/s" % (ms, tops))
     ach_flops = tops  # useful ops are the MFMA flops (8 per complex MAC)
     traffic = recorded_traffic(info["kernel_name"], "cgemm_f16.hip")
+    if traffic is not None:
+        traffic = round(traffic)
     roofline = {"bound": "mfma", "achieved": round(ach_flops, 1), "peak": PEAK_F16_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(ach_flops / PEAK_F16_TFLOPS, 4), "traffic": traffic,
                 "algorithmic_bytes": info["algorithmic_bytes"],

@@ -455,6 +455,17 @@ __device__ __forceinline__ half8 tr_frag(const char *lds_bytes, int off0, int of
 // s_waitcnt with only vmcnt constrained (gfx9 encoding: vmcnt low bits [3:0],
 // high bits [15:14]; expcnt and lgkmcnt left at their maxima).
 constexpr int vmcnt_imm(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4) | (15 << 8); }
+// s_waitcnt lgkmcnt(0) alone (vmcnt and expcnt left at their maxima).
+constexpr int kWaitLds = 15 | (3 << 14) | (7 << 4);
+
+// Workgroup barrier for LDS-only hazards: this wave's LDS accesses are
+// complete, then a bare s_barrier (no release fence, so outstanding global
+// stores and loads are not waited for).  The clobber keeps the compiler from
+// moving memory accesses across it.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_s_waitcnt(kWaitLds);
+    asm volatile("s_barrier" ::: "memory");
+}
 
 template <int BK, int NS, int CIL>
 __global__ __launch_bounds__(NT, 2) void cgemm_f16_fast_kernel(
@@ -634,7 +645,7 @@ __global__ __launch_bounds__(NT, 2) void cgemm_f16_fast_kernel(
     const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc((void *)Cc, 0, 8 * M * N, RSRC_FLAGS);
 #pragma unroll
     for (int round = 0; round < 2; ++round) {
-        __syncthreads();  // stage buffers free (main loop or previous round done)
+        lds_barrier();  // stage buffers free (main loop or previous round done)
         if (!CIL || wm == round) {
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
@@ -659,7 +670,7 @@ __global__ __launch_bounds__(NT, 2) void cgemm_f16_fast_kernel(
                     }
             }
         }
-        __syncthreads();  // round staged
+        lds_barrier();  // round staged
         if (CIL) {
             // 64 rows of 1 KiB; wave w stores rows w, w+4, ...; lane l owns chunk l
 #pragma unroll 4
