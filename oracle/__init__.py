@@ -47,6 +47,8 @@ def _load():
     lib.oracle_dot1bit_xor.restype = _i64
     lib.oracle_dot1bit_and.argtypes = [_i64, _p, _p]
     lib.oracle_dot1bit_and.restype = _i64
+    lib.oracle_e4m3_decode.argtypes = [_i64, _p, _p]
+    lib.oracle_quantize_e4m3_rows.argtypes = [_i64, _i64, _p, _p, _p, _p, _p]
     lib.oracle_num_threads.argtypes = []
     lib.oracle_num_threads.restype = _int
     _lib = lib
@@ -253,3 +255,30 @@ def dot1bit_and(a_words, b_words, L):
     a = _c(a_words, np.uint32)
     b = _c(b_words, np.uint32)
     return int(_load().oracle_dot1bit_and(L, _ptr(a), _ptr(b)))
+
+
+# --------------------------------------------------------------------------
+# FP8 (e4m3) mode
+# --------------------------------------------------------------------------
+
+def e4m3_decode(codes):
+    """uint8 e4m3 codes -> exact float64 values (NaN for the NaN codes)."""
+    c = _c(codes, np.uint8)
+    out = np.empty(c.shape, np.float64)
+    _load().oracle_e4m3_decode(c.size, _ptr(c), _ptr(out))
+    return out
+
+
+def quantize_e4m3_rows(re, im):
+    """Per-row quantisation of [rows, cols] planes (values converted to fp32).
+    Returns (q_re, q_im) uint8 codes and fp32 scales [rows]."""
+    r = _c(re, np.float32)
+    i = _c(im, np.float32)
+    if r.shape != i.shape or r.ndim != 2:
+        raise ValueError("re, im must be equal-shape [rows, cols]")
+    rows, cols = r.shape
+    qr = np.empty((rows, cols), np.uint8)
+    qi = np.empty((rows, cols), np.uint8)
+    sc = np.empty(rows, np.float32)
+    _load().oracle_quantize_e4m3_rows(rows, cols, _ptr(r), _ptr(i), _ptr(qr), _ptr(qi), _ptr(sc))
+    return qr, qi, sc

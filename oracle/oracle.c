@@ -301,3 +301,83 @@ int64_t oracle_dot1bit_and(int64_t L, const uint32_t *a, const uint32_t *b)
     }
     return 2 * same - L;
 }
+
+/* ------------------------------------------------------------------------- */
+/* FP8 (e4m3) mode                                                             */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * OCP FP8 E4M3 (the "8-bit float" formats the paper expects to matter, Sec. VI):
+ * 1 sign bit, 4 exponent bits with bias 7, 3 mantissa bits; exponent 0 holds
+ * subnormals m * 2^-9; exponent 15 with mantissa 7 is NaN; there are no
+ * infinities and the largest finite magnitude is 448.
+ */
+double oracle_e4m3_decode_one(uint8_t b)
+{
+    int s = b >> 7, e = (b >> 3) & 15, m = b & 7;
+    double v;
+    if (e == 15 && m == 7)
+        return NAN;
+    v = (e == 0) ? ldexp((double)m, -9) : ldexp((double)(8 + m), e - 10);
+    return s ? -v : v;
+}
+
+void oracle_e4m3_decode(int64_t n, const uint8_t *codes, double *out)
+{
+    for (int64_t i = 0; i < n; ++i)
+        out[i] = oracle_e4m3_decode_one(codes[i]);
+}
+
+/*
+ * Round a value to the nearest finite e4m3 magnitude by scanning every finite
+ * code; a tie goes to the code with an even mantissa; beyond 448 it saturates.
+ */
+static uint8_t e4m3_round_nearest_even(float y)
+{
+    double a = fabs((double)y);
+    int best = 0;
+    double best_d = a;                       /* distance to code 0 (+0.0) */
+    for (int c = 1; c <= 126; ++c) {
+        double d = fabs(oracle_e4m3_decode_one((uint8_t)c) - a);
+        if (d < best_d || (d == best_d && (c & 1) == 0)) {
+            best = c;
+            best_d = d;
+        }
+    }
+    if (isnan(y))
+        return 0x7f;
+    return (uint8_t)(best | (signbit(y) ? 0x80 : 0));
+}
+
+/*
+ * The library's per-row FP8 quantisation, step by step in fp32:
+ *   amax  = max |x| over the row's real and imaginary parts
+ *   scale = amax / 448           (1 when amax is 0)
+ *   inv   = 448 / amax           (1 when amax is 0)
+ *   q     = nearest-even e4m3 of (x * inv), saturating at 448
+ * so that q * scale approximates x.  re, im: [rows][cols] fp32 values; one
+ * scale per row.
+ */
+void oracle_quantize_e4m3_rows(int64_t rows, int64_t cols, const float *re, const float *im,
+                               uint8_t *qre, uint8_t *qim, float *scales)
+{
+    int64_t r;
+#pragma omp parallel for schedule(static)
+    for (r = 0; r < rows; ++r) {
+        float amax = 0.0f, scale, inv;
+        for (int64_t k = 0; k < cols; ++k) {
+            float a = fabsf(re[r * cols + k]), b = fabsf(im[r * cols + k]);
+            if (a > amax) amax = a;
+            if (b > amax) amax = b;
+        }
+        scale = amax > 0.0f ? amax / 448.0f : 1.0f;
+        inv = amax > 0.0f ? 448.0f / amax : 1.0f;
+        scales[r] = scale;
+        for (int64_t k = 0; k < cols; ++k) {
+            float yr = re[r * cols + k] * inv;
+            float yi = im[r * cols + k] * inv;
+            qre[r * cols + k] = e4m3_round_nearest_even(yr);
+            qim[r * cols + k] = e4m3_round_nearest_even(yi);
+        }
+    }
+}
