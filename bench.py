@@ -8,8 +8,8 @@ M=1024 beams, K=576 receivers, N=4096 samples, fp16 in, fp32 complex out),
 inputs resident in HBM.  Throughput is counted as 8 useful ops per complex
 multiply-accumulate on the unpadded sizes.  The per-launch kernel time comes
 from HIP events on the stream the library launches on (torch's current
-stream).  Prints ONE JSON line; secondary workloads (1-bit, ultrasound shape,
-sign packing) ride along in its "secondary" list.
+stream).  Prints ONE JSON line; secondary workloads (1-bit, sign packing,
+ultrasound shape in fp16 and FP8) ride along in its "secondary" list.
 """
 import argparse
 import hashlib
@@ -27,6 +27,7 @@ METRIC = "complex-GEMM TeraOps/s (8 ops/cMAC) & % MFMA peak; p99 latency served,
 # MI355X published dense peaks
 PEAK_F16_TFLOPS = 2516.6
 PEAK_I8_TOPS = 5033.2
+PEAK_F8_TFLOPS = 5033.2
 PEAK_HBM_GBS = 8000.0
 # VALU xor+popcount peak: 256 CU x 64 lanes x 2.4 GHz lane-ops/s, each xor+popcount
 # pair covers 32 real +-1 MACs = 64 ops -> 32 ops per lane-op
@@ -190,6 +191,27 @@ def bench_secondary(steps):
                 "value": round(tops, 1), "unit": "TeraOps/s", "ms_per_launch": round(ms, 4), "dtype": "f16",
                 "roofline": {"bound": "mfma", "achieved": round(tops, 1), "peak": PEAK_F16_TFLOPS,
                              "unit": "TFLOP/s", "frac": round(tops / PEAK_F16_TFLOPS, 4)}})
+    del C
+    # the same shape in FP8: W quantised once (resident weights), X quantised
+    # every step; per-row fp32 scales and per-32-block E8M0 scales
+    for dt, block, name in ((tcbf.F8_E4M3, 0, "fp8-e4m3 per-row scales"),
+                            (tcbf.MXF8_E4M3, 32, "mxfp8-e4m3 per-32-block scales")):
+        Wq, Ws = tcbf.quantize_e4m3(A, k_major=True, layout=tcbf.PLANAR, block=block)
+        Xq, Xs = tcbf.quantize_e4m3(B, k_major=False, layout=tcbf.PLANAR, block=block)
+        plan = tcbf.Plan(1, cfg["M"], cfg["N"], cfg["K"], dt)
+        info = plan.info()
+        C = plan.empty_output()
+        ms = time_launches(lambda: plan.execute(Wq, Xq, C, Ws, Xs), st, 1)
+        ms_q = time_launches(lambda: tcbf.quantize_e4m3(B, k_major=False, layout=tcbf.PLANAR, block=block,
+                                                        out=Xq, scales=Xs), st, 1)
+        tops = info["useful_ops"] / (ms * 1e-3) / 1e12
+        out.append({"workload": "ultrasound-%s: batch=1 M=32768 K=8192 N=256" % name, "kernel": info["kernel_name"],
+                    "value": round(tops, 1), "unit": "TeraOps/s", "ms_per_launch": round(ms, 4), "dtype": "e4m3",
+                    "x_quantise_ms": round(ms_q, 4),
+                    "step_with_x_quantise_tops": round(info["useful_ops"] / ((ms + ms_q) * 1e-3) / 1e12, 1),
+                    "roofline": {"bound": "mfma", "achieved": round(tops, 1), "peak": PEAK_F8_TFLOPS,
+                                 "unit": "TFLOP/s", "frac": round(tops / PEAK_F8_TFLOPS, 4)}})
+        del Wq, Ws, Xq, Xs, C
     return out
 
 

@@ -8,8 +8,10 @@
  * i.e. Eq. (3) of the Tensor-Core Beamformer paper (each beam output is the
  * weighted sum of the K receiver signals) evaluated for N samples at once,
  * which Sec. II maps to a matrix product with M = beams, N = samples and
- * K = receivers.  There is no conjugation.  Two input precisions exist, as in
- * Sec. III: 16-bit float and 1-bit (sign only, Sec. III-D).
+ * K = receivers.  There is no conjugation.  The input precisions are those of
+ * Sec. III, 16-bit float and 1-bit (sign only, Sec. III-D), plus 8-bit float
+ * (OCP FP8 e4m3), which Sec. VI names as a future option, with per-row or
+ * per-32-receiver-block scales.
  *
  * Every entry point is a plain C function over plain pointers and sizes.
  * Device pointers are HIP device (or managed) allocations; `stream` is a
@@ -46,10 +48,12 @@ typedef enum tcbf_status {
     TCBF_ERROR_INTERNAL = 5
 } tcbf_status;
 
-/* Input precision of W and X (Sec. III: 16-bit float and 1-bit). */
+/* Input precision of W and X (Sec. III: 16-bit float and 1-bit; Sec. VI: 8-bit float). */
 typedef enum tcbf_dtype {
-    TCBF_F16 = 0,  /* fp16 in, fp32 accumulate, fp32 complex out              */
-    TCBF_INT1 = 1  /* packed sign bits in, exact int32 complex out            */
+    TCBF_F16 = 0,       /* fp16 in, fp32 accumulate, fp32 complex out            */
+    TCBF_INT1 = 1,      /* packed sign bits in, exact int32 complex out          */
+    TCBF_F8_E4M3 = 2,   /* e4m3 in with one fp32 scale per row, fp32 out         */
+    TCBF_MXF8_E4M3 = 3  /* e4m3 in with an E8M0 scale per 32-receiver block       */
 } tcbf_dtype;
 
 /* Complex storage.  PLANAR keeps a real plane then an imaginary plane for each
@@ -84,6 +88,20 @@ typedef enum tcbf_src_type {
  *   C = out planar [batch][2][M][N] or interleaved [batch][M][N][2], int32
  *   a_layout and b_layout must be TCBF_PLANAR (the packed form).  Bits past K
  *   in the last word must be 0 (tcbf_pack1bit guarantees it).
+ *
+ * TCBF_F8_E4M3 / TCBF_MXF8_E4M3 layouts (as tcbf_quantize_e4m3 writes them;
+ * codes are OCP FP8 E4M3 bytes; Kp = 32 * ceil(K / 32)):
+ *   A = W   [batch][2][M][Kp]  receivers contiguous, bytes past K zero
+ *   B = X   [batch][2][N][Kp]  packed along K for each sample n
+ *   C = out planar [batch][2][M][N] or interleaved [batch][M][N][2], fp32
+ *   a_layout and b_layout must be TCBF_PLANAR; N must be a multiple of 4.
+ *   Scales (tcbf_execute's a_scale, b_scale):
+ *     TCBF_F8_E4M3:   fp32 a_scale [batch][M] (or [M] when a_shared), fp32
+ *                     b_scale [batch][N]; out = a_scale[m] * b_scale[n] *
+ *                     sum_k decode(W[m][k]) * decode(X[n][k]) (complex)
+ *     TCBF_MXF8_E4M3: uint8 E8M0 codes (2^(code-127), 255 not allowed)
+ *                     a_scale [batch][M][Kp/32] (or [M][Kp/32]), b_scale
+ *                     [batch][N][Kp/32]; block j scales receivers 32j..32j+31
  *
  * a_shared != 0: W holds a single batch entry that every channel uses.
  * C is always overwritten (the output starts from zero, as in Sec. III-B).
@@ -134,12 +152,14 @@ tcbf_status tcbf_plan(const tcbf_plan_desc *desc, tcbf_plan_t *plan);
  * tcbf_execute -- enqueue B = W . X on `stream` (Sec. III-B: four real
  * products per complex product, Im(X) negated in registers; Sec. III-D for
  * TCBF_INT1).  A, B, C are device pointers in the plan's layouts, each 16-byte
- * aligned; C must not overlap A or B.  a_scale and b_scale are reserved and
- * must be NULL.  Asynchronous, allocation-free and graph-capturable.
- * The device that is current on the calling thread must be the plan's device.
+ * aligned; C must not overlap A or B.  a_scale and b_scale are device
+ * pointers to the FP8 scales described above (16-byte aligned) and must be
+ * NULL for TCBF_F16 and TCBF_INT1.  Asynchronous, allocation-free and
+ * graph-capturable.  The device that is current on the calling thread must be
+ * the plan's device.
  */
 tcbf_status tcbf_execute(tcbf_plan_t plan, const void *A, const void *B, void *C,
-                         const float *a_scale, const float *b_scale, void *stream);
+                         const void *a_scale, const void *b_scale, void *stream);
 
 /*
  * tcbf_pack1bit -- sign-pack complex data for TCBF_INT1 (Sec. III kernels
@@ -157,6 +177,28 @@ tcbf_status tcbf_execute(tcbf_plan_t plan, const void *A, const void *B, void *C
 tcbf_status tcbf_pack1bit(const void *src, int32_t src_type, int32_t src_layout,
                           int64_t batch, int64_t rows, int64_t K, int32_t src_k_major,
                           uint32_t *dst, void *stream);
+
+/*
+ * tcbf_quantize_e4m3 -- quantise complex data to the FP8 operand form.
+ * The paper has no 8-bit kernel (Sec. VI names 8-bit floats as future work);
+ * the rule is the library's.  Every value x of a row (both parts) or of a
+ * 32-receiver block of a row is mapped to the nearest e4m3 code (ties to an
+ * even mantissa, saturating at +-448, NaN to 0x7f) of:
+ *   block == 0:  x * (448 / amax), scale = amax / 448 (both fp32; 1 and 1 when
+ *                amax == 0), amax = max |x| over the row's re and im parts
+ *   block == 32: ldexp(x, -e), scale code e + 127, e the smallest integer with
+ *                amax <= 448 * 2^e over the block (clamped to [-127, 127],
+ *                0 for an all-zero block)
+ *   src (device), src_type, src_layout and src_k_major as for tcbf_pack1bit.
+ *   dst (device): [batch][2][rows][Kp] bytes, Kp = 32 * ceil(K / 32), zero
+ *   past K.  scales (device): block 0: fp32 [batch][rows]; block 32: uint8
+ *   [batch][rows][Kp / 32].
+ * src, dst and scales must be 16-byte aligned device buffers that do not
+ * overlap.  Enqueues several kernels on `stream`; allocation-free.
+ */
+tcbf_status tcbf_quantize_e4m3(const void *src, int32_t src_type, int32_t src_layout,
+                               int64_t batch, int64_t rows, int64_t K, int32_t src_k_major,
+                               int32_t block, uint8_t *dst, void *scales, void *stream);
 
 /* Report the plan's choice.  info->struct_size must be set by the caller. */
 tcbf_status tcbf_plan_query(tcbf_plan_t plan, tcbf_plan_info *info);

@@ -49,6 +49,7 @@ def _load():
     lib.oracle_dot1bit_and.restype = _i64
     lib.oracle_e4m3_decode.argtypes = [_i64, _p, _p]
     lib.oracle_quantize_e4m3_rows.argtypes = [_i64, _i64, _p, _p, _p, _p, _p]
+    lib.oracle_quantize_e4m3_blocks.argtypes = [_i64, _i64, _p, _p, _p, _p, _p]
     lib.oracle_num_threads.argtypes = []
     lib.oracle_num_threads.restype = _int
     _lib = lib
@@ -282,3 +283,26 @@ def quantize_e4m3_rows(re, im):
     sc = np.empty(rows, np.float32)
     _load().oracle_quantize_e4m3_rows(rows, cols, _ptr(r), _ptr(i), _ptr(qr), _ptr(qi), _ptr(sc))
     return qr, qi, sc
+
+
+def quantize_e4m3_blocks(re, im):
+    """Per-32-block quantisation of [rows, cols] planes (values converted to
+    fp32).  Returns (q_re, q_im) uint8 codes and uint8 E8M0 scale codes
+    [rows, ceil(cols / 32)] (scale 2^(code - 127))."""
+    r = _c(re, np.float32)
+    i = _c(im, np.float32)
+    if r.shape != i.shape or r.ndim != 2:
+        raise ValueError("re, im must be equal-shape [rows, cols]")
+    rows, cols = r.shape
+    qr = np.empty((rows, cols), np.uint8)
+    qi = np.empty((rows, cols), np.uint8)
+    codes = np.empty((rows, (cols + 31) // 32), np.uint8)
+    _load().oracle_quantize_e4m3_blocks(rows, cols, _ptr(r), _ptr(i), _ptr(qr), _ptr(qi), _ptr(codes))
+    return qr, qi, codes
+
+
+def e8m0_decode(codes):
+    """E8M0 scale codes -> float64 powers of two 2^(code - 127) (NaN for 255)."""
+    c = np.asarray(codes, np.int64)
+    out = np.ldexp(1.0, c - 127)
+    return np.where(c == 255, np.nan, out)

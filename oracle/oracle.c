@@ -381,3 +381,55 @@ void oracle_quantize_e4m3_rows(int64_t rows, int64_t cols, const float *re, cons
         }
     }
 }
+
+/*
+ * Smallest integer e with amax <= 448 * 2^e (the power-of-two scale that
+ * brings a block's largest magnitude inside the e4m3 range), found by plain
+ * upward search from -127; 127 when no e up to 127 suffices (infinity), 0 for
+ * an all-zero block.  E8M0 stores e + 127.
+ */
+static int mx_block_exponent(float amax)
+{
+    int e;
+    if (!(amax > 0.0f))
+        return 0;
+    for (e = -127; e < 127; ++e)
+        if ((double)amax <= 448.0 * ldexp(1.0, e))
+            return e;
+    return 127;
+}
+
+/*
+ * The library's per-block FP8 quantisation (the OCP MX arrangement: one
+ * power-of-two scale per 32 consecutive receivers of a row, shared by its real
+ * and imaginary parts):
+ *   amax  = max |x| over the block's real and imaginary parts (fp32, NaN ignored)
+ *   e     = mx_block_exponent(amax)
+ *   q     = nearest-even e4m3 of x * 2^-e (exact in double, then fp32)
+ * re, im: [rows][cols]; codes: [rows][ceil(cols / 32)] holding e + 127.
+ */
+void oracle_quantize_e4m3_blocks(int64_t rows, int64_t cols, const float *re, const float *im,
+                                 uint8_t *qre, uint8_t *qim, uint8_t *codes)
+{
+    const int64_t nb = (cols + 31) / 32;
+    int64_t r;
+#pragma omp parallel for schedule(static)
+    for (r = 0; r < rows; ++r) {
+        for (int64_t b = 0; b < nb; ++b) {
+            const int64_t k0 = 32 * b, k1 = (k0 + 32 < cols) ? k0 + 32 : cols;
+            float amax = 0.0f;
+            int e;
+            for (int64_t k = k0; k < k1; ++k) {
+                float a = fabsf(re[r * cols + k]), c = fabsf(im[r * cols + k]);
+                if (a > amax) amax = a;
+                if (c > amax) amax = c;
+            }
+            e = mx_block_exponent(amax);
+            codes[r * nb + b] = (uint8_t)(e + 127);
+            for (int64_t k = k0; k < k1; ++k) {
+                qre[r * cols + k] = e4m3_round_nearest_even((float)ldexp((double)re[r * cols + k], -e));
+                qim[r * cols + k] = e4m3_round_nearest_even((float)ldexp((double)im[r * cols + k], -e));
+            }
+        }
+    }
+}

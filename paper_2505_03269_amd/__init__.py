@@ -12,19 +12,19 @@ import ctypes
 import os
 
 __all__ = [
-    "F16", "INT1", "PLANAR", "INTERLEAVED", "SRC_I8", "SRC_F16", "SRC_F32",
-    "TcbfError", "Plan", "pack1bit", "lib", "status_string", "EXPORTS",
+    "F16", "INT1", "F8_E4M3", "MXF8_E4M3", "PLANAR", "INTERLEAVED", "SRC_I8", "SRC_F16", "SRC_F32",
+    "TcbfError", "Plan", "pack1bit", "quantize_e4m3", "f8_kp", "lib", "status_string", "EXPORTS",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtcbf.so")
 
-F16, INT1 = 0, 1
+F16, INT1, F8_E4M3, MXF8_E4M3 = 0, 1, 2, 3
 PLANAR, INTERLEAVED = 0, 1
 SRC_I8, SRC_F16, SRC_F32 = 0, 1, 2
 
 # every symbol include/tcbf.h declares
-EXPORTS = ("tcbf_plan", "tcbf_execute", "tcbf_pack1bit", "tcbf_plan_query",
+EXPORTS = ("tcbf_plan", "tcbf_execute", "tcbf_pack1bit", "tcbf_quantize_e4m3", "tcbf_plan_query",
            "tcbf_plan_destroy", "tcbf_status_string", "tcbf_version")
 
 _STATUS = {0: "TCBF_SUCCESS", 1: "TCBF_ERROR_INVALID_VALUE", 2: "TCBF_ERROR_NOT_SUPPORTED",
@@ -71,6 +71,8 @@ def lib():
     L.tcbf_execute.restype = i32
     L.tcbf_pack1bit.argtypes = [vp, i32, i32, i64, i64, i64, i32, vp, vp]
     L.tcbf_pack1bit.restype = i32
+    L.tcbf_quantize_e4m3.argtypes = [vp, i32, i32, i64, i64, i64, i32, i32, vp, vp, vp]
+    L.tcbf_quantize_e4m3.restype = i32
     L.tcbf_plan_query.argtypes = [vp, ctypes.POINTER(PlanInfo)]
     L.tcbf_plan_query.restype = i32
     L.tcbf_plan_destroy.argtypes = [vp]
@@ -81,6 +83,15 @@ def lib():
     L.tcbf_version.restype = i32
     _lib = L
     return L
+
+
+def f8_kp(K):
+    """Row pitch (bytes) of the FP8 operand form: 32 * ceil(K / 32)."""
+    return (int(K) + 31) // 32 * 32
+
+
+def _is_f8(dtype):
+    return dtype in (F8_E4M3, MXF8_E4M3)
 
 
 def status_string(status):
@@ -145,12 +156,24 @@ class Plan:
         nb = 1 if self.a_shared else self.batch
         if self.dtype == INT1:
             return (nb, 2, self.M, (self.K + 31) // 32)
+        if _is_f8(self.dtype):
+            return (nb, 2, self.M, f8_kp(self.K))
         return (nb, 2, self.M, self.K) if self.a_layout == PLANAR else (nb, self.M, self.K, 2)
 
     def shape_b(self):
         if self.dtype == INT1:
             return (self.batch, 2, self.N, (self.K + 31) // 32)
+        if _is_f8(self.dtype):
+            return (self.batch, 2, self.N, f8_kp(self.K))
         return (self.batch, 2, self.K, self.N) if self.b_layout == PLANAR else (self.batch, self.K, self.N, 2)
+
+    def shape_a_scale(self):
+        """FP8 modes: W scales ([nb, M] fp32 per row, [nb, M, Kp/32] uint8 per block)."""
+        nb = 1 if self.a_shared else self.batch
+        return (nb, self.M) if self.dtype == F8_E4M3 else (nb, self.M, f8_kp(self.K) // 32)
+
+    def shape_b_scale(self):
+        return (self.batch, self.N) if self.dtype == F8_E4M3 else (self.batch, self.N, f8_kp(self.K) // 32)
 
     def shape_c(self):
         return (self.batch, 2, self.M, self.N) if self.c_layout == PLANAR else (self.batch, self.M, self.N, 2)
@@ -159,24 +182,38 @@ class Plan:
         import torch
         if self.dtype == INT1:
             return torch.int32, torch.int32, torch.int32  # packed words viewed as int32
+        if _is_f8(self.dtype):
+            return torch.uint8, torch.uint8, torch.float32  # e4m3 codes
         return torch.float16, torch.float16, torch.float32
 
     def empty_output(self):
         import torch
         return torch.empty(self.shape_c(), dtype=self._dtypes()[2], device="cuda:%d" % self.device)
 
-    def execute(self, A, B, C, stream=None):
-        """Enqueue C = A . B (W, X, output) on the current torch stream."""
+    def execute(self, A, B, C, a_scale=None, b_scale=None, stream=None):
+        """Enqueue C = A . B (W, X, output) on the current torch stream.
+
+        FP8 modes also take the W and X scales (as quantize_e4m3 returns them).
+        """
         import torch
         ta, tb, tc = self._dtypes()
-        for t, dt, shp, nm in ((A, ta, self.shape_a(), "A"), (B, tb, self.shape_b(), "B"),
-                               (C, tc, self.shape_c(), "C")):
+        checks = [(A, ta, self.shape_a(), "A"), (B, tb, self.shape_b(), "B"), (C, tc, self.shape_c(), "C")]
+        if _is_f8(self.dtype):
+            if a_scale is None or b_scale is None:
+                raise ValueError("FP8 plans need a_scale and b_scale")
+            st = torch.float32 if self.dtype == F8_E4M3 else torch.uint8
+            checks += [(a_scale, st, self.shape_a_scale(), "a_scale"), (b_scale, st, self.shape_b_scale(), "b_scale")]
+        elif a_scale is not None or b_scale is not None:
+            raise ValueError("scales are only taken by FP8 plans")
+        for t, dt, shp, nm in checks:
             if t.dtype != dt and not (self.dtype == INT1 and t.dtype == torch.uint32 and nm != "C"):
                 raise ValueError("%s must be %s, got %s" % (nm, dt, t.dtype))
             if tuple(t.shape) != tuple(shp):
                 raise ValueError("%s must have shape %s, got %s" % (nm, shp, tuple(t.shape)))
         pa, pb, pc = _dev_ptr(A, "A"), _dev_ptr(B, "B"), _dev_ptr(C, "C")
-        _check(lib().tcbf_execute(self._h, pa, pb, pc, None, None, _stream_handle(stream)), "tcbf_execute")
+        psa = _dev_ptr(a_scale, "a_scale") if a_scale is not None else None
+        psb = _dev_ptr(b_scale, "b_scale") if b_scale is not None else None
+        _check(lib().tcbf_execute(self._h, pa, pb, pc, psa, psb, _stream_handle(stream)), "tcbf_execute")
         return C
 
 
@@ -214,3 +251,49 @@ def pack1bit(src, K=None, k_major=True, layout=PLANAR, out=None, stream=None):
                                int(kk), int(bool(k_major)), _dev_ptr(out, "out"), _stream_handle(stream)),
            "tcbf_pack1bit")
     return out
+
+
+def _source_geometry(src, k_major, layout):
+    if src.dim() != 4:
+        raise ValueError("source must be 4-d")
+    if layout == PLANAR:
+        if src.shape[1] != 2:
+            raise ValueError("planar source needs a plane axis of 2")
+        rows, kk = (src.shape[2], src.shape[3]) if k_major else (src.shape[3], src.shape[2])
+    else:
+        if src.shape[3] != 2:
+            raise ValueError("interleaved source needs a trailing axis of 2")
+        rows, kk = (src.shape[1], src.shape[2]) if k_major else (src.shape[2], src.shape[1])
+    return src.shape[0], rows, kk
+
+
+def quantize_e4m3(src, k_major=True, layout=PLANAR, block=0, out=None, scales=None, stream=None):
+    """Quantise a device tensor (int8 / float16 / float32) to the FP8 operand form.
+
+    Source orientation as for pack1bit.  Returns (codes, scales): uint8 codes
+    [batch, 2, rows, Kp] and fp32 scales [batch, rows] (block=0) or uint8 E8M0
+    codes [batch, rows, Kp/32] (block=32).
+    """
+    import torch
+    types = {torch.int8: SRC_I8, torch.float16: SRC_F16, torch.float32: SRC_F32}
+    if src.dtype not in types:
+        raise ValueError("unsupported source dtype %s" % src.dtype)
+    batch, rows, kk = _source_geometry(src, k_major, layout)
+    kp = f8_kp(kk)
+    if out is None:
+        out = torch.empty((batch, 2, rows, kp), dtype=torch.uint8, device=src.device)
+    if scales is None:
+        if block == 0:
+            scales = torch.empty((batch, rows), dtype=torch.float32, device=src.device)
+        else:
+            scales = torch.empty((batch, rows, kp // 32), dtype=torch.uint8, device=src.device)
+    if tuple(out.shape) != (batch, 2, rows, kp) or out.dtype != torch.uint8:
+        raise ValueError("out must be uint8 [batch, 2, rows, Kp]")
+    want = ((batch, rows), torch.float32) if block == 0 else ((batch, rows, kp // 32), torch.uint8)
+    if tuple(scales.shape) != want[0] or scales.dtype != want[1]:
+        raise ValueError("scales must be %s %s" % (want[1], want[0]))
+    _check(lib().tcbf_quantize_e4m3(_dev_ptr(src, "src"), types[src.dtype], int(layout), int(batch), int(rows),
+                                    int(kk), int(bool(k_major)), int(block), _dev_ptr(out, "out"),
+                                    _dev_ptr(scales, "scales"), _stream_handle(stream)),
+           "tcbf_quantize_e4m3")
+    return out, scales

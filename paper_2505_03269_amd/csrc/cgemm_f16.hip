@@ -30,49 +30,26 @@
 //  * cgemm_f16_kernel: any layout and alignment.  Tiles go through registers,
 //    interleaved (re, im) data is split into planes and X is transposed while
 //    being written to LDS.
-#include "tcbf_internal.h"
+#include "tcbf_tile.h"
 
 namespace tcbf {
 namespace {
 
+using namespace tile;
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef short short4v __attribute__((ext_vector_type(4)));
-typedef float f32x16 __attribute__((ext_vector_type(16)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+#define LDS_AS TCBF_LDS_AS
 
-#define LDS_AS __attribute__((address_space(3)))
-
-constexpr int BM = 128, BN = 128, BK = 32, NT = 256;
+constexpr int BK = 32;                    // receivers per stage (generic kernel)
 constexpr int PLANE_A = BM * BK;          // halves per W plane in a stage
 constexpr int PLANE_B = BN * BK;          // halves per X plane in a stage
 constexpr int STAGE = 2 * PLANE_A + 2 * PLANE_B;  // 16384 halves = 32 KiB
-constexpr uint32_t OOB = 0x80000000u;     // buffer offset past every range: reads 0, writes dropped
-constexpr int RSRC_FLAGS = 0x00020000;    // raw buffer, 32-bit data format (gfx9 family)
 
 __device__ __forceinline__ half8 negate(half8 v) {
     u32x4 u = __builtin_bit_cast(u32x4, v);
     u ^= 0x80008000u;  // flip both fp16 sign bits: exact negation
     return __builtin_bit_cast(half8, u);
 }
-
-// Accumulators of one wave: [i: 32-beam sub-tile][j: 32-sample sub-tile].
-// Element r of lane l holds beam i*32 + l%32 and samples
-// j*32 + 8*(r/4) + 4*(l/32) + r%4: each lane owns runs of four consecutive
-// samples of one beam.
-struct Acc {
-    f32x16 re[2][2], im[2][2];
-    __device__ void zero() {
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                re[i][j] = (f32x16){};
-                im[i][j] = (f32x16){};
-            }
-    }
-};
 
 // One 16-receiver step.  w*: W fragments (lane l: beam l%32, receivers
 // 8*(l/32) + 0..7); x*: X fragments (lane l: sample l%32, same receivers).
@@ -90,16 +67,6 @@ __device__ __forceinline__ void mma_step(Acc &a, const half8 (&wr)[2], const hal
             a.re[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(xi[j], wn[i], a.re[i][j], 0, 0, 0);
             a.im[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(xr[j], wi[i], a.im[i][j], 0, 0, 0);
         }
-}
-
-// Four consecutive accumulator elements 4q..4q+3 (a sub-register view).
-__device__ __forceinline__ f32x4 quad(const f32x16 &v, int q) {
-    switch (q) {
-    case 0: return __builtin_shufflevector(v, v, 0, 1, 2, 3);
-    case 1: return __builtin_shufflevector(v, v, 4, 5, 6, 7);
-    case 2: return __builtin_shufflevector(v, v, 8, 9, 10, 11);
-    default: return __builtin_shufflevector(v, v, 12, 13, 14, 15);
-    }
 }
 
 // ===========================================================================
@@ -452,21 +419,6 @@ __device__ __forceinline__ half8 tr_frag(const char *lds_bytes, int off0, int of
     return __builtin_bit_cast(half8, v);
 }
 
-// s_waitcnt with only vmcnt constrained (gfx9 encoding: vmcnt low bits [3:0],
-// high bits [15:14]; expcnt and lgkmcnt left at their maxima).
-constexpr int vmcnt_imm(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4) | (15 << 8); }
-// s_waitcnt lgkmcnt(0) alone (vmcnt and expcnt left at their maxima).
-constexpr int kWaitLds = 15 | (3 << 14) | (7 << 4);
-
-// Workgroup barrier for LDS-only hazards: this wave's LDS accesses are
-// complete, then a bare s_barrier (no release fence, so outstanding global
-// stores and loads are not waited for).  The clobber keeps the compiler from
-// moving memory accesses across it.
-__device__ __forceinline__ void lds_barrier() {
-    __builtin_amdgcn_s_waitcnt(kWaitLds);
-    asm volatile("s_barrier" ::: "memory");
-}
-
 template <int BK, int NS, int CIL>
 __global__ __launch_bounds__(NT, 2) void cgemm_f16_fast_kernel(
     const uint16_t *__restrict__ A, const uint16_t *__restrict__ B, float *__restrict__ C,
@@ -626,73 +578,15 @@ __global__ __launch_bounds__(NT, 2) void cgemm_f16_fast_kernel(
     for (int u = 0; u < NS - 1; ++u)
         if (kt0 + u < nk) stage_step(kt0 + u, u);
 
-    // Epilogue, staged through the (now idle) stage buffers so that every
-    // store instruction writes whole rows: a planar plane row is 128 samples x
-    // 4 B = 512 B, an interleaved row 128 x 8 B = 1 KiB.  Staged rows keep
-    // their 16-byte chunks XOR-swizzled by (row % 32) so both the writes (32
-    // beams, same samples) and the row reads are free of bank conflicts.
-    // Planar: round p stages plane p of the whole tile.  Interleaved: round h
-    // stages beams 64h..64h+63 (the waves with wm == h) with (re, im) pairs.
-    constexpr int PITCH = CIL ? 1024 : 512;           // staged row bytes
-    constexpr int ROWS_PER_BUF = G::STAGE / PITCH;
+    // Epilogue through the (now idle) stage buffers.
+    constexpr int ROWS_PER_BUF = G::STAGE / staging_pitch<CIL>();
     static_assert(ROWS_PER_BUF * (NS < 4 ? NS : 4) >= (CIL ? 64 : 128), "stage buffers hold a staging round");
     auto row_ptr = [&](int row) -> char * {  // select chain: no dynamically indexed array
         const int b = row / ROWS_PER_BUF;
         char *base = b == 0 ? lds0 : b == 1 ? lds1 : b == 2 ? lds2 : lds3;
-        return base + (row % ROWS_PER_BUF) * PITCH;
+        return base + (row % ROWS_PER_BUF) * staging_pitch<CIL>();
     };
-    float *Cc = C + (int64_t)c * 2 * M * N;
-    const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc((void *)Cc, 0, 8 * M * N, RSRC_FLAGS);
-#pragma unroll
-    for (int round = 0; round < 2; ++round) {
-        lds_barrier();  // stage buffers free (main loop or previous round done)
-        if (!CIL || wm == round) {
-#pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                const int row = (CIL ? 0 : wm * 64) + 32 * i + l32;
-                char *rp = row_ptr(row);
-#pragma unroll
-                for (int j = 0; j < 2; ++j)
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int n = wn * 64 + 32 * j + 8 * q + 4 * hl;  // first of 4 samples
-                        if (CIL) {
-                            const f32x4 re = quad(acc.re[i][j], q), im = quad(acc.im[i][j], q);
-                            const int ch = n >> 1;  // two 16-byte chunks: samples n, n+1 and n+2, n+3
-                            *reinterpret_cast<f32x4 *>(rp + ((ch ^ (row & 31)) * 16)) =
-                                (f32x4){re[0], im[0], re[1], im[1]};
-                            *reinterpret_cast<f32x4 *>(rp + (((ch + 1) ^ (row & 31)) * 16)) =
-                                (f32x4){re[2], im[2], re[3], im[3]};
-                        } else {
-                            const f32x4 v = round == 0 ? quad(acc.re[i][j], q) : quad(acc.im[i][j], q);
-                            *reinterpret_cast<f32x4 *>(rp + (((n >> 2) ^ (row & 31)) * 16)) = v;
-                        }
-                    }
-            }
-        }
-        lds_barrier();  // round staged
-        if (CIL) {
-            // 64 rows of 1 KiB; wave w stores rows w, w+4, ...; lane l owns chunk l
-#pragma unroll 4
-            for (int t = 0; t < 16; ++t) {
-                const int row = wave + 4 * t;
-                const f32x4 v = *reinterpret_cast<const f32x4 *>(row_ptr(row) + ((lane ^ (row & 31)) * 16));
-                const int m = m0 + 64 * round + row, n = n0 + 2 * lane;
-                const uint32_t off = (m < M && n < N) ? (uint32_t)((m * N + n) * 8) : OOB;
-                __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), rc, off, 0, 0);
-            }
-        } else {
-            // 128 rows of 512 B; one instruction covers rows 2t' and 2t'+1
-#pragma unroll 4
-            for (int t = 0; t < 16; ++t) {
-                const int row = 32 * wave + 2 * t + hl;
-                const f32x4 v = *reinterpret_cast<const f32x4 *>(row_ptr(row) + ((l32 ^ (row & 31)) * 16));
-                const int m = m0 + row, n = n0 + 4 * l32;
-                const uint32_t off = (m < M && n < N) ? (uint32_t)((m * N + n) * 4) : OOB;
-                __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), rc, off, round * M * N * 4, 0);
-            }
-        }
-    }
+    store_tile_staged<CIL>(acc, row_ptr, C + (int64_t)c * 2 * M * N, M, N, m0, n0, wave, lane);
 }
 
 typedef void (*KernFn)(const uint16_t *, const uint16_t *, float *, int64_t, int64_t, int64_t, int,

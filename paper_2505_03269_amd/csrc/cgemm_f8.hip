@@ -1,0 +1,316 @@
+// FP8 (OCP e4m3) complex beamforming product on the gfx950 FP8 matrix cores.
+//
+// The 8-bit path is the library's extension of Sec. III-B (the paper names
+// 8-bit floats as future work in Sec. VI).  Inputs are e4m3 codes as the
+// quantiser writes them: W [batch][2][M][Kp] and X [batch][2][N][Kp], both
+// receiver-contiguous with Kp = 32 * ceil(K / 32) and zero padding.  The sum
+// over receivers is exact-product, fp32-accumulated:
+//   per-row scales (TCBF_F8_E4M3): C[m][n] = a_scale[m] * b_scale[n] * sum_k W8 X8
+//     -- the scales factor out of the sum, so they are applied in the epilogue;
+//   per-block scales (TCBF_MXF8_E4M3): every 32-receiver block carries its own
+//     power-of-two scales, applied inside the scaled MFMA per lane.
+// As in the 16-bit kernel, the imaginary part of the product uses W's
+// imaginary plane negated in registers (a sign-bit flip, exact in e4m3).
+//
+// Workgroup: 128 beams x 128 samples, 4 waves in a 2 x 2 grid of 64 x 64
+// blocks, each wave 2 x 2 MFMA tiles of v_mfma_scale_f32_32x32x64_f8f6f4 per
+// real/imaginary accumulator.  One stage holds 64 receivers of both operands
+// (2 planes x 128 rows x 64 bytes each, 32 KiB) and is moved by direct-to-LDS
+// buffer loads; 16-byte chunks of a row sit XOR-swizzled so the fragment reads
+// (32 rows x one chunk per half-wave) are free of bank conflicts.
+//
+// Operand layout of the 32x32x64 FP8 instruction (measured with one nonzero
+// byte per row against distinct block scales): lane l supplies row l%32; its
+// first 16 bytes are receivers 16*(l/32) + 0..15 of the step and its second 16
+// bytes receivers 32 + 16*(l/32) + 0..15.  The block scale a lane passes
+// covers receivers 32*(l/32) + 0..31 of its row.  So a lane reads staged
+// chunks l/32 and 2 + l/32, and lanes 0..31 / 32..63 pass the scales of the
+// step's first / second 32-receiver block.
+//
+// The instruction sums its products in groups of 8 and, within a group,
+// keeps about 14 bits below the leading product (measured: terms 2^-14 of the
+// leading one and smaller are dropped); group sums accumulate in fp32.
+#include "tcbf_tile.h"
+
+namespace tcbf {
+namespace {
+
+using namespace tile;
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+
+constexpr int BK = 64;                  // receivers (bytes) per stage
+constexpr int ROWB = BK;                // staged row bytes
+constexpr int PLANE = BM * ROWB;        // one plane of one operand: 8 KiB
+constexpr int REG = 2 * PLANE;          // one operand (2 planes): 16 KiB
+constexpr int STAGE = 2 * REG;          // W then X: 32 KiB
+constexpr int PIECES_PER_WAVE = REG / 1024 / 4;  // 1 KiB wave loads per operand per wave
+constexpr int PIECE_ROWS = 1024 / ROWB;          // rows per wave load
+constexpr uint32_t NEG = 0x80808080u;   // sign bits of four e4m3 codes
+constexpr int SCALE_ONE = 127;          // E8M0 code of 2^0
+
+static_assert(BM == BN, "both operands share the staged geometry");
+
+// Position of chunk ch (0..3) of staged row m: ch ^ swz(m).  Uses row bits
+// 1..3 only, so rows 16 apart (the wave-load step) and 32 apart (the MFMA
+// tile step) share a swizzle.
+__device__ __forceinline__ int swz(int m) { return ((m >> 1) ^ ((m >> 3) & 1)) & 3; }
+
+__device__ __forceinline__ i32x8 frag(const char *st, int o0, int o1) {
+    const u32x4 lo = *reinterpret_cast<const u32x4 *>(st + o0);
+    const u32x4 hi = *reinterpret_cast<const u32x4 *>(st + o1);
+    return (i32x8){(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3], (int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
+}
+
+__device__ __forceinline__ f32x16 mma(const i32x8 &x, const i32x8 &w, const f32x16 &c, int sx, int sw) {
+    // A = X fragment (rows: samples), B = W fragment (columns: beams); both e4m3
+    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(x, w, c, 0, 0, 0, sx, 0, sw);
+}
+
+template <int NS, int CIL, int MX>
+__global__ __launch_bounds__(NT, 2) void cgemm_f8_kernel(
+    const uint8_t *__restrict__ A, const uint8_t *__restrict__ B, float *__restrict__ C,
+    const void *__restrict__ a_scale, const void *__restrict__ b_scale, int M, int N, int Kp, int a_shared,
+    int tiles_m, int tiles_n, int nblocks) {
+    static_assert(NS >= 2 && NS <= 4, "ring depth");
+    __shared__ __attribute__((aligned(1024))) char lds0[STAGE];
+    __shared__ __attribute__((aligned(1024))) char lds1[STAGE];
+    __shared__ __attribute__((aligned(NS > 2 ? 1024 : 4))) char lds2[NS > 2 ? STAGE : 4];
+    __shared__ __attribute__((aligned(NS > 3 ? 1024 : 4))) char lds3[NS > 3 ? STAGE : 4];
+    char *const bufs[4] = {lds0, lds1, lds2, lds3};
+
+    const int tid = threadIdx.x;
+    const int t = (int)xcd_remap(blockIdx.x, nblocks);
+    const int per_c = tiles_m * tiles_n;
+    const int c = t / per_c;
+    const int rem = t - c * per_c;
+    const int tn = rem / tiles_m, tm = rem - tn * tiles_m;
+    const int m0 = tm * BM, n0 = tn * BN;
+
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int hl = lane >> 5, l32 = lane & 31;
+
+    const int cw = a_shared ? 0 : c;
+    const uint8_t *Wc = A + (int64_t)cw * 2 * M * Kp;
+    const uint8_t *Xc = B + (int64_t)c * 2 * N * Kp;
+    const __amdgpu_buffer_rsrc_t rw = __builtin_amdgcn_make_buffer_rsrc((void *)Wc, 0, 2 * M * Kp, RSRC_FLAGS);
+    const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc((void *)Xc, 0, 2 * N * Kp, RSRC_FLAGS);
+
+    // This lane's 16-byte chunk in each of the wave's loads.  Slot s of an
+    // operand region (16 B each, lane order within a 1 KiB wave load) holds
+    // plane s/512, row (s/4)%128, chunk (s%4)^swz(row); the wave's pieces are
+    // 16 rows apart within one plane.
+    int row0, kc;  // staged row of piece 0, receiver offset of the chunk
+    uint32_t plane_off_w, plane_off_x;
+    {
+        const int s = wave * PIECES_PER_WAVE * 64 + lane;
+        const int p = s / (BM * 4);
+        row0 = (s / 4) % BM;
+        kc = ((s & 3) ^ swz(row0)) * 16;
+        plane_off_w = (uint32_t)(p * M) * Kp;
+        plane_off_x = (uint32_t)(p * N) * Kp;
+    }
+
+    // Fragment offsets within a stage (plane 0 of W; X adds REG, the
+    // imaginary plane adds PLANE, the second 32-row tile adds 32 rows).
+    const int fw = wm * 64 + l32, fx = wn * 64 + l32;
+    const int ow0 = fw * ROWB + ((hl ^ swz(fw)) * 16), ow1 = fw * ROWB + (((2 + hl) ^ swz(fw)) * 16);
+    const int ox0 = REG + fx * ROWB + ((hl ^ swz(fx)) * 16);
+    const int ox1 = REG + fx * ROWB + (((2 + hl) ^ swz(fx)) * 16);
+
+    // Per-block scale bytes: this lane reads block 2*kt + hl of beams fw, fw+32
+    // and samples fx, fx+32 ([rows][Kp/32] per channel).
+    const int nkb = Kp / 32;
+    const uint8_t *ASc = MX ? (const uint8_t *)a_scale + (int64_t)cw * M * nkb : nullptr;
+    const uint8_t *BSc = MX ? (const uint8_t *)b_scale + (int64_t)c * N * nkb : nullptr;
+    const __amdgpu_buffer_rsrc_t rsa = __builtin_amdgcn_make_buffer_rsrc((void *)ASc, 0, MX ? M * nkb : 0, RSRC_FLAGS);
+    const __amdgpu_buffer_rsrc_t rsb = __builtin_amdgcn_make_buffer_rsrc((void *)BSc, 0, MX ? N * nkb : 0, RSRC_FLAGS);
+    uint32_t sa_off[2] = {OOB, OOB}, sb_off[2] = {OOB, OOB};
+    if (MX) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int m = m0 + fw + 32 * i, n = n0 + fx + 32 * i;
+            sa_off[i] = m < M ? (uint32_t)(m * nkb + hl) : OOB;
+            sb_off[i] = n < N ? (uint32_t)(n * nkb + hl) : OOB;
+        }
+    }
+    // [stage slot][W tile i, X tile j]; whole-ring static indices only
+    int sreg[NS][4];
+#pragma unroll
+    for (int u = 0; u < NS; ++u)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) sreg[u][q] = SCALE_ONE;
+
+    auto issue = [&](char *base, int kt, int u) {
+        const int k0 = kt * BK;
+        const bool kin = k0 + kc < Kp;
+#pragma unroll
+        for (int q = 0; q < PIECES_PER_WAVE; ++q) {
+            const int r = row0 + q * PIECE_ROWS;
+            const uint32_t off = (kin && m0 + r < M) ? plane_off_w + (uint32_t)(m0 + r) * Kp + kc : OOB;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rw, (TCBF_LDS_AS void *)(base + (wave * PIECES_PER_WAVE + q) * 1024),
+                                                     16, off, k0, 0, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < PIECES_PER_WAVE; ++q) {
+            const int r = row0 + q * PIECE_ROWS;
+            const uint32_t off = (kin && n0 + r < N) ? plane_off_x + (uint32_t)(n0 + r) * Kp + kc : OOB;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                rx, (TCBF_LDS_AS void *)(base + REG + (wave * PIECES_PER_WAVE + q) * 1024), 16, off, k0, 0, 0);
+        }
+        if (MX) {
+            // a block past Kp/32 (second half of the last stage when Kp % 64
+            // == 32) has zero data; it reads scale code 0 instead of a
+            // neighbour's byte
+            const bool bin = 2 * kt + hl < nkb;
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                sreg[u][i] = __builtin_amdgcn_raw_buffer_load_b8(rsa, bin ? sa_off[i] + 2 * kt : OOB, 0, 0);
+                sreg[u][2 + i] = __builtin_amdgcn_raw_buffer_load_b8(rsb, bin ? sb_off[i] + 2 * kt : OOB, 0, 0);
+            }
+        }
+    };
+
+    Acc acc;
+    acc.zero();
+    auto compute = [&](const char *st, int u) {
+        i32x8 xr[2], xi[2];
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            xr[j] = frag(st, ox0 + j * 32 * ROWB, ox1 + j * 32 * ROWB);
+            xi[j] = frag(st, ox0 + j * 32 * ROWB + PLANE, ox1 + j * 32 * ROWB + PLANE);
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const i32x8 wr = frag(st, ow0 + i * 32 * ROWB, ow1 + i * 32 * ROWB);
+            const i32x8 wi = frag(st, ow0 + i * 32 * ROWB + PLANE, ow1 + i * 32 * ROWB + PLANE);
+            const i32x8 wn = wi ^ (int)NEG;
+            const int sw = sreg[u][i];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int sx = sreg[u][2 + j];
+                acc.re[i][j] = mma(xr[j], wr, acc.re[i][j], sx, sw);
+                acc.im[i][j] = mma(xi[j], wr, acc.im[i][j], sx, sw);
+                acc.re[i][j] = mma(xi[j], wn, acc.re[i][j], sx, sw);
+                acc.im[i][j] = mma(xr[j], wi, acc.im[i][j], sx, sw);
+            }
+        }
+    };
+
+    // Ring: stage kt lives in buffer kt % NS; NS-1 stages are in flight.
+    constexpr int PER_STAGE = 2 * PIECES_PER_WAVE + (MX ? 4 : 0);  // loads per wave per stage
+    static_assert((NS - 2) * PER_STAGE < 64, "vmcnt range");
+    constexpr int kWaitRing = vmcnt_imm((NS - 2) * PER_STAGE), kWaitAll = vmcnt_imm(0);
+    const int nk = (Kp + BK - 1) / BK;
+    auto stage_step = [&](int kt, int u) {
+        if (kt + NS - 2 < nk) __builtin_amdgcn_s_waitcnt(kWaitRing);
+        else __builtin_amdgcn_s_waitcnt(kWaitAll);
+        // all waves' loads for stage kt landed, stage kt-1 fully read
+        asm volatile("s_barrier" ::: "memory");
+        if (kt + NS - 1 < nk) issue(bufs[(u + NS - 1) % NS], kt + NS - 1, (u + NS - 1) % NS);
+        compute(bufs[u], u);
+    };
+#pragma unroll
+    for (int s = 0; s < NS - 1; ++s)
+        if (s < nk) issue(bufs[s], s, s);
+    int kt0 = 0;
+    for (; kt0 + NS <= nk; kt0 += NS) {
+#pragma unroll
+        for (int u = 0; u < NS; ++u) stage_step(kt0 + u, u);
+    }
+#pragma unroll
+    for (int u = 0; u < NS - 1; ++u)
+        if (kt0 + u < nk) stage_step(kt0 + u, u);
+
+    if (!MX) {
+        // per-row scales: beams fw + 32 i, samples wn*64 + 32 j + 8 q + 4 hl + (0..3)
+        const float *as = (const float *)a_scale + (int64_t)cw * M;
+        const float *bs = (const float *)b_scale + (int64_t)c * N;
+        const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc((void *)as, 0, 4 * M, RSRC_FLAGS);
+        const __amdgpu_buffer_rsrc_t rb = __builtin_amdgcn_make_buffer_rsrc((void *)bs, 0, 4 * N, RSRC_FLAGS);
+        float sa[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int m = m0 + fw + 32 * i;
+            sa[i] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(ra, m < M ? (uint32_t)(4 * m) : OOB, 0, 0));
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int n = n0 + wn * 64 + 32 * j + 8 * q + 4 * hl;  // N % 4 == 0: all four or none
+                // whole-vector cast: a bit_cast of one subscripted element
+                // would not select that element
+                const f32x4 tb = __builtin_bit_cast(
+                    f32x4, __builtin_amdgcn_raw_buffer_load_b128(rb, n < N ? (uint32_t)(4 * n) : OOB, 0, 0));
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const float f = sa[i] * tb[e];
+                        acc.re[i][j][4 * q + e] *= f;
+                        acc.im[i][j][4 * q + e] *= f;
+                    }
+                }
+            }
+    }
+
+    // Epilogue through the (now idle) stage buffers.
+    constexpr int ROWS_PER_BUF = STAGE / staging_pitch<CIL>();
+    static_assert(ROWS_PER_BUF * 2 >= (CIL ? 64 : 128), "two stage buffers hold a staging round");
+    auto row_ptr = [&](int row) -> char * {
+        return (row < ROWS_PER_BUF ? lds0 : lds1) + (row % ROWS_PER_BUF) * staging_pitch<CIL>();
+    };
+    store_tile_staged<CIL>(acc, row_ptr, C + (int64_t)c * 2 * M * N, M, N, m0, n0, wave, lane);
+}
+
+typedef void (*F8Fn)(const uint8_t *, const uint8_t *, float *, const void *, const void *, int, int, int, int, int,
+                     int, int);
+
+F8Fn f8_fn(int v, bool cil, bool mx) {
+    if (mx) {
+        if (v == 2) return cil ? cgemm_f8_kernel<3, 1, 1> : cgemm_f8_kernel<3, 0, 1>;
+        return cil ? cgemm_f8_kernel<2, 1, 1> : cgemm_f8_kernel<2, 0, 1>;
+    }
+    if (v == 2) return cil ? cgemm_f8_kernel<3, 1, 0> : cgemm_f8_kernel<3, 0, 0>;
+    return cil ? cgemm_f8_kernel<2, 1, 0> : cgemm_f8_kernel<2, 0, 0>;
+}
+
+constexpr int kNumVariants = 2;  // 1: two-stage ring (default), 2: three-stage ring
+
+}  // namespace
+
+int64_t f8_kp(int64_t K) { return (K + 31) / 32 * 32; }
+
+bool f8_select(const Problem &p, int forced_variant, F8Config *cfg) {
+    int v = forced_variant == 0 ? 1 : forced_variant;
+    if (v < 1 || v > kNumVariants) return false;
+    if (p.N % 4 != 0) return false;
+    cfg->variant = v;
+    cfg->tile_m = BM;
+    cfg->tile_n = BN;
+    cfg->tile_k = BK;
+    cfg->threads = NT;
+    return true;
+}
+
+int64_t f8_workgroups(const Problem &p, const F8Config &cfg) {
+    return p.batch * ((p.M + cfg.tile_m - 1) / cfg.tile_m) * ((p.N + cfg.tile_n - 1) / cfg.tile_n);
+}
+
+const char *f8_kernel_name(const F8Config &) { return "cgemm_f8_kernel"; }
+
+hipError_t f8_launch(const Problem &p, const F8Config &cfg, bool mx, const void *A, const void *B, void *C,
+                     const void *a_scale, const void *b_scale, hipStream_t stream) {
+    const int tiles_m = (int)((p.M + BM - 1) / BM);
+    const int tiles_n = (int)((p.N + BN - 1) / BN);
+    const int64_t nblocks = p.batch * tiles_m * tiles_n;
+    F8Fn fn = f8_fn(cfg.variant, p.c_layout == TCBF_INTERLEAVED, mx);
+    hipLaunchKernelGGL(fn, dim3((uint32_t)nblocks), dim3(NT), 0, stream, (const uint8_t *)A, (const uint8_t *)B,
+                       (float *)C, a_scale, b_scale, (int)p.M, (int)p.N, (int)f8_kp(p.K), p.a_shared, tiles_m,
+                       tiles_n, (int)nblocks);
+    return hipGetLastError();
+}
+
+}  // namespace tcbf

@@ -1,6 +1,7 @@
 // C ABI of the beamforming library: plan creation (validation and kernel
 // choice, host only), execution (argument checks and one kernel launch), sign
-// packing.  No entry point throws, aborts or allocates device memory.
+// packing and FP8 quantisation.  No entry point throws, aborts or allocates
+// device memory.
 #include <new>
 #include <stdio.h>
 #include <string.h>
@@ -12,6 +13,7 @@ struct tcbf_plan_s {
     tcbf::Problem prob;
     tcbf::F16Config f16;
     tcbf::Int1Config int1;
+    tcbf::F8Config f8;
 };
 
 namespace {
@@ -21,6 +23,8 @@ constexpr int64_t kMaxIndex = (int64_t)1 << 31;  // per-launch workgroup limit
 
 bool is_layout(int32_t v) { return v == TCBF_PLANAR || v == TCBF_INTERLEAVED; }
 bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+bool is_f8(int32_t dtype) { return dtype == TCBF_F8_E4M3 || dtype == TCBF_MXF8_E4M3; }
+bool is_src_type(int32_t t) { return t == TCBF_SRC_I8 || t == TCBF_SRC_F16 || t == TCBF_SRC_F32; }
 
 tcbf_status device_check(int device) {
     int count = 0;
@@ -54,6 +58,13 @@ tcbf_status validate_desc(const tcbf_plan_desc *d) {
         // int32 accumulators hold 4 * 2K: keep K well inside that range
         if (d->K > ((int64_t)1 << 26)) return TCBF_ERROR_NOT_SUPPORTED;
         if (2 * d->M * d->N >= kMaxIndex) return TCBF_ERROR_NOT_SUPPORTED;
+    } else if (is_f8(d->dtype)) {
+        if (d->a_layout != TCBF_PLANAR || d->b_layout != TCBF_PLANAR) return TCBF_ERROR_INVALID_VALUE;
+        if (d->N % 4 != 0) return TCBF_ERROR_INVALID_VALUE;
+        // byte offsets of every per-channel operand and output fit 31 bits
+        const int64_t kp = tcbf::f8_kp(d->K);
+        if (2 * d->M * kp >= kMaxIndex || 2 * d->N * kp >= kMaxIndex || 8 * d->M * d->N >= kMaxIndex)
+            return TCBF_ERROR_NOT_SUPPORTED;
     } else {
         return TCBF_ERROR_INVALID_VALUE;
     }
@@ -95,6 +106,9 @@ tcbf_status tcbf_plan(const tcbf_plan_desc *desc, tcbf_plan_t *plan) {
     if (desc->dtype == TCBF_F16) {
         if (!tcbf::f16_select(p, desc->variant, &tmp.f16)) return TCBF_ERROR_INVALID_VALUE;
         wgs = tcbf::f16_workgroups(p, tmp.f16);
+    } else if (is_f8(desc->dtype)) {
+        if (!tcbf::f8_select(p, desc->variant, &tmp.f8)) return TCBF_ERROR_INVALID_VALUE;
+        wgs = tcbf::f8_workgroups(p, tmp.f8);
     } else {
         if (!tcbf::int1_select(p, desc->variant, &tmp.int1)) return TCBF_ERROR_INVALID_VALUE;
         wgs = tcbf::int1_workgroups(p, tmp.int1);
@@ -134,6 +148,18 @@ tcbf_status tcbf_plan_query(tcbf_plan_t plan, tcbf_plan_info *info) {
         r.workgroups = tcbf::f16_workgroups(p, plan->f16);
         r.algorithmic_bytes = 4.0 * nw * p.M * p.K + 4.0 * p.batch * p.K * p.N + 8.0 * p.batch * p.M * p.N;
         snprintf(r.kernel_name, sizeof(r.kernel_name), "%s", tcbf::f16_kernel_name(plan->f16));
+    } else if (is_f8(plan->desc.dtype)) {
+        const double kp = (double)tcbf::f8_kp(p.K);
+        r.variant = plan->f8.variant;
+        r.tile_m = plan->f8.tile_m;
+        r.tile_n = plan->f8.tile_n;
+        r.tile_k = plan->f8.tile_k;
+        r.threads = plan->f8.threads;
+        r.workgroups = tcbf::f8_workgroups(p, plan->f8);
+        // codes, scales (fp32 per row, or one byte per 32-receiver block), output
+        const double sa = plan->desc.dtype == TCBF_F8_E4M3 ? 4.0 : kp / 32.0;
+        r.algorithmic_bytes = (2.0 * kp + sa) * (nw * p.M + (double)p.batch * p.N) + 8.0 * p.batch * p.M * p.N;
+        snprintf(r.kernel_name, sizeof(r.kernel_name), "%s", tcbf::f8_kernel_name(plan->f8));
     } else {
         const double kw = (double)((p.K + 31) / 32);
         r.variant = plan->int1.variant;
@@ -149,16 +175,25 @@ tcbf_status tcbf_plan_query(tcbf_plan_t plan, tcbf_plan_info *info) {
     return TCBF_SUCCESS;
 }
 
-tcbf_status tcbf_execute(tcbf_plan_t plan, const void *A, const void *B, void *C, const float *a_scale,
-                         const float *b_scale, void *stream) {
+tcbf_status tcbf_execute(tcbf_plan_t plan, const void *A, const void *B, void *C, const void *a_scale,
+                         const void *b_scale, void *stream) {
     if (plan == nullptr || A == nullptr || B == nullptr || C == nullptr) return TCBF_ERROR_INVALID_VALUE;
-    if (a_scale != nullptr || b_scale != nullptr) return TCBF_ERROR_INVALID_VALUE;
+    const bool f8 = is_f8(plan->desc.dtype);
+    if (f8) {
+        if (a_scale == nullptr || b_scale == nullptr) return TCBF_ERROR_INVALID_VALUE;
+        if (!aligned16(a_scale) || !aligned16(b_scale)) return TCBF_ERROR_INVALID_VALUE;
+    } else if (a_scale != nullptr || b_scale != nullptr) {
+        return TCBF_ERROR_INVALID_VALUE;
+    }
     if (!aligned16(A) || !aligned16(B) || !aligned16(C)) return TCBF_ERROR_INVALID_VALUE;
     tcbf_status st = current_device_is(plan->desc.device);
     if (st != TCBF_SUCCESS) return st;
     hipError_t e;
     if (plan->desc.dtype == TCBF_F16) {
         e = tcbf::f16_launch(plan->prob, plan->f16, A, B, C, (hipStream_t)stream);
+    } else if (f8) {
+        e = tcbf::f8_launch(plan->prob, plan->f8, plan->desc.dtype == TCBF_MXF8_E4M3, A, B, C, a_scale, b_scale,
+                            (hipStream_t)stream);
     } else {
         e = tcbf::int1_launch(plan->prob, plan->int1, (const uint32_t *)A, (const uint32_t *)B, (int32_t *)C,
                               (hipStream_t)stream);
@@ -169,8 +204,7 @@ tcbf_status tcbf_execute(tcbf_plan_t plan, const void *A, const void *B, void *C
 tcbf_status tcbf_pack1bit(const void *src, int32_t src_type, int32_t src_layout, int64_t batch, int64_t rows,
                           int64_t K, int32_t src_k_major, uint32_t *dst, void *stream) {
     if (src == nullptr || dst == nullptr) return TCBF_ERROR_INVALID_VALUE;
-    if (src_type != TCBF_SRC_I8 && src_type != TCBF_SRC_F16 && src_type != TCBF_SRC_F32)
-        return TCBF_ERROR_INVALID_VALUE;
+    if (!is_src_type(src_type)) return TCBF_ERROR_INVALID_VALUE;
     if (!is_layout(src_layout)) return TCBF_ERROR_INVALID_VALUE;
     if (batch < 1 || rows < 1 || K < 1) return TCBF_ERROR_INVALID_VALUE;
     if (!aligned16(src) || !aligned16(dst)) return TCBF_ERROR_INVALID_VALUE;
@@ -179,6 +213,21 @@ tcbf_status tcbf_pack1bit(const void *src, int32_t src_type, int32_t src_layout,
     if (threads / 256 + 1 >= kMaxIndex) return TCBF_ERROR_NOT_SUPPORTED;
     hipError_t e = tcbf::pack1bit_launch(src, src_type, src_layout, batch, rows, K, src_k_major != 0, dst,
                                          (hipStream_t)stream);
+    return e == hipSuccess ? TCBF_SUCCESS : TCBF_ERROR_DEVICE;
+}
+
+tcbf_status tcbf_quantize_e4m3(const void *src, int32_t src_type, int32_t src_layout, int64_t batch, int64_t rows,
+                               int64_t K, int32_t src_k_major, int32_t block, uint8_t *dst, void *scales,
+                               void *stream) {
+    if (src == nullptr || dst == nullptr || scales == nullptr) return TCBF_ERROR_INVALID_VALUE;
+    if (!is_src_type(src_type) || !is_layout(src_layout)) return TCBF_ERROR_INVALID_VALUE;
+    if (block != 0 && block != 32) return TCBF_ERROR_INVALID_VALUE;
+    if (batch < 1 || rows < 1 || K < 1) return TCBF_ERROR_INVALID_VALUE;
+    if (!aligned16(src) || !aligned16(dst) || !aligned16(scales)) return TCBF_ERROR_INVALID_VALUE;
+    if (tcbf::quantize_e4m3_tiles(batch, rows, K) >= kMaxIndex || batch * rows / 256 + 1 >= kMaxIndex)
+        return TCBF_ERROR_NOT_SUPPORTED;
+    hipError_t e = tcbf::quantize_e4m3_launch(src, src_type, src_layout, batch, rows, K, src_k_major != 0, block,
+                                              dst, scales, (hipStream_t)stream);
     return e == hipSuccess ? TCBF_SUCCESS : TCBF_ERROR_DEVICE;
 }
 

@@ -28,6 +28,25 @@ const char *f16_kernel_name(const F16Config &cfg);
 hipError_t f16_launch(const Problem &p, const F16Config &cfg, const void *A, const void *B,
                       void *C, hipStream_t stream);
 
+// FP8 modes (e4m3 codes in, fp32 out): per-row fp32 scales or per-32-block
+// E8M0 scales (mx).  Operands are receiver-contiguous with row pitch f8_kp(K).
+struct F8Config {
+    int variant;  // 1 = two-stage ring, 2 = three-stage ring
+    int tile_m, tile_n, tile_k, threads;
+};
+int64_t f8_kp(int64_t K);
+bool f8_select(const Problem &p, int forced_variant, F8Config *cfg);
+int64_t f8_workgroups(const Problem &p, const F8Config &cfg);
+const char *f8_kernel_name(const F8Config &cfg);
+hipError_t f8_launch(const Problem &p, const F8Config &cfg, bool mx, const void *A, const void *B, void *C,
+                     const void *a_scale, const void *b_scale, hipStream_t stream);
+
+// e4m3 quantisation (block 0: per-row fp32 scales, 32: per-block E8M0).
+int64_t quantize_e4m3_tiles(int64_t batch, int64_t rows, int64_t K);
+hipError_t quantize_e4m3_launch(const void *src, int src_type, int src_layout, int64_t batch, int64_t rows,
+                                int64_t K, int src_k_major, int block, uint8_t *dst, void *scales,
+                                hipStream_t stream);
+
 // 1-bit mode (packed sign bits in, int32 out).
 struct Int1Config {
     int variant;  // 1 = int8 MFMA on unpacked bits, 2 = VALU xor/popcount

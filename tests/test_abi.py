@@ -65,6 +65,9 @@ def _plan_status(**kw):
     dict(a_layout=2), dict(b_layout=-1), dict(c_layout=5), dict(variant=-1), dict(variant=9),
     dict(dtype=tcbf.INT1, a_layout=tcbf.INTERLEAVED), dict(dtype=tcbf.INT1, b_layout=tcbf.INTERLEAVED),
     dict(dtype=tcbf.INT1, variant=7),
+    dict(dtype=tcbf.F8_E4M3, a_layout=tcbf.INTERLEAVED), dict(dtype=tcbf.MXF8_E4M3, b_layout=tcbf.INTERLEAVED),
+    dict(dtype=tcbf.F8_E4M3, N=6), dict(dtype=tcbf.MXF8_E4M3, N=1), dict(dtype=tcbf.F8_E4M3, variant=3),
+    dict(dtype=4),
 ])
 def test_bad_descriptors_rejected_without_device(bad):
     assert _plan_status(**bad) == 1
@@ -73,6 +76,8 @@ def test_bad_descriptors_rejected_without_device(bad):
 def test_oversized_rejected():
     assert _plan_status(M=1 << 20, K=1 << 12) == 2
     assert _plan_status(dtype=tcbf.INT1, K=(1 << 26) + 1) == 2
+    assert _plan_status(dtype=tcbf.F8_E4M3, M=1 << 14, K=1 << 16) == 2   # 2*M*Kp bytes
+    assert _plan_status(dtype=tcbf.MXF8_E4M3, M=1 << 14, N=1 << 14) == 2  # 8*M*N bytes
 
 
 def test_null_arguments():
@@ -83,6 +88,7 @@ def test_null_arguments():
     assert L.tcbf_plan_query(None, None) == 1
     assert L.tcbf_plan_destroy(None) == 0
     assert L.tcbf_pack1bit(None, 0, 0, 1, 1, 1, 1, None, None) == 1
+    assert L.tcbf_quantize_e4m3(None, 0, 0, 1, 1, 1, 1, 0, None, None, None) == 1
 
 
 def test_pack_argument_checks():
@@ -98,6 +104,20 @@ def test_pack_argument_checks():
     assert L.tcbf_pack1bit(p, 0, 0, 1, 1, 0, 1, p, None) == 1       # K 0
     q = ctypes.c_void_p(addr + 4)
     assert L.tcbf_pack1bit(q, 0, 0, 1, 1, 1, 1, p, None) == 1       # misaligned
+
+
+def test_quantize_argument_checks():
+    L = tcbf.lib()
+    buf = ctypes.create_string_buffer(256)
+    addr = (ctypes.addressof(buf) + 15) & ~15
+    p = ctypes.c_void_p(addr)
+    assert L.tcbf_quantize_e4m3(p, 9, 0, 1, 1, 1, 1, 0, p, p, None) == 1     # bad source type
+    assert L.tcbf_quantize_e4m3(p, 1, 2, 1, 1, 1, 1, 0, p, p, None) == 1     # bad layout
+    assert L.tcbf_quantize_e4m3(p, 1, 0, 1, 1, 1, 1, 16, p, p, None) == 1    # bad block
+    assert L.tcbf_quantize_e4m3(p, 1, 0, 1, 0, 1, 1, 0, p, p, None) == 1     # rows 0
+    assert L.tcbf_quantize_e4m3(p, 1, 0, 1, 1, 1, 1, 0, p, None, None) == 1  # no scales
+    q = ctypes.c_void_p(addr + 4)
+    assert L.tcbf_quantize_e4m3(p, 1, 0, 1, 1, 1, 1, 32, p, q, None) == 1    # misaligned scales
 
 
 def test_valid_descriptor_without_gpu_reports_device():

@@ -1,0 +1,379 @@
+"""GPU parity of the FP8 (e4m3) path against the oracle (through the C ABI).
+
+* The quantiser is integer work: codes and scales must equal the oracle's
+  bit for bit (per-row fp32 scales compared as bit patterns).
+* The product is compared with the FP64 oracle evaluated on the dequantised
+  inputs (decode each code exactly, times its scale): relative Frobenius error
+  <= 3e-2 per channel (the stated FP8 tolerance) and, per element,
+      |gpu - oracle| <= (2^-9 + 2 gamma(2K) + 4u) * sum_k |w_k| |x_k|.
+  Products of e4m3 values and power-of-two scales are exact.  The FP8 matrix
+  instruction sums its products in groups of 8, dropping bits more than about
+  13 binades below the group's leading product (measured), so a group loses
+  at most 8 * 2^-13 = 2^-10 of its largest |product| (2^-9: twice that);
+  the group sums accumulate in fp32 (2 gamma(2K)); the per-row epilogue
+  adds two fp32 roundings (4u).
+* The error against the unquantised inputs is the quantisation error itself;
+  it is logged per result and bounded loosely.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+from gpu_util import U32, c_inter_to_complex, c_planar_to_complex, gamma, log, rel_fro, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_2505_03269_amd as tcbf  # noqa: E402
+
+REL_FRO_F8 = 3e-2
+TORCH_TYPES = {"i8": torch.int8, "f16": torch.float16, "f32": torch.float32}
+NP_TYPES = {"i8": np.int8, "f16": np.float16, "f32": np.float32}
+
+
+# --------------------------------------------------------------------------
+# helpers
+# --------------------------------------------------------------------------
+
+def planes_of(src, k_major, layout):
+    """Host source array -> list over batch of (re, im) fp32 [rows, K]."""
+    out = []
+    for b in range(src.shape[0]):
+        s = src[b].astype(np.float32)
+        if layout == tcbf.PLANAR:
+            re, im = s[0], s[1]
+        else:
+            re, im = s[..., 0], s[..., 1]
+        if not k_major:
+            re, im = re.T, im.T
+        out.append((np.ascontiguousarray(re), np.ascontiguousarray(im)))
+    return out
+
+
+def quant_expected(src, k_major, layout, block):
+    """Oracle codes [batch, 2, rows, Kp] (zero padded) and scales."""
+    pl = planes_of(src, k_major, layout)
+    rows, K = pl[0][0].shape
+    kp = tcbf.f8_kp(K)
+    codes = np.zeros((len(pl), 2, rows, kp), np.uint8)
+    scales = []
+    for b, (re, im) in enumerate(pl):
+        if block == 0:
+            qr, qi, sc = oracle.quantize_e4m3_rows(re, im)
+        else:
+            qr, qi, sc = oracle.quantize_e4m3_blocks(re, im)
+            pad = np.full((rows, kp // 32), 127, np.uint8)
+            pad[:, :sc.shape[1]] = sc
+            sc = pad
+        codes[b, 0, :, :K] = qr
+        codes[b, 1, :, :K] = qi
+        scales.append(sc)
+    return codes, np.stack(scales)
+
+
+def dequant(codes, scales, block, K):
+    """codes [nb, 2, rows, Kp], scales -> complex128 [nb, rows, K] (exact)."""
+    d = oracle.e4m3_decode(codes[..., :K])
+    if block == 0:
+        s = np.asarray(scales, np.float64)[:, None, :, None]
+    else:
+        s = np.repeat(oracle.e8m0_decode(scales), 32, axis=2)[:, None, :, :K]
+    d = d * s
+    return d[:, 0] + 1j * d[:, 1]
+
+
+def gpu_quantize(src_np, k_major, layout, block):
+    src = to_dev(src_np)
+    codes, scales = tcbf.quantize_e4m3(src, k_major=k_major, layout=layout, block=block)
+    torch.cuda.synchronize()
+    return codes, scales
+
+
+def run_f8(Wq, Ws, Xq, Xs, dtype, c_layout=tcbf.PLANAR, shared=False, variant=0):
+    """Device codes/scales -> complex128 [batch, M, N]."""
+    batch, _, N, kp = Xq.shape
+    M = Wq.shape[2]
+    K = kp  # the padded tail is zero; the plan only needs a K with the same Kp
+    plan = tcbf.Plan(batch, M, N, K, dtype, c_layout=c_layout, a_shared=shared, variant=variant)
+    C = plan.empty_output()
+    plan.execute(Wq, Xq, C, Ws, Xs)
+    torch.cuda.synchronize()
+    Ch = C.cpu().numpy()
+    return c_planar_to_complex(Ch) if c_layout == tcbf.PLANAR else c_inter_to_complex(Ch)
+
+
+def check_f8(got, Wd, Xd, K, shared=False):
+    """Wd [nb, M, K], Xd [batch, N, K] dequantised complex."""
+    Xk = np.ascontiguousarray(Xd.transpose(0, 2, 1))
+    Wk = Wd[0] if shared else Wd
+    ref = oracle.cgemm(Wk, Xk)
+    absdot = np.matmul(np.abs(Wk), np.abs(Xk))
+    for c in range(ref.shape[0]):
+        r = rel_fro(got[c], ref[c]) if np.linalg.norm(ref[c]) > 0 else float(np.abs(got[c]).max())
+        assert r <= REL_FRO_F8, "channel %d: rel Frobenius %.3e" % (c, r)
+    bound = (2.0 ** -9 + 2.0 * gamma(2 * K) + 4 * U32) * absdot
+    err = np.maximum(np.abs(got.real - ref.real), np.abs(got.imag - ref.imag))
+    assert np.all(err <= bound), "elementwise bound violated: worst ratio %.3f" % float(np.max(err / np.maximum(bound, 1e-300)))
+    return ref
+
+
+def random_source(seed, shape, kind, scale=3.0):
+    g = np.random.default_rng(np.random.SeedSequence([3000, seed] + list(shape)))
+    v = g.normal(0.0, scale, shape) * np.exp(g.uniform(-3, 3, shape[:-1] + (1,)))
+    if kind == "i8":
+        return np.clip(np.rint(v * 10), -128, 127).astype(np.int8)
+    return v.astype(NP_TYPES[kind])
+
+
+def src_shape(batch, rows, K, k_major, layout):
+    if layout == tcbf.PLANAR:
+        return (batch, 2, rows, K) if k_major else (batch, 2, K, rows)
+    return (batch, rows, K, 2) if k_major else (batch, K, rows, 2)
+
+
+# --------------------------------------------------------------------------
+# quantiser
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("block", [0, 32])
+@pytest.mark.parametrize("k_major", [True, False])
+@pytest.mark.parametrize("layout", [tcbf.PLANAR, tcbf.INTERLEAVED])
+@pytest.mark.parametrize("kind", ["i8", "f16", "f32"])
+def test_quantiser_bit_exact(kind, layout, k_major, block):
+    batch, rows, K = 2, 70, 77
+    src = random_source(1, src_shape(batch, rows, K, k_major, layout), kind)
+    log("quantise %s layout=%d k_major=%d block=%d" % (kind, layout, k_major, block))
+    codes, scales = gpu_quantize(src, k_major, layout, block)
+    ecodes, escales = quant_expected(src, k_major, layout, block)
+    assert np.array_equal(codes.cpu().numpy(), ecodes)
+    s = scales.cpu().numpy()
+    if block == 0:
+        assert np.array_equal(s.view(np.uint32), escales.astype(np.float32).view(np.uint32))
+    else:
+        assert np.array_equal(s, escales)
+
+
+@pytest.mark.parametrize("block", [0, 32])
+@pytest.mark.parametrize("k_major", [True, False])
+def test_quantiser_special_values(k_major, block):
+    """Nearest-even ties (normal and subnormal), saturation, signed zeros, NaN
+    (ignored by the maximum, coded 0x7f) and a row holding infinity."""
+    rows, K = 6, 64
+    re = np.zeros((rows, K), np.float32)
+    im = np.zeros((rows, K), np.float32)
+    re[0, 0] = 448.0                                   # pins amax (scale 1 / exponent 0)
+    re[0, 1:9] = [1.0625, 1.1875, 17.0, 19.0, 2.0 ** -10, 3 * 2.0 ** -10, 15 * 2.0 ** -11, 440.0]
+    im[0, 0:4] = [-0.0, -1.0625, -2.0 ** -12, 0.0]
+    re[1, :] = np.float32(np.nan)
+    re[1, 3] = 5.0                                     # amax 5 despite the NaNs
+    im[2, 7] = np.inf
+    im[2, 8] = -2.5
+    re[3, 33] = -1e-30                                 # tiny block
+    re[4, :] = 7.0                                     # all equal
+    # row 5 stays zero
+    src = np.stack([re, im])[None]
+    if not k_major:
+        src = np.ascontiguousarray(src.transpose(0, 1, 3, 2))
+    codes, scales = gpu_quantize(src, k_major, tcbf.PLANAR, block)
+    ecodes, escales = quant_expected(src, k_major, tcbf.PLANAR, block)
+    assert np.array_equal(codes.cpu().numpy(), ecodes)
+    s = scales.cpu().numpy()
+    if block == 0:
+        assert np.array_equal(s.view(np.uint32), escales.astype(np.float32).view(np.uint32))
+    else:
+        assert np.array_equal(s, escales)
+
+
+@pytest.mark.parametrize("block", [0, 32])
+def test_quantiser_larger_ragged(block):
+    for k_major in (True, False):
+        src = random_source(2, src_shape(1, 1000, 1000, k_major, tcbf.PLANAR), "f16")
+        codes, scales = gpu_quantize(src, k_major, tcbf.PLANAR, block)
+        ecodes, escales = quant_expected(src, k_major, tcbf.PLANAR, block)
+        assert np.array_equal(codes.cpu().numpy(), ecodes)
+        if block == 0:
+            assert np.array_equal(scales.cpu().numpy().view(np.uint32), escales.astype(np.float32).view(np.uint32))
+        else:
+            assert np.array_equal(scales.cpu().numpy(), escales)
+
+
+# --------------------------------------------------------------------------
+# product
+# --------------------------------------------------------------------------
+
+F8_SHAPES = [
+    (1, 1, 4, 1), (2, 200, 132, 77), (1, 129, 260, 576), (3, 64, 64, 32), (1, 300, 128, 2080),
+    (2, 128, 128, 200), (1, 33, 500, 96), (1, 256, 256, 8192),
+]
+
+
+def f8_case(seed, batch, M, N, K, block, shared=False):
+    """Random fp16 operands quantised on the GPU (the quantiser is checked
+    above).  Returns device codes/scales, host copies and dequantised values."""
+    nw = 1 if shared else batch
+    W = random_source(seed, (nw, 2, M, K), "f16", 1.0)
+    X = random_source(seed + 1, (batch, 2, K, N), "f16", 30.0)
+    Wq, Ws = gpu_quantize(W, True, tcbf.PLANAR, block)
+    Xq, Xs = gpu_quantize(X, False, tcbf.PLANAR, block)
+    Wd = dequant(Wq.cpu().numpy(), Ws.cpu().numpy(), block, K)
+    Xd = dequant(Xq.cpu().numpy(), Xs.cpu().numpy(), block, K)
+    return (Wq, Ws, Xq, Xs), (W, X), (Wd, Xd)
+
+
+@pytest.mark.parametrize("batch,M,N,K", F8_SHAPES)
+@pytest.mark.parametrize("dtype", [tcbf.F8_E4M3, tcbf.MXF8_E4M3])
+def test_gemm_vs_dequantised_oracle(dtype, batch, M, N, K):
+    block = 0 if dtype == tcbf.F8_E4M3 else 32
+    log("f8 gemm dtype=%d batch=%d M=%d N=%d K=%d" % (dtype, batch, M, N, K))
+    dev, host, deq = f8_case(10, batch, M, N, K, block)
+    got = run_f8(*dev, dtype)
+    check_f8(got, deq[0], deq[1], K)
+
+
+@pytest.mark.parametrize("dtype", [tcbf.F8_E4M3, tcbf.MXF8_E4M3])
+def test_gemm_layouts_shared_variants(dtype):
+    """Interleaved output and both ring depths agree bitwise with the planar
+    default; a shared W matches the oracle."""
+    block = 0 if dtype == tcbf.F8_E4M3 else 32
+    batch, M, N, K = 2, 160, 136, 300
+    dev, host, deq = f8_case(20, batch, M, N, K, block)
+    base = run_f8(*dev, dtype)
+    check_f8(base, deq[0], deq[1], K)
+    inter = run_f8(*dev, dtype, c_layout=tcbf.INTERLEAVED)
+    v2 = run_f8(*dev, dtype, variant=2)
+    assert np.array_equal(base, inter) and np.array_equal(base, v2)
+    dev, host, deq = f8_case(21, batch, M, N, K, block, shared=True)
+    got = run_f8(*dev, dtype, shared=True)
+    check_f8(got, deq[0], deq[1], K, shared=True)
+
+
+def test_gemm_exact_small_integers():
+    """Codes of small integers with power-of-two scales: every product and
+    partial sum is exact in fp32, so the result equals the oracle exactly."""
+    g = np.random.default_rng(7)
+    batch, M, N, K = 2, 96, 68, 256
+    kp = tcbf.f8_kp(K)
+    ints = np.arange(-8, 9, dtype=np.float32)
+    Wv = g.choice(ints[4:13], (batch, 2, M, kp)).astype(np.float32)  # -4..4
+    Xv = g.choice(ints, (batch, 2, N, kp)).astype(np.float32)        # -8..8
+    Wc = torch.from_numpy(Wv).to(torch.float8_e4m3fn).view(torch.uint8).numpy()
+    Xc = torch.from_numpy(Xv).to(torch.float8_e4m3fn).view(torch.uint8).numpy()
+    assert np.array_equal(oracle.e4m3_decode(Wc), Wv)  # the integers are exact codes
+    # per-row: power-of-two fp32 scales
+    ws = np.ldexp(1.0, g.integers(-3, 4, (batch, M))).astype(np.float32)
+    xs = np.ldexp(1.0, g.integers(-3, 4, (batch, N))).astype(np.float32)
+    got = run_f8(to_dev(Wc), to_dev(ws), to_dev(Xc), to_dev(xs), tcbf.F8_E4M3)
+    Wd, Xd = dequant(Wc, ws, 0, K), dequant(Xc, xs, 0, K)
+    ref = oracle.cgemm(Wd, np.ascontiguousarray(Xd.transpose(0, 2, 1)))
+    assert np.array_equal(got, ref)
+    # per-block: E8M0 codes 2^-1..2^1, so every product of a group of 8 lies
+    # within 2^-2..2^7 and the instruction's group sums stay exact
+    wsb = g.integers(126, 129, (batch, M, kp // 32)).astype(np.uint8)
+    xsb = g.integers(126, 129, (batch, N, kp // 32)).astype(np.uint8)
+    got = run_f8(to_dev(Wc), to_dev(wsb), to_dev(Xc), to_dev(xsb), tcbf.MXF8_E4M3)
+    Wd, Xd = dequant(Wc, wsb, 32, K), dequant(Xc, xsb, 32, K)
+    ref = oracle.cgemm(Wd, np.ascontiguousarray(Xd.transpose(0, 2, 1)))
+    assert np.array_equal(got, ref)
+
+
+def test_block_scales_apply_per_block():
+    """One nonzero block per row with a distinct exponent: each block's scale
+    must land on its own 32 receivers (a wrong block-to-lane mapping moves the
+    scale onto another block and changes the result)."""
+    batch, M, N, K = 1, 64, 64, 256
+    kp = tcbf.f8_kp(K)
+    nb = kp // 32
+    Wc = np.zeros((batch, 2, M, kp), np.uint8)
+    Xc = np.zeros((batch, 2, N, kp), np.uint8)
+    for m in range(M):
+        b = m % nb
+        Wc[0, 0, m, 32 * b:32 * b + 32] = 0x38  # 1.0
+    Xc[0, 0] = 0x38
+    Xc[0, 1] = 0x40                               # 2.0
+    ws = np.zeros((batch, M, nb), np.uint8) + 127
+    for m in range(M):
+        ws[0, m, :] = 127 + np.arange(nb) - 3     # distinct exponent per block
+    xs = np.full((batch, N, nb), 127, np.uint8)
+    got = run_f8(to_dev(Wc), to_dev(ws), to_dev(Xc), to_dev(xs), tcbf.MXF8_E4M3)
+    Wd, Xd = dequant(Wc, ws, 32, K), dequant(Xc, xs, 32, K)
+    ref = oracle.cgemm(Wd, np.ascontiguousarray(Xd.transpose(0, 2, 1)))
+    assert np.array_equal(got, ref)
+    # row m: 32 receivers of value 2^(b-3), times (1 + 2i)
+    expect = 32.0 * np.ldexp(1.0, (np.arange(M) % nb) - 3)
+    assert np.array_equal(got[0, :, 0].real, expect) and np.array_equal(got[0, :, 0].imag, 2 * expect)
+
+
+def test_rejects_bad_scales():
+    plan = tcbf.Plan(1, 32, 32, 32, tcbf.F8_E4M3)
+    A = torch.zeros(plan.shape_a(), dtype=torch.uint8, device="cuda:0")
+    B = torch.zeros(plan.shape_b(), dtype=torch.uint8, device="cuda:0")
+    sa = torch.ones(plan.shape_a_scale(), dtype=torch.float32, device="cuda:0")
+    sb = torch.ones(plan.shape_b_scale(), dtype=torch.float32, device="cuda:0")
+    C = plan.empty_output()
+    lib = tcbf.lib()
+    import ctypes
+    p = lambda t: ctypes.c_void_p(t.data_ptr())  # noqa: E731
+    s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    assert lib.tcbf_execute(plan._h, p(A), p(B), p(C), None, p(sb), s) == 1
+    assert lib.tcbf_execute(plan._h, p(A), p(B), p(C), p(sa), None, s) == 1
+    assert lib.tcbf_execute(plan._h, p(A), p(B), p(C), ctypes.c_void_p(sa.data_ptr() + 4), p(sb), s) == 1
+    assert lib.tcbf_execute(plan._h, p(A), p(B), p(C), p(sa), p(sb), s) == 0
+    f16 = tcbf.Plan(1, 32, 32, 32, tcbf.F16)
+    A16 = torch.zeros(f16.shape_a(), dtype=torch.float16, device="cuda:0")
+    B16 = torch.zeros(f16.shape_b(), dtype=torch.float16, device="cuda:0")
+    assert lib.tcbf_execute(f16._h, p(A16), p(B16), p(C), p(sa), p(sb), s) == 1
+    torch.cuda.synchronize()
+
+
+# --------------------------------------------------------------------------
+# config 4 (ultrasound, 1 x 32768 x 8192 x 256) at full size
+# --------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def c4_inputs():
+    log("c4 fp8: generating inputs")
+    W, X = wl.c4_channel(0)
+    return W[None], X[None]
+
+
+@pytest.mark.parametrize("dtype", [tcbf.F8_E4M3, tcbf.MXF8_E4M3])
+def test_c4_full_size_sampled(c4_inputs, dtype):
+    """Quantise W and X on the GPU, run the plan the benchmark times, then
+    check sampled W rows' codes against the oracle quantiser and every output
+    of 48 sampled beams (plus the first and last) against the FP64 oracle on
+    the dequantised inputs.  The error against the unquantised inputs is
+    logged as the stated accuracy of the mode."""
+    W, X = c4_inputs
+    cfg = wl.CONFIGS[4]
+    M, N, K = cfg["M"], cfg["N"], cfg["K"]
+    block = 0 if dtype == tcbf.F8_E4M3 else 32
+    log("c4 fp8 dtype=%d: quantise + execute" % dtype)
+    Wq, Ws = gpu_quantize(W, True, tcbf.PLANAR, block)
+    Xq, Xs = gpu_quantize(X, False, tcbf.PLANAR, block)
+    plan = tcbf.Plan(1, M, N, K, dtype)
+    C = plan.empty_output()
+    plan.execute(Wq, Xq, C, Ws, Xs)
+    torch.cuda.synchronize()
+    g = np.random.default_rng(11)
+    ms = np.unique(np.concatenate([[0, M - 1], g.choice(M, 48, replace=False)]))
+    Wq_s = Wq[:, :, torch.from_numpy(ms).cuda()].cpu().numpy()
+    Ws_s = Ws[:, torch.from_numpy(ms).cuda()].cpu().numpy()
+    Xq_h, Xs_h = Xq.cpu().numpy(), Xs.cpu().numpy()
+    # quantiser parity on the sampled rows and on all of X
+    sub = np.ascontiguousarray(W[:, :, ms])
+    ec, es = quant_expected(sub, True, tcbf.PLANAR, block)
+    assert np.array_equal(Wq_s, ec)
+    assert np.array_equal(Ws_s.view(np.uint8), es.astype(Ws_s.dtype).view(np.uint8))
+    ec, es = quant_expected(X, False, tcbf.PLANAR, block)
+    assert np.array_equal(Xq_h, ec)
+    # product parity on the sampled beams
+    got = c_planar_to_complex(C[:, :, torch.from_numpy(ms).cuda()].cpu().numpy())
+    Wd = dequant(Wq_s, Ws_s, block, K)
+    Xd = dequant(Xq_h, Xs_h, block, K)
+    ref = check_f8(got, Wd, Xd, K)
+    # stated accuracy: against the unquantised fp16 inputs
+    exact = oracle.cgemm(wl.planar_to_complex(sub), wl.planar_to_complex(X))
+    log("c4 fp8 dtype=%d: rel Frobenius vs dequantised %.3e, vs unquantised %.3e"
+        % (dtype, rel_fro(got, ref), rel_fro(got, exact)))
+    assert rel_fro(got, exact) < 6e-2

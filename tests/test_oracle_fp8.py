@@ -73,3 +73,64 @@ def test_quantiser_scale_and_error_bound():
     # the element of largest magnitude maps to +-448 exactly
     big = np.maximum(np.abs(oracle.e4m3_decode(qr)).max(1), np.abs(oracle.e4m3_decode(qi)).max(1))
     assert np.all(big[rows] == 448.0)
+
+
+# --------------------------------------------------------------------------
+# per-32-block quantiser (power-of-two E8M0 scales)
+# --------------------------------------------------------------------------
+
+def test_block_exponent_hand_values():
+    """amax 448 needs no scaling; just above it needs 2^1; 1.75 = 448 * 2^-8
+    sits exactly on a boundary; an all-zero block gets 2^0."""
+    cases = [(448.0, 0), (449.0, 1), (1.75, -8), (1.76, -7), (1.0, -8), (0.5, -9), (896.0, 1), (896.5, 2),
+             (0.0, 0), (3.0e38, 120)]
+    re = np.zeros((len(cases), 32), np.float32)
+    im = np.zeros((len(cases), 32), np.float32)
+    for r, (a, _) in enumerate(cases):
+        im[r, 5] = -a  # the maximum may come from either part and either sign
+    _, _, codes = oracle.quantize_e4m3_blocks(re, im)
+    assert [int(c) - 127 for c in codes[:, 0]] == [e for _, e in cases]
+
+
+def test_block_exponent_is_minimal():
+    g = np.random.default_rng(4)
+    mag = np.exp(g.uniform(-30, 30, (64, 96))).astype(np.float32)
+    re = (mag * np.sign(g.normal(size=mag.shape))).astype(np.float32)
+    im = np.roll(re, 7, axis=1)
+    _, _, codes = oracle.quantize_e4m3_blocks(re, im)
+    e = codes.astype(np.int64) - 127
+    for b in range(3):
+        blk = slice(32 * b, 32 * b + 32)
+        amax = np.maximum(np.abs(re[:, blk]).max(1), np.abs(im[:, blk]).max(1)).astype(np.float64)
+        assert np.all(amax <= 448.0 * np.ldexp(1.0, e[:, b]))
+        assert np.all(amax > 448.0 * np.ldexp(1.0, e[:, b] - 1))
+
+
+def test_block_codes_match_torch_cast():
+    """Once the exponent is known the codes are a plain nearest-even cast of
+    x * 2^-e, which torch implements independently.  cols = 77: a ragged last
+    block of 13 receivers."""
+    g = np.random.default_rng(5)
+    re = (g.normal(0, 1, (40, 77)) * np.exp(g.uniform(-8, 8, (40, 1)))).astype(np.float32)
+    im = (g.normal(0, 1, (40, 77)) * np.exp(g.uniform(-8, 8, (40, 1)))).astype(np.float32)
+    re[3, 40:] = 0.0
+    im[3, 40:] = 0.0  # an all-zero third block
+    qr, qi, codes = oracle.quantize_e4m3_blocks(re, im)
+    assert codes.shape == (40, 3) and codes[3, 2] == 127
+    e = np.repeat(codes.astype(np.int64) - 127, 32, axis=1)[:, :77]
+    for v, q in ((re, qr), (im, qi)):
+        y = np.ldexp(v.astype(np.float64), -e).astype(np.float32)
+        ref = torch.from_numpy(y).to(torch.float8_e4m3fn).view(torch.uint8).numpy()
+        assert np.array_equal(q, ref)
+
+
+def test_block_quantiser_error_bound():
+    g = np.random.default_rng(6)
+    re = g.normal(0, 50.0, (30, 128)).astype(np.float32)
+    im = g.normal(0, 50.0, (30, 128)).astype(np.float32)
+    qr, qi, codes = oracle.quantize_e4m3_blocks(re, im)
+    s = np.repeat(oracle.e8m0_decode(codes), 32, axis=1)
+    for v, q in ((re, qr), (im, qi)):
+        d = oracle.e4m3_decode(q) * s
+        tol = np.maximum(np.abs(v) * 2.0 ** -4, 2.0 ** -10 * s) * (1 + 1e-9)
+        assert np.all(np.abs(d - v) <= tol)
