@@ -8,8 +8,9 @@ M=1024 beams, K=576 receivers, N=4096 samples, fp16 in, fp32 complex out),
 inputs resident in HBM.  Throughput is counted as 8 useful ops per complex
 multiply-accumulate on the unpadded sizes.  The per-launch kernel time comes
 from HIP events on the stream the library launches on (torch's current
-stream).  Prints ONE JSON line; secondary workloads (1-bit, sign packing,
-ultrasound shape in fp16 and FP8) ride along in its "secondary" list.
+stream).  Prints ONE JSON line; secondary workloads (1-bit, steering weights,
+sign packing, ultrasound shape in fp16 and FP8) ride along in its "secondary"
+list.
 """
 import argparse
 import hashlib
@@ -163,6 +164,22 @@ def bench_secondary(steps):
                     "roofline": {"bound": bound, "achieved": round(tops, 1), "peak": round(peak, 1),
                                  "unit": "TOP/s", "frac": round(tops / peak, 4)}})
         del C
+    # steering weights of the radio-astronomy geometry on the GPU (FP64 phases,
+    # fp16 planar out): 256 channels x 1024 beams x 576 antennas
+    ax, ay, bl, bm = wl.c2_geometry()
+    pos = torch.from_numpy(np.column_stack([ax, ay, np.zeros_like(ax)])).to("cuda:0")
+    dirs = torch.from_numpy(np.column_stack([bl, bm, np.zeros_like(bl)])).to("cuda:0")
+    freqs = torch.tensor([wl.c2_frequency(c) for c in range(256)], dtype=torch.float64, device="cuda:0")
+    Wst = torch.empty((256, 2, 1024, 576), dtype=torch.float16, device="cuda:0")
+    ms = time_launches(lambda: tcbf.steering_weights(pos, dirs, freqs, wl.C0, out=Wst), st, 1)
+    nbytes = Wst.numel() * 2 + (pos.numel() + dirs.numel() + freqs.numel()) * 8
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    out.append({"workload": "steering weights fp16: 256 ch x 1024 beams x 576 antennas (FP64 phase)",
+                "kernel": "steering_kernel", "value": round(gbs, 1), "unit": "GB/s", "ms_per_launch": round(ms, 4),
+                "weights_per_s": round(Wst.numel() / 2 / (ms * 1e-3), 1),
+                "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                             "frac": round(gbs / PEAK_HBM_GBS, 4)}})
+    del Wst, pos, dirs, freqs
     # sign packing of int8 interleaved data shaped like the 1-bit X: [64][8192][8192][2]
     g = torch.Generator(device="cuda:0")
     g.manual_seed(3)

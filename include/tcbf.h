@@ -200,6 +200,30 @@ tcbf_status tcbf_quantize_e4m3(const void *src, int32_t src_type, int32_t src_la
                                int64_t batch, int64_t rows, int64_t K, int32_t src_k_major,
                                int32_t block, uint8_t *dst, void *scales, void *stream);
 
+/*
+ * tcbf_steering_weights -- the weights W of Eq. 3 from array geometry, in FP64
+ * on the device.  Sec. II's far-field delay (Eq. 2), for sensor k at
+ * positions[k] = (x, y, z) metres and beam m along directions[m] = (l, m, n)
+ * (direction cosines), is tau = (x l + y m + z n) / wave_speed; the weight
+ * that re-aligns its phase at frequencies[c] is
+ *     W[c][m][k] = exp(+i 2 pi frac(f tau)),   frac(v) = v - floor(v),
+ * with s = x l + y m + z n summed left to right, cycles = (f s) / wave_speed,
+ * every FP64 operation rounded on its own (nothing fused), cos/sin of
+ * 2 pi frac(cycles) from the device math library.
+ *   positions (device) [K][3] double, directions (device) [M][3] double,
+ *   frequencies (device) [batch] double, all 8-byte aligned;
+ *   W (device, 16-byte aligned): planar [batch][2][M][K], element type
+ *   out_type = TCBF_SRC_F16 (each value rounded once, to nearest even) or
+ *   TCBF_SRC_F32 (nearest).  This is the TCBF_F16 operand layout of W; FP8
+ *   weights follow with tcbf_quantize_e4m3.
+ * Returns INVALID_VALUE for NULL or misaligned pointers, non-positive sizes,
+ * a wave speed that is not positive and finite, or another out_type.
+ * Asynchronous on `stream`; allocation-free.
+ */
+tcbf_status tcbf_steering_weights(const double *positions, const double *directions,
+                                  const double *frequencies, double wave_speed, int64_t batch,
+                                  int64_t M, int64_t K, int32_t out_type, void *W, void *stream);
+
 /* Report the plan's choice.  info->struct_size must be set by the caller. */
 tcbf_status tcbf_plan_query(tcbf_plan_t plan, tcbf_plan_info *info);
 

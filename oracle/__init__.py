@@ -50,6 +50,7 @@ def _load():
     lib.oracle_e4m3_decode.argtypes = [_i64, _p, _p]
     lib.oracle_quantize_e4m3_rows.argtypes = [_i64, _i64, _p, _p, _p, _p, _p]
     lib.oracle_quantize_e4m3_blocks.argtypes = [_i64, _i64, _p, _p, _p, _p, _p]
+    lib.oracle_steering_weights.argtypes = [_i64, _i64, _i64, _p, _p, _p, ctypes.c_double, _p, _p]
     lib.oracle_num_threads.argtypes = []
     lib.oracle_num_threads.restype = _int
     _lib = lib
@@ -306,3 +307,22 @@ def e8m0_decode(codes):
     c = np.asarray(codes, np.int64)
     out = np.ldexp(1.0, c - 127)
     return np.where(c == 255, np.nan, out)
+
+
+# --------------------------------------------------------------------------
+# steering weights (Sec. II delays, Eq. 3 weights)
+# --------------------------------------------------------------------------
+
+def steering_weights(positions, directions, freqs, wave_speed):
+    """positions [K, 3] m, directions [M, 3] (direction cosines), freqs [batch] Hz
+    -> complex128 weights [batch, M, K], w = exp(+2 pi i frac(f s / c))."""
+    p = _c(positions, np.float64)
+    d = _c(directions, np.float64)
+    f = _c(np.atleast_1d(freqs), np.float64)
+    if p.ndim != 2 or p.shape[1] != 3 or d.ndim != 2 or d.shape[1] != 3:
+        raise ValueError("positions [K, 3] and directions [M, 3]")
+    K, M, batch = p.shape[0], d.shape[0], f.size
+    re = np.empty((batch, M, K), np.float64)
+    im = np.empty((batch, M, K), np.float64)
+    _load().oracle_steering_weights(batch, M, K, _ptr(p), _ptr(d), _ptr(f), float(wave_speed), _ptr(re), _ptr(im))
+    return re + 1j * im

@@ -433,3 +433,40 @@ void oracle_quantize_e4m3_blocks(int64_t rows, int64_t cols, const float *re, co
         }
     }
 }
+
+/* ------------------------------------------------------------------------- */
+/* Steering weights from array geometry                                      */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * Far-field delay of Sec. II (Eq. 2, tau_k = d_k sin(theta) / c, written for a
+ * 3-D array as the projection of the sensor position on the beam direction):
+ *   s = x_k l_m + y_k m_m + z_k n_m        (metres, left to right, no fused ops)
+ *   cycles = (f_c * s) / c
+ * and the weight that re-aligns the phase of sensor k for beam m (Eq. 3):
+ *   w = exp(+i 2 pi frac(cycles)),  frac(v) = v - floor(v)
+ * positions [K][3] (x, y, z), directions [M][3] (l, m, n), freqs [batch];
+ * re, im: [batch][M][K] FP64.
+ */
+void oracle_steering_weights(int64_t batch, int64_t M, int64_t K, const double *positions,
+                             const double *directions, const double *freqs, double wave_speed,
+                             double *re, double *im)
+{
+    int64_t cm;
+    const double two_pi = 6.283185307179586;
+#pragma omp parallel for schedule(static)
+    for (cm = 0; cm < batch * M; ++cm) {
+        const int64_t c = cm / M, m = cm % M;
+        const double l = directions[3 * m], mm = directions[3 * m + 1], n = directions[3 * m + 2];
+        for (int64_t k = 0; k < K; ++k) {
+            double s = positions[3 * k] * l;
+            double cycles, phi;
+            s = s + positions[3 * k + 1] * mm;
+            s = s + positions[3 * k + 2] * n;
+            cycles = (freqs[c] * s) / wave_speed;
+            phi = two_pi * (cycles - floor(cycles));
+            re[cm * K + k] = cos(phi);
+            im[cm * K + k] = sin(phi);
+        }
+    }
+}

@@ -13,7 +13,8 @@ import os
 
 __all__ = [
     "F16", "INT1", "F8_E4M3", "MXF8_E4M3", "PLANAR", "INTERLEAVED", "SRC_I8", "SRC_F16", "SRC_F32",
-    "TcbfError", "Plan", "pack1bit", "quantize_e4m3", "f8_kp", "lib", "status_string", "EXPORTS",
+    "TcbfError", "Plan", "pack1bit", "quantize_e4m3", "steering_weights", "f8_kp", "lib", "status_string",
+    "EXPORTS",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -24,8 +25,8 @@ PLANAR, INTERLEAVED = 0, 1
 SRC_I8, SRC_F16, SRC_F32 = 0, 1, 2
 
 # every symbol include/tcbf.h declares
-EXPORTS = ("tcbf_plan", "tcbf_execute", "tcbf_pack1bit", "tcbf_quantize_e4m3", "tcbf_plan_query",
-           "tcbf_plan_destroy", "tcbf_status_string", "tcbf_version")
+EXPORTS = ("tcbf_plan", "tcbf_execute", "tcbf_pack1bit", "tcbf_quantize_e4m3", "tcbf_steering_weights",
+           "tcbf_plan_query", "tcbf_plan_destroy", "tcbf_status_string", "tcbf_version")
 
 _STATUS = {0: "TCBF_SUCCESS", 1: "TCBF_ERROR_INVALID_VALUE", 2: "TCBF_ERROR_NOT_SUPPORTED",
            3: "TCBF_ERROR_OUT_OF_MEMORY", 4: "TCBF_ERROR_DEVICE", 5: "TCBF_ERROR_INTERNAL"}
@@ -73,6 +74,8 @@ def lib():
     L.tcbf_pack1bit.restype = i32
     L.tcbf_quantize_e4m3.argtypes = [vp, i32, i32, i64, i64, i64, i32, i32, vp, vp, vp]
     L.tcbf_quantize_e4m3.restype = i32
+    L.tcbf_steering_weights.argtypes = [vp, vp, vp, ctypes.c_double, i64, i64, i64, i32, vp, vp]
+    L.tcbf_steering_weights.restype = i32
     L.tcbf_plan_query.argtypes = [vp, ctypes.POINTER(PlanInfo)]
     L.tcbf_plan_query.restype = i32
     L.tcbf_plan_destroy.argtypes = [vp]
@@ -297,3 +300,29 @@ def quantize_e4m3(src, k_major=True, layout=PLANAR, block=0, out=None, scales=No
                                     _dev_ptr(scales, "scales"), _stream_handle(stream)),
            "tcbf_quantize_e4m3")
     return out, scales
+
+
+def steering_weights(positions, directions, frequencies, wave_speed, dtype=None, out=None, stream=None):
+    """Steering weights on the device: positions [K, 3], directions [M, 3],
+    frequencies [batch] (float64 device tensors) -> planar [batch, 2, M, K]
+    float16 (default) or float32 weights, w = exp(+2 pi i frac(f s / c))."""
+    import torch
+    dtype = torch.float16 if dtype is None else dtype
+    types = {torch.float16: SRC_F16, torch.float32: SRC_F32}
+    if dtype not in types:
+        raise ValueError("dtype must be float16 or float32")
+    for t, nm in ((positions, "positions"), (directions, "directions"), (frequencies, "frequencies")):
+        if t.dtype != torch.float64:
+            raise ValueError("%s must be float64" % nm)
+    if positions.dim() != 2 or positions.shape[1] != 3 or directions.dim() != 2 or directions.shape[1] != 3:
+        raise ValueError("positions [K, 3] and directions [M, 3]")
+    K, M, batch = positions.shape[0], directions.shape[0], frequencies.numel()
+    if out is None:
+        out = torch.empty((batch, 2, M, K), dtype=dtype, device=positions.device)
+    if tuple(out.shape) != (batch, 2, M, K) or out.dtype != dtype:
+        raise ValueError("out must be %s [batch, 2, M, K]" % dtype)
+    _check(lib().tcbf_steering_weights(_dev_ptr(positions, "positions"), _dev_ptr(directions, "directions"),
+                                       _dev_ptr(frequencies, "frequencies"), float(wave_speed), int(batch), int(M),
+                                       int(K), types[dtype], _dev_ptr(out, "out"), _stream_handle(stream)),
+           "tcbf_steering_weights")
+    return out

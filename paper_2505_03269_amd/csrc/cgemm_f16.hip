@@ -391,19 +391,21 @@ __global__ __launch_bounds__(NT, 2) void cgemm_f16_kernel(
 // Fast kernel: direct-to-LDS loads, transposing LDS reads, NS-deep ring.
 // ===========================================================================
 //
-// LDS stage (bytes), for a stage of BK receivers:
-//   W region [2 planes][128 beams][BK] fp16: rows of BK*2 bytes split in
+// The workgroup has 2*WM waves in a WM x 2 grid and owns TM = 64*WM beams x
+// 128 samples.  LDS stage (bytes), for a stage of BK receivers:
+//   W region [2 planes][TM beams][BK] fp16: rows of BK*2 bytes split in
 //     16-byte chunks; chunk ch of beam m sits at ch ^ swzW(m);
 //   X region [2 planes][BK][128 samples] fp16: rows of 256 bytes (16 chunks);
 //     chunk ch of row k sits at ch ^ swzX(k).
 // The swizzles keep the MFMA operand reads free of bank conflicts for 8- and
 // 16-lane access phases.
-template <int BK> struct FastGeo {
+template <int WM, int BK> struct FastGeo {
+    static constexpr int TM = 64 * WM;                 // beams per workgroup
+    static constexpr int NW = 2 * WM;                  // waves
     static constexpr int WCH = BK / 8;                 // chunks per W row
-    static constexpr int WREG = 2 * BM * BK * 2;       // W region bytes
+    static constexpr int WREG = 2 * TM * BK * 2;       // W region bytes
     static constexpr int XREG = 2 * BK * BN * 2;       // X region bytes
     static constexpr int STAGE = WREG + XREG;          // stage bytes
-    static constexpr int LOADS = (WREG + XREG) / (NT * 16);  // 16-byte loads per thread per stage
     // both use only beam bits 1..3, so beams 16 apart share a swizzle
     __device__ static int swzW(int m) {
         return BK == 32 ? (((m >> 1) ^ ((m >> 3) & 1)) & 3) : (((m >> 2) ^ (m >> 3)) & 1);
@@ -419,13 +421,14 @@ __device__ __forceinline__ half8 tr_frag(const char *lds_bytes, int off0, int of
     return __builtin_bit_cast(half8, v);
 }
 
-template <int BK, int NS, int CIL>
-__global__ __launch_bounds__(NT, 2) void cgemm_f16_fast_kernel(
+template <int WM, int BK, int NS, int CIL>
+__global__ __launch_bounds__(128 * WM, WM == 2 ? 2 : 1) void cgemm_f16_fast_kernel(
     const uint16_t *__restrict__ A, const uint16_t *__restrict__ B, float *__restrict__ C,
     int M, int N, int K, int a_shared, int tiles_m, int tiles_n, int nblocks) {
-    typedef FastGeo<BK> G;
-    static_assert(NS >= 2 && NS <= 5, "ring depth");
-    static_assert(G::WREG % (64 * 16) == 0 && G::XREG % (64 * 16) == 0, "whole wave loads");
+    typedef FastGeo<WM, BK> G;
+    constexpr int TM = G::TM, NW = G::NW;
+    static_assert(NS >= 2 && NS <= 6, "ring depth");
+    static_assert(G::WREG % (NW * 1024) == 0 && G::XREG % (NW * 1024) == 0, "whole wave loads");
     // every stage buffer is its own object, so the compiler can tell the
     // direct-to-LDS writes into one from the fragment reads of another
     __shared__ __attribute__((aligned(1024))) char lds0[G::STAGE];
@@ -433,7 +436,8 @@ __global__ __launch_bounds__(NT, 2) void cgemm_f16_fast_kernel(
     __shared__ __attribute__((aligned(NS > 2 ? 1024 : 4))) char lds2[NS > 2 ? G::STAGE : 4];
     __shared__ __attribute__((aligned(NS > 3 ? 1024 : 4))) char lds3[NS > 3 ? G::STAGE : 4];
     __shared__ __attribute__((aligned(NS > 4 ? 1024 : 4))) char lds4[NS > 4 ? G::STAGE : 4];
-    char *const bufs[5] = {lds0, lds1, lds2, lds3, lds4};
+    __shared__ __attribute__((aligned(NS > 5 ? 1024 : 4))) char lds5[NS > 5 ? G::STAGE : 4];
+    char *const bufs[6] = {lds0, lds1, lds2, lds3, lds4, lds5};
 
     const int tid = threadIdx.x;
     const int t = (int)xcd_remap(blockIdx.x, nblocks);
@@ -441,7 +445,7 @@ __global__ __launch_bounds__(NT, 2) void cgemm_f16_fast_kernel(
     const int c = t / per_c;
     const int rem = t - c * per_c;
     const int tn = rem / tiles_m, tm = rem - tn * tiles_m;
-    const int m0 = tm * BM, n0 = tn * BN;
+    const int m0 = tm * TM, n0 = tn * BN;
 
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lane = tid & 63;
@@ -459,13 +463,13 @@ __global__ __launch_bounds__(NT, 2) void cgemm_f16_fast_kernel(
     // the pieces differ only by whole rows (same plane, same swizzle), so one
     // per-lane offset plus a uniform row stride per piece addresses them all.
     constexpr int WPIECES = G::WREG / 1024, XPIECES = G::XREG / 1024;
-    constexpr int WPW = WPIECES / 4, XPW = XPIECES / 4;  // pieces per wave
+    constexpr int WPW = WPIECES / NW, XPW = XPIECES / NW;  // pieces per wave
     constexpr int WROWS = 64 / G::WCH, XROWS = 64 / 16;  // rows per piece
     uint32_t va, vb;   // byte offsets of piece 0
     int ka, kb, am;    // receiver offset of the W chunk, X row of piece 0, W beam of piece 0
     {
         const int s = wave * WPW * 64 + lane;
-        const int p = s / (BM * G::WCH), m = (s / G::WCH) % BM;
+        const int p = s / (TM * G::WCH), m = (s / G::WCH) % TM;
         const int ch = (s % G::WCH) ^ G::swzW(m);
         ka = ch * 8;
         am = m;
@@ -477,7 +481,7 @@ __global__ __launch_bounds__(NT, 2) void cgemm_f16_fast_kernel(
         kb = k;
         vb = (n0 + ch * 8 < N) ? (uint32_t)(((p * K + k) * N + n0 + ch * 8) * 2) : OOB;
     }
-    const bool rows_full = m0 + BM <= M;
+    const bool rows_full = m0 + TM <= M;
 
     // LDS byte offsets of this lane's MFMA fragments in a stage (plane 0):
     // W fragment for 16-receiver step s: beam wm*64 + l32, chunk 2s + hl;
@@ -530,7 +534,7 @@ __global__ __launch_bounds__(NT, 2) void cgemm_f16_fast_kernel(
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
                 wr[i] = *reinterpret_cast<const half8 *>(st + ow[s] + i * 32 * BK * 2);
-                wi[i] = *reinterpret_cast<const half8 *>(st + ow[s] + i * 32 * BK * 2 + BM * BK * 2);
+                wi[i] = *reinterpret_cast<const half8 *>(st + ow[s] + i * 32 * BK * 2 + TM * BK * 2);
             }
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
@@ -580,13 +584,20 @@ __global__ __launch_bounds__(NT, 2) void cgemm_f16_fast_kernel(
 
     // Epilogue through the (now idle) stage buffers.
     constexpr int ROWS_PER_BUF = G::STAGE / staging_pitch<CIL>();
-    static_assert(ROWS_PER_BUF * (NS < 4 ? NS : 4) >= (CIL ? 64 : 128), "stage buffers hold a staging round");
+    static_assert(G::STAGE % staging_pitch<CIL>() == 0, "staged rows stay inside one buffer");
+    static_assert(ROWS_PER_BUF * NS >= staging_rows<WM, CIL>(), "stage buffers hold a staging round");
     auto row_ptr = [&](int row) -> char * {  // select chain: no dynamically indexed array
+        constexpr int NB = (staging_rows<WM, CIL>() + ROWS_PER_BUF - 1) / ROWS_PER_BUF;  // buffers in use
         const int b = row / ROWS_PER_BUF;
-        char *base = b == 0 ? lds0 : b == 1 ? lds1 : b == 2 ? lds2 : lds3;
+        char *base = lds0;
+        if (NB > 1 && b == 1) base = lds1;
+        if (NB > 2 && b == 2) base = lds2;
+        if (NB > 3 && b == 3) base = lds3;
+        if (NB > 4 && b == 4) base = lds4;
+        if (NB > 5 && b == 5) base = lds5;
         return base + (row % ROWS_PER_BUF) * staging_pitch<CIL>();
     };
-    store_tile_staged<CIL>(acc, row_ptr, C + (int64_t)c * 2 * M * N, M, N, m0, n0, wave, lane);
+    store_tile_staged<WM, CIL>(acc, row_ptr, C + (int64_t)c * 2 * M * N, M, N, m0, n0, wave, lane);
 }
 
 typedef void (*KernFn)(const uint16_t *, const uint16_t *, float *, int64_t, int64_t, int64_t, int,
@@ -602,19 +613,36 @@ KernFn pick(int ail, int bil, int cil) {
     return table[(ail << 2) | (bil << 1) | cil];
 }
 
-// Fast-kernel configurations: (receivers per stage, ring depth).
+// Fast-kernel configurations (variant: beam waves WM, receivers per stage,
+// ring depth):  2: 2, 32, 2   3: 2, 16, 4   4: 2, 16, 5   5: 2, 32, 3
+//               6: 4, 32, 3   7: 4, 16, 6
+// WM = 2 runs two 256-thread workgroups per CU; WM = 4 one 512-thread
+// workgroup with a 256 x 128 tile.
 constexpr int kFirstFast = 2;
-constexpr int kNumFast = 4;
+constexpr int kNumFast = 6;
 constexpr int kDefaultFast = 2;
 
-int fast_bk(int v) { return (v == 2 || v == 5) ? 32 : 16; }
+struct FastShape {
+    int wm, bk;
+};
+FastShape fast_shape(int v) {
+    switch (v) {
+    case 2: return {2, 32};
+    case 3: case 4: return {2, 16};
+    case 5: return {2, 32};
+    case 6: return {4, 32};
+    default: return {4, 16};
+    }
+}
 
 FastFn fast_fn(int v, bool cil) {
     switch (v) {
-    case 2: return cil ? cgemm_f16_fast_kernel<32, 2, 1> : cgemm_f16_fast_kernel<32, 2, 0>;
-    case 3: return cil ? cgemm_f16_fast_kernel<16, 4, 1> : cgemm_f16_fast_kernel<16, 4, 0>;
-    case 4: return cil ? cgemm_f16_fast_kernel<16, 5, 1> : cgemm_f16_fast_kernel<16, 5, 0>;
-    default: return cil ? cgemm_f16_fast_kernel<32, 3, 1> : cgemm_f16_fast_kernel<32, 3, 0>;
+    case 2: return cil ? cgemm_f16_fast_kernel<2, 32, 2, 1> : cgemm_f16_fast_kernel<2, 32, 2, 0>;
+    case 3: return cil ? cgemm_f16_fast_kernel<2, 16, 4, 1> : cgemm_f16_fast_kernel<2, 16, 4, 0>;
+    case 4: return cil ? cgemm_f16_fast_kernel<2, 16, 5, 1> : cgemm_f16_fast_kernel<2, 16, 5, 0>;
+    case 5: return cil ? cgemm_f16_fast_kernel<2, 32, 3, 1> : cgemm_f16_fast_kernel<2, 32, 3, 0>;
+    case 6: return cil ? cgemm_f16_fast_kernel<4, 32, 3, 1> : cgemm_f16_fast_kernel<4, 32, 3, 0>;
+    default: return cil ? cgemm_f16_fast_kernel<4, 16, 6, 1> : cgemm_f16_fast_kernel<4, 16, 6, 0>;
     }
 }
 
@@ -636,10 +664,10 @@ bool f16_select(const Problem &p, int forced_variant, F16Config *cfg) {
     if (v < 1 || v >= kFirstFast + kNumFast) return false;
     if (v >= kFirstFast && !fast_ok(p)) return false;
     cfg->variant = v;
-    cfg->tile_m = BM;
+    cfg->tile_m = v >= kFirstFast ? 64 * fast_shape(v).wm : BM;
     cfg->tile_n = BN;
-    cfg->tile_k = v >= kFirstFast ? fast_bk(v) : BK;
-    cfg->threads = NT;
+    cfg->tile_k = v >= kFirstFast ? fast_shape(v).bk : BK;
+    cfg->threads = v >= kFirstFast ? 128 * fast_shape(v).wm : NT;
     // 16-byte loads need every row start 16-byte aligned (base pointers are
     // required to be 16-byte aligned by the ABI).
     cfg->a_vec = p.a_layout == TCBF_PLANAR ? (p.K % 8 == 0) : (p.K % 4 == 0);
@@ -659,12 +687,12 @@ const char *f16_kernel_name(const F16Config &cfg) {
 
 hipError_t f16_launch(const Problem &p, const F16Config &cfg, const void *A, const void *B,
                       void *C, hipStream_t stream) {
-    int tiles_m = (int)((p.M + BM - 1) / BM);
+    int tiles_m = (int)((p.M + cfg.tile_m - 1) / cfg.tile_m);
     int tiles_n = (int)((p.N + BN - 1) / BN);
     int64_t nblocks = p.batch * tiles_m * tiles_n;
     if (cfg.variant >= kFirstFast) {
         FastFn fn = fast_fn(cfg.variant, p.c_layout == TCBF_INTERLEAVED);
-        hipLaunchKernelGGL(fn, dim3((uint32_t)nblocks), dim3(NT), 0, stream, (const uint16_t *)A,
+        hipLaunchKernelGGL(fn, dim3((uint32_t)nblocks), dim3(cfg.threads), 0, stream, (const uint16_t *)A,
                            (const uint16_t *)B, (float *)C, (int)p.M, (int)p.N, (int)p.K, p.a_shared,
                            tiles_m, tiles_n, (int)nblocks);
         return hipGetLastError();

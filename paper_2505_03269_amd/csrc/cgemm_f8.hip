@@ -262,7 +262,7 @@ __global__ __launch_bounds__(NT, 2) void cgemm_f8_kernel(
     auto row_ptr = [&](int row) -> char * {
         return (row < ROWS_PER_BUF ? lds0 : lds1) + (row % ROWS_PER_BUF) * staging_pitch<CIL>();
     };
-    store_tile_staged<CIL>(acc, row_ptr, C + (int64_t)c * 2 * M * N, M, N, m0, n0, wave, lane);
+    store_tile_staged<2, CIL>(acc, row_ptr, C + (int64_t)c * 2 * M * N, M, N, m0, n0, wave, lane);
 }
 
 typedef void (*F8Fn)(const uint8_t *, const uint8_t *, float *, const void *, const void *, int, int, int, int, int,

@@ -1,7 +1,7 @@
 // C ABI of the beamforming library: plan creation (validation and kernel
 // choice, host only), execution (argument checks and one kernel launch), sign
-// packing and FP8 quantisation.  No entry point throws, aborts or allocates
-// device memory.
+// packing, FP8 quantisation and steering weights.  No entry point throws,
+// aborts or allocates device memory.
 #include <new>
 #include <stdio.h>
 #include <string.h>
@@ -23,6 +23,7 @@ constexpr int64_t kMaxIndex = (int64_t)1 << 31;  // per-launch workgroup limit
 
 bool is_layout(int32_t v) { return v == TCBF_PLANAR || v == TCBF_INTERLEAVED; }
 bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+bool aligned8(const void *p) { return ((uintptr_t)p & 7u) == 0; }
 bool is_f8(int32_t dtype) { return dtype == TCBF_F8_E4M3 || dtype == TCBF_MXF8_E4M3; }
 bool is_src_type(int32_t t) { return t == TCBF_SRC_I8 || t == TCBF_SRC_F16 || t == TCBF_SRC_F32; }
 
@@ -228,6 +229,22 @@ tcbf_status tcbf_quantize_e4m3(const void *src, int32_t src_type, int32_t src_la
         return TCBF_ERROR_NOT_SUPPORTED;
     hipError_t e = tcbf::quantize_e4m3_launch(src, src_type, src_layout, batch, rows, K, src_k_major != 0, block,
                                               dst, scales, (hipStream_t)stream);
+    return e == hipSuccess ? TCBF_SUCCESS : TCBF_ERROR_DEVICE;
+}
+
+tcbf_status tcbf_steering_weights(const double *positions, const double *directions, const double *frequencies,
+                                  double wave_speed, int64_t batch, int64_t M, int64_t K, int32_t out_type, void *W,
+                                  void *stream) {
+    if (positions == nullptr || directions == nullptr || frequencies == nullptr || W == nullptr)
+        return TCBF_ERROR_INVALID_VALUE;
+    if (out_type != TCBF_SRC_F16 && out_type != TCBF_SRC_F32) return TCBF_ERROR_INVALID_VALUE;
+    if (batch < 1 || M < 1 || K < 1) return TCBF_ERROR_INVALID_VALUE;
+    if (!(wave_speed > 0.0) || wave_speed > 1e300) return TCBF_ERROR_INVALID_VALUE;
+    if (!aligned8(positions) || !aligned8(directions) || !aligned8(frequencies) || !aligned16(W))
+        return TCBF_ERROR_INVALID_VALUE;
+    if (tcbf::steering_blocks(batch, M, K) >= kMaxIndex) return TCBF_ERROR_NOT_SUPPORTED;
+    hipError_t e = tcbf::steering_launch(positions, directions, frequencies, wave_speed, batch, M, K, out_type, W,
+                                         (hipStream_t)stream);
     return e == hipSuccess ? TCBF_SUCCESS : TCBF_ERROR_DEVICE;
 }
 

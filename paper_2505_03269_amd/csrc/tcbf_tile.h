@@ -64,27 +64,32 @@ __device__ __forceinline__ f32x4 quad(const f32x16 &v, int q) {
 // Epilogue: write the workgroup's finished tile (each wave's Acc) to C,
 // staged through LDS so every store instruction writes whole rows: a planar
 // plane row is 128 samples x 4 B = 512 B, an interleaved row 128 x 8 B = 1 KiB.
+// The workgroup has 2*WM waves in a WM x 2 grid (wave w: beams (w/2)*64..,
+// samples (w%2)*64..), so the tile is 64*WM beams x 128 samples.
 // Staged rows keep their 16-byte chunks XOR-swizzled by (row % 32) so both the
 // writes (32 beams, same samples) and the row reads avoid bank conflicts.
-// Planar: round p stages plane p of the whole tile.  Interleaved: round h
-// stages beams 64h..64h+63 (the waves with wm == h) with (re, im) pairs.
-// row_ptr(row) must map staged rows 0..127 (planar) or 0..63 (interleaved) of
-// PITCH bytes each to idle LDS.  C: this channel's output; rows past M and
-// samples past N are dropped through the buffer range check.
+// Planar: round p stages plane p of the whole tile (64*WM rows).  Interleaved:
+// round h stages the upper or lower half of the beams (32*WM rows) with
+// (re, im) pairs.  row_ptr(row) must map every staged row of a round, PITCH
+// bytes each, to idle LDS.  C: this channel's output; rows past M and samples
+// past N are dropped through the buffer range check (N a multiple of 4).
 template <int CIL> constexpr int staging_pitch() { return CIL ? 1024 : 512; }
+template <int WM, int CIL> constexpr int staging_rows() { return CIL ? 32 * WM : 64 * WM; }
 
-template <int CIL, typename RowPtr>
+template <int WM, int CIL, typename RowPtr>
 __device__ __forceinline__ void store_tile_staged(const Acc &acc, RowPtr row_ptr, float *Cc, int M, int N,
                                                   int m0, int n0, int wave, int lane) {
+    constexpr int NW = 2 * WM, HALF = WM / 2;
+    static_assert(WM % 2 == 0, "whole beam halves");
     const int wm = wave >> 1, wn = wave & 1, hl = lane >> 5, l32 = lane & 31;
     const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc((void *)Cc, 0, 8 * M * N, RSRC_FLAGS);
 #pragma unroll
     for (int round = 0; round < 2; ++round) {
         lds_barrier();  // staging area free (main loop or previous round done)
-        if (!CIL || wm == round) {
+        if (!CIL || wm / HALF == round) {
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
-                const int row = (CIL ? 0 : wm * 64) + 32 * i + l32;
+                const int row = (CIL ? (wm % HALF) * 64 : wm * 64) + 32 * i + l32;
                 char *rp = row_ptr(row);
 #pragma unroll
                 for (int j = 0; j < 2; ++j)
@@ -107,24 +112,29 @@ __device__ __forceinline__ void store_tile_staged(const Acc &acc, RowPtr row_ptr
         }
         lds_barrier();  // round staged
         if (CIL) {
-            // 64 rows of 1 KiB; wave w stores rows w, w+4, ...; lane l owns chunk l
+            // 32*WM rows of 1 KiB; wave w stores rows w, w+NW, ...; lane l owns chunk l
 #pragma unroll 4
-            for (int t = 0; t < 16; ++t) {
-                const int row = wave + 4 * t;
+            for (int t = 0; t < 32 * WM / NW; ++t) {
+                const int row = wave + NW * t;
                 const f32x4 v = *reinterpret_cast<const f32x4 *>(row_ptr(row) + ((lane ^ (row & 31)) * 16));
-                const int m = m0 + 64 * round + row, n = n0 + 2 * lane;
+                const int m = m0 + 32 * WM * round + row, n = n0 + 2 * lane;
                 const uint32_t off = (m < M && n < N) ? (uint32_t)((m * N + n) * 8) : OOB;
                 __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), rc, off, 0, 0);
             }
         } else {
-            // 128 rows of 512 B; one instruction covers two rows
+            // 64*WM rows of 512 B; one instruction covers two rows; wave w
+            // stores rows 32w..32w+31
 #pragma unroll 4
-            for (int t = 0; t < 16; ++t) {
+            for (int t = 0; t < 64 * WM / (2 * NW); ++t) {
                 const int row = 32 * wave + 2 * t + hl;
                 const f32x4 v = *reinterpret_cast<const f32x4 *>(row_ptr(row) + ((l32 ^ (row & 31)) * 16));
                 const int m = m0 + row, n = n0 + 4 * l32;
-                const uint32_t off = (m < M && n < N) ? (uint32_t)((m * N + n) * 4) : OOB;
-                __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), rc, off, round * M * N * 4, 0);
+                // the plane offset goes into the per-lane offset: a buffer
+                // store with a register soffset gets no protection from the
+                // compiler against its data registers being overwritten by
+                // the very next instruction, which corrupts the stored data
+                const uint32_t off = (m < M && n < N) ? (uint32_t)((round * M * N + m * N + n) * 4) : OOB;
+                __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), rc, off, 0, 0);
             }
         }
     }

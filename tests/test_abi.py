@@ -120,6 +120,21 @@ def test_quantize_argument_checks():
     assert L.tcbf_quantize_e4m3(p, 1, 0, 1, 1, 1, 1, 32, p, q, None) == 1    # misaligned scales
 
 
+def test_steering_argument_checks():
+    L = tcbf.lib()
+    buf = ctypes.create_string_buffer(256)
+    addr = (ctypes.addressof(buf) + 15) & ~15
+    p = ctypes.c_void_p(addr)
+    q = ctypes.c_void_p(addr + 4)
+    assert L.tcbf_steering_weights(None, p, p, 3e8, 1, 1, 1, 1, p, None) == 1   # NULL positions
+    assert L.tcbf_steering_weights(p, p, p, 3e8, 1, 1, 1, 0, p, None) == 1      # int8 output
+    assert L.tcbf_steering_weights(p, p, p, 0.0, 1, 1, 1, 1, p, None) == 1      # wave speed 0
+    assert L.tcbf_steering_weights(p, p, p, float("nan"), 1, 1, 1, 1, p, None) == 1
+    assert L.tcbf_steering_weights(p, p, p, 3e8, 1, 0, 1, 1, p, None) == 1      # M 0
+    assert L.tcbf_steering_weights(q, p, p, 3e8, 1, 1, 1, 1, p, None) == 1      # misaligned positions
+    assert L.tcbf_steering_weights(p, p, p, 3e8, 1, 1, 1, 1, ctypes.c_void_p(addr + 8), None) == 1
+
+
 def test_valid_descriptor_without_gpu_reports_device():
     import torch
     if torch.cuda.is_available():

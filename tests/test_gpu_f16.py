@@ -219,10 +219,10 @@ def test_rejects_bad_tensors():
 
 
 ALIGNED_SHAPES = [(1, 1, 8, 8), (1, 130, 136, 40), (2, 200, 264, 72), (1, 129, 8, 520), (3, 64, 128, 32),
-                  (1, 257, 392, 576), (2, 128, 128, 8)]
+                  (1, 257, 392, 576), (2, 128, 128, 8), (1, 300, 264, 112)]
 
 
-FAST_VARIANTS = [2, 3, 4, 5]
+FAST_VARIANTS = [2, 3, 4, 5, 6, 7]
 
 
 @pytest.mark.parametrize("batch,M,N,K", ALIGNED_SHAPES)
