@@ -1,7 +1,7 @@
 #!/usr/bin/env python3
 """Benchmark of the batched complex beamforming product on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-secondary]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-secondary] [--sweep]
 
 One step = one tcbf_execute of the radio-astronomy workload (256 channels,
 M=1024 beams, K=576 receivers, N=4096 samples, fp16 in, fp32 complex out),
@@ -229,7 +229,103 @@ def bench_secondary(steps):
                     "roofline": {"bound": "mfma", "achieved": round(tops, 1), "peak": PEAK_F8_TFLOPS,
                                  "unit": "TFLOP/s", "frac": round(tops / PEAK_F8_TFLOPS, 4)}})
         del Wq, Ws, Xq, Xs, C
+    del A, B
+    torch.cuda.empty_cache()
+    # grouped persistent launch: 16 uneven job shapes from the served-stream
+    # distribution in one launch, against one launch per job
+    shapes = wl.mixed_shapes(0, 16)
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(7)
+    probs = []
+    for (M, N, K) in shapes:
+        Wg = torch.randn((1, 2, M, K), device="cuda:0", generator=g).half()
+        Xg = torch.randint(-127, 128, (1, 2, K, N), device="cuda:0", generator=g).half()
+        probs.append((Wg, Xg, torch.empty((1, 2, M, N), device="cuda:0")))
+    plans = [tcbf.Plan(1, M, N, K, tcbf.F16) for (M, N, K) in shapes]
+    ws = torch.empty(tcbf.GROUP_WORKSPACE_BYTES, dtype=torch.uint8, device="cuda:0")
+    ops = sum(8.0 * M * N * K for (M, N, K) in shapes)
+    ms_g = time_launches(lambda: tcbf.group_execute(probs, workspace=ws), st, 1)
+
+    def each():
+        for pl, (Wg, Xg, Cg) in zip(plans, probs):
+            pl.execute(Wg, Xg, Cg)
+    ms_s = time_launches(each, st, 1)
+    out.append({"workload": "grouped fp16: 16 jobs, M~U[128,4096] N~U[256,8192] K~U[64,2048]",
+                "kernel": "cgemm_f16_group_kernel", "value": round(ops / (ms_g * 1e-3) / 1e12, 1),
+                "unit": "TeraOps/s", "ms_per_launch": round(ms_g, 4),
+                "separate_launches_tops": round(ops / (ms_s * 1e-3) / 1e12, 1),
+                "separate_launches_ms": round(ms_s, 4), "dtype": "f16",
+                "roofline": {"bound": "mfma", "achieved": round(ops / (ms_g * 1e-3) / 1e12, 1),
+                             "peak": PEAK_F16_TFLOPS, "unit": "TFLOP/s",
+                             "frac": round(ops / (ms_g * 1e-3) / 1e12 / PEAK_F16_TFLOPS, 4)}})
+    del probs, plans
+    torch.cuda.empty_cache()
+    out.append(bench_serving())
     return out
+
+
+def bench_serving(warmup=1000, measured=10000):
+    """Served mixed stream: 16 resident weight sets per dtype (fp16, FP8
+    per-row, 1-bit), jobs uniform over them, N ~ U[256, 8192]; a closed-loop
+    run gives the sustained capacity, then Poisson arrivals at 80% and 50% of
+    it.  Latency is completion seen by the host minus arrival."""
+    from paper_2505_03269_amd import serve
+    srv = serve.Server(seed=0)
+    srv.run(srv.make_jobs(warmup, None, seed=100))
+    closed = srv.run(srv.make_jobs(measured, None, seed=200))
+    cap = measured / closed["makespan_s"]
+    runs = {}
+    for load in (0.8, 0.5):
+        runs[load] = srv.run(srv.make_jobs(measured, load * cap, seed=300 + int(load * 10)))
+    r = runs[0.8]
+    rnd = lambda d: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()}  # noqa: E731
+    return {"workload": "served mixed stream: fp16/fp8/1-bit jobs, 16 resident weight sets per dtype, "
+                        "M~U[128,4096] K~U[64,2048] N~U[256,8192], Poisson arrivals at 80% of capacity",
+            "kernel": "cgemm_f16_group_kernel + cgemm_f8_kernel + cgemm_1bit_mfma_kernel",
+            "value": round(r["tops"], 1), "unit": "TeraOps/s", "p50_ms": round(r["p50_ms"], 3),
+            "p99_ms": round(r["p99_ms"], 3), "capacity_jobs_per_s": round(cap, 1),
+            "closed_loop": rnd(closed), "load_0.8": rnd(runs[0.8]), "load_0.5": rnd(runs[0.5]),
+            "warmup_jobs": warmup, "measured_jobs": measured, "streams": len(srv.streams),
+            "budget_bytes": srv.budget}
+
+
+def sweep(steps):
+    """The paper's measurement shapes, synthetic data, one JSON line each:
+    the LOFAR beamformer sweep (256 x 1024 beams x 1024 samples, 8..512
+    stations, Sec. V-B) and the roofline shapes (Sec. IV-B)."""
+    import torch
+    import paper_2505_03269_amd as tcbf
+    shapes = [("lofar-stations", tcbf.F16, 256, 1024, 1024, k) for k in
+              (8, 16, 24, 32, 48, 64, 96, 128, 160, 192, 256, 320, 384, 448, 512)]
+    shapes += [("roofline-f16-small", tcbf.F16, 256, 1024, 1024, 64), ("roofline-f16-big", tcbf.F16, 1, 8192, 8192, 8192),
+               ("roofline-int1-small", tcbf.INT1, 256, 1024, 1024, 256)]
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(11)
+    for name, dt, batch, M, N, K in shapes:
+        plan = tcbf.Plan(batch, M, N, K, dt)
+        info = plan.info()
+        if dt == tcbf.INT1:
+            A = torch.randint(-2**31, 2**31 - 1, plan.shape_a(), dtype=torch.int32, device="cuda:0", generator=g)
+            B = torch.randint(-2**31, 2**31 - 1, plan.shape_b(), dtype=torch.int32, device="cuda:0", generator=g)
+            peak = PEAK_I8_TOPS
+        else:
+            A = torch.randn(plan.shape_a(), device="cuda:0", generator=g).half()
+            B = torch.randint(-127, 128, plan.shape_b(), device="cuda:0", generator=g).half()
+            peak = PEAK_F16_TFLOPS
+        C = plan.empty_output()
+        ms = time_launches(lambda: plan.execute(A, B, C), steps, 2)
+        tops = info["useful_ops"] / (ms * 1e-3) / 1e12
+        gbs = info["algorithmic_bytes"] / (ms * 1e-3) / 1e9
+        ai = info["useful_ops"] / info["algorithmic_bytes"]
+        ridge = peak * 1e3 / PEAK_HBM_GBS
+        bound = "mfma" if ai >= ridge else "hbm"
+        frac = tops / peak if bound == "mfma" else gbs / PEAK_HBM_GBS
+        print(json.dumps({"sweep": name, "batch": batch, "M": M, "N": N, "K": K, "dtype": "f16" if dt == tcbf.F16 else "int1",
+                          "kernel": info["kernel_name"], "variant": info["variant"], "ms": round(ms, 4),
+                          "tops": round(tops, 1), "gbs_algorithmic": round(gbs, 1), "ops_per_byte": round(ai, 1),
+                          "bound": bound, "frac_of_bound": round(frac, 4)}), flush=True)
+        del A, B, C
+        torch.cuda.empty_cache()
 
 
 def main():
@@ -239,6 +335,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--sweep", action="store_true",
+                    help="print one JSON line per paper measurement shape (LOFAR station sweep, roofline shapes)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 1 GiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -258,6 +356,9 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_calibration:
         copy_calibration()
+    if args.sweep:
+        sweep(args.steps)
+        return
 
     W, X, info, ms, tops = bench_c2(args.steps, args.warmup)
     log("c2: %.4f ms/launch, %.1f TeraOps/s" % (ms, tops))

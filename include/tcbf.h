@@ -224,6 +224,42 @@ tcbf_status tcbf_steering_weights(const double *positions, const double *directi
                                   const double *frequencies, double wave_speed, int64_t batch,
                                   int64_t M, int64_t K, int32_t out_type, void *W, void *stream);
 
+/*
+ * Grouped persistent launch (TCBF_F16): up to TCBF_GROUP_MAX independent
+ * problems of different shapes -- channels, frames or jobs, each B = W . X in
+ * the TCBF_F16 layouts with planar W and X -- run in ONE launch.  The
+ * problems' output tiles form one work list, longest receiver count first
+ * (the paper's Sec. IV-C size sweep shows per-shape padding and tail effects;
+ * one shared list keeps every CU busy across shape boundaries); persistent
+ * workgroups (two per CU) take tiles from a device counter until the list is
+ * empty.  The problem table travels in the launch's kernel arguments, so the
+ * call can be captured in a HIP graph and replayed.
+ *   problems: host array of `count` descriptors (1 <= count <= TCBF_GROUP_MAX);
+ *     each needs batch, M, N, K >= 1, K and N multiples of 8, 16-byte
+ *     aligned device pointers, per-channel W and X below 2 GiB and its
+ *     output below 2 GiB.
+ *   workspace: device memory of TCBF_GROUP_WORKSPACE_BYTES, 16-byte aligned,
+ *     used for the tile counter; calls that overlap in time (on different
+ *     streams) need different workspaces.
+ * The current device must be `device`.  Enqueues two kernels on `stream`
+ * (counter reset, persistent product); allocation-free.
+ */
+#define TCBF_GROUP_MAX 32
+#define TCBF_GROUP_WORKSPACE_BYTES 256
+
+typedef struct tcbf_group_problem {
+    const void *A;     /* W, planar fp16 [batch|1][2][M][K]                */
+    const void *B;     /* X, planar fp16 [batch][2][K][N]                  */
+    void *C;           /* output fp32, layout c_layout                     */
+    int64_t batch, M, N, K;
+    int32_t a_shared;  /* nonzero: one W for all batch entries             */
+    int32_t reserved;  /* must be 0                                        */
+} tcbf_group_problem;
+
+tcbf_status tcbf_group_execute(int32_t device, int32_t dtype, int32_t c_layout,
+                               const tcbf_group_problem *problems, int32_t count,
+                               void *workspace, void *stream);
+
 /* Report the plan's choice.  info->struct_size must be set by the caller. */
 tcbf_status tcbf_plan_query(tcbf_plan_t plan, tcbf_plan_info *info);
 

@@ -13,8 +13,8 @@ import os
 
 __all__ = [
     "F16", "INT1", "F8_E4M3", "MXF8_E4M3", "PLANAR", "INTERLEAVED", "SRC_I8", "SRC_F16", "SRC_F32",
-    "TcbfError", "Plan", "pack1bit", "quantize_e4m3", "steering_weights", "f8_kp", "lib", "status_string",
-    "EXPORTS",
+    "TcbfError", "Plan", "pack1bit", "quantize_e4m3", "steering_weights", "group_execute", "f8_kp", "lib",
+    "status_string", "EXPORTS", "GROUP_MAX", "GROUP_WORKSPACE_BYTES",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -26,7 +26,9 @@ SRC_I8, SRC_F16, SRC_F32 = 0, 1, 2
 
 # every symbol include/tcbf.h declares
 EXPORTS = ("tcbf_plan", "tcbf_execute", "tcbf_pack1bit", "tcbf_quantize_e4m3", "tcbf_steering_weights",
-           "tcbf_plan_query", "tcbf_plan_destroy", "tcbf_status_string", "tcbf_version")
+           "tcbf_group_execute", "tcbf_plan_query", "tcbf_plan_destroy", "tcbf_status_string", "tcbf_version")
+GROUP_MAX = 32
+GROUP_WORKSPACE_BYTES = 256
 
 _STATUS = {0: "TCBF_SUCCESS", 1: "TCBF_ERROR_INVALID_VALUE", 2: "TCBF_ERROR_NOT_SUPPORTED",
            3: "TCBF_ERROR_OUT_OF_MEMORY", 4: "TCBF_ERROR_DEVICE", 5: "TCBF_ERROR_INTERNAL"}
@@ -44,6 +46,12 @@ class PlanDesc(ctypes.Structure):
                 ("K", ctypes.c_int64), ("dtype", ctypes.c_int32), ("a_layout", ctypes.c_int32),
                 ("b_layout", ctypes.c_int32), ("c_layout", ctypes.c_int32),
                 ("a_shared", ctypes.c_int32), ("variant", ctypes.c_int32)]
+
+
+class GroupProblem(ctypes.Structure):
+    _fields_ = [("A", ctypes.c_void_p), ("B", ctypes.c_void_p), ("C", ctypes.c_void_p),
+                ("batch", ctypes.c_int64), ("M", ctypes.c_int64), ("N", ctypes.c_int64), ("K", ctypes.c_int64),
+                ("a_shared", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -76,6 +84,8 @@ def lib():
     L.tcbf_quantize_e4m3.restype = i32
     L.tcbf_steering_weights.argtypes = [vp, vp, vp, ctypes.c_double, i64, i64, i64, i32, vp, vp]
     L.tcbf_steering_weights.restype = i32
+    L.tcbf_group_execute.argtypes = [i32, i32, i32, ctypes.POINTER(GroupProblem), i32, vp, vp]
+    L.tcbf_group_execute.restype = i32
     L.tcbf_plan_query.argtypes = [vp, ctypes.POINTER(PlanInfo)]
     L.tcbf_plan_query.restype = i32
     L.tcbf_plan_destroy.argtypes = [vp]
@@ -326,3 +336,42 @@ def steering_weights(positions, directions, frequencies, wave_speed, dtype=None,
                                        int(K), types[dtype], _dev_ptr(out, "out"), _stream_handle(stream)),
            "tcbf_steering_weights")
     return out
+
+
+def group_execute(problems, c_layout=PLANAR, workspace=None, device=0, stream=None):
+    """One grouped persistent launch over up to GROUP_MAX fp16 problems.
+
+    problems: list of (W, X, C) or (W, X, C, a_shared) device tensors with
+    W float16 [batch|1, 2, M, K], X float16 [batch, 2, K, N], C float32
+    [batch, 2, M, N] (planar) or [batch, M, N, 2] (interleaved).
+    workspace: uint8 device tensor of GROUP_WORKSPACE_BYTES (allocated here
+    if None; pass one to stay allocation-free).
+    """
+    import torch
+    if not 1 <= len(problems) <= GROUP_MAX:
+        raise ValueError("1..%d problems per launch" % GROUP_MAX)
+    arr = (GroupProblem * len(problems))()
+    for i, pr in enumerate(problems):
+        W, X, C = pr[0], pr[1], pr[2]
+        shared = bool(pr[3]) if len(pr) > 3 else False
+        if W.dtype != torch.float16 or X.dtype != torch.float16 or C.dtype != torch.float32:
+            raise ValueError("problem %d: W, X float16 and C float32 expected" % i)
+        if W.dim() != 4 or X.dim() != 4 or W.shape[1] != 2 or X.shape[1] != 2:
+            raise ValueError("problem %d: planar W [b, 2, M, K] and X [b, 2, K, N] expected" % i)
+        batch, K, N = X.shape[0], X.shape[2], X.shape[3]
+        M = W.shape[2]
+        if W.shape[3] != K or W.shape[0] != (1 if shared else batch):
+            raise ValueError("problem %d: W does not match X" % i)
+        want = (batch, 2, M, N) if c_layout == PLANAR else (batch, M, N, 2)
+        if tuple(C.shape) != want:
+            raise ValueError("problem %d: C must have shape %s" % (i, want))
+        arr[i] = GroupProblem(_dev_ptr(W, "W").value, _dev_ptr(X, "X").value, _dev_ptr(C, "C").value,
+                              batch, M, N, K, int(shared), 0)
+    if workspace is None:
+        workspace = torch.empty(GROUP_WORKSPACE_BYTES, dtype=torch.uint8, device="cuda:%d" % device)
+    if workspace.numel() * workspace.element_size() < GROUP_WORKSPACE_BYTES:
+        raise ValueError("workspace too small")
+    _check(lib().tcbf_group_execute(int(device), F16, int(c_layout), arr, len(problems),
+                                    _dev_ptr(workspace, "workspace"), _stream_handle(stream)),
+           "tcbf_group_execute")
+    return [pr[2] for pr in problems]

@@ -30,6 +30,8 @@
 //  * cgemm_f16_kernel: any layout and alignment.  Tiles go through registers,
 //    interleaved (re, im) data is split into planes and X is transposed while
 //    being written to LDS.
+#include <string.h>
+
 #include "tcbf_tile.h"
 
 namespace tcbf {
@@ -421,30 +423,37 @@ __device__ __forceinline__ half8 tr_frag(const char *lds_bytes, int off0, int of
     return __builtin_bit_cast(half8, v);
 }
 
+// The stage buffers of one workgroup.  Every buffer is its own __shared__
+// object, so the compiler can tell the direct-to-LDS writes into one from the
+// fragment reads of another; buffers past the ring depth are 4-byte stubs.
+template <int WM, int BK, int NS> struct FastLds {
+    typedef FastGeo<WM, BK> G;
+    static constexpr int S2 = NS > 2 ? G::STAGE : 4, S3 = NS > 3 ? G::STAGE : 4, S4 = NS > 4 ? G::STAGE : 4,
+                         S5 = NS > 5 ? G::STAGE : 4;
+};
+#define TCBF_FAST_LDS(WM, BK, NS)                                                                          \
+    __shared__ __attribute__((aligned(1024))) char lds0[FastGeo<WM, BK>::STAGE];                           \
+    __shared__ __attribute__((aligned(1024))) char lds1[FastGeo<WM, BK>::STAGE];                           \
+    __shared__ __attribute__((aligned(NS > 2 ? 1024 : 4))) char lds2[FastLds<WM, BK, NS>::S2];             \
+    __shared__ __attribute__((aligned(NS > 3 ? 1024 : 4))) char lds3[FastLds<WM, BK, NS>::S3];             \
+    __shared__ __attribute__((aligned(NS > 4 ? 1024 : 4))) char lds4[FastLds<WM, BK, NS>::S4];             \
+    __shared__ __attribute__((aligned(NS > 5 ? 1024 : 4))) char lds5[FastLds<WM, BK, NS>::S5];
+
+// One output tile (64*WM beams x 128 samples of channel c at tile (tm, tn)):
+// the whole K loop and the epilogue.  Entered and left with the stage buffers
+// idle; the caller separates two tiles of one workgroup with a barrier.
 template <int WM, int BK, int NS, int CIL>
-__global__ __launch_bounds__(128 * WM, WM == 2 ? 2 : 1) void cgemm_f16_fast_kernel(
-    const uint16_t *__restrict__ A, const uint16_t *__restrict__ B, float *__restrict__ C,
-    int M, int N, int K, int a_shared, int tiles_m, int tiles_n, int nblocks) {
+__device__ __forceinline__ void fast_tile(const uint16_t *__restrict__ A, const uint16_t *__restrict__ B,
+                                          float *__restrict__ C, int M, int N, int K, int a_shared, int c, int tm,
+                                          int tn, char *lds0, char *lds1, char *lds2, char *lds3, char *lds4,
+                                          char *lds5) {
     typedef FastGeo<WM, BK> G;
     constexpr int TM = G::TM, NW = G::NW;
     static_assert(NS >= 2 && NS <= 6, "ring depth");
     static_assert(G::WREG % (NW * 1024) == 0 && G::XREG % (NW * 1024) == 0, "whole wave loads");
-    // every stage buffer is its own object, so the compiler can tell the
-    // direct-to-LDS writes into one from the fragment reads of another
-    __shared__ __attribute__((aligned(1024))) char lds0[G::STAGE];
-    __shared__ __attribute__((aligned(1024))) char lds1[G::STAGE];
-    __shared__ __attribute__((aligned(NS > 2 ? 1024 : 4))) char lds2[NS > 2 ? G::STAGE : 4];
-    __shared__ __attribute__((aligned(NS > 3 ? 1024 : 4))) char lds3[NS > 3 ? G::STAGE : 4];
-    __shared__ __attribute__((aligned(NS > 4 ? 1024 : 4))) char lds4[NS > 4 ? G::STAGE : 4];
-    __shared__ __attribute__((aligned(NS > 5 ? 1024 : 4))) char lds5[NS > 5 ? G::STAGE : 4];
     char *const bufs[6] = {lds0, lds1, lds2, lds3, lds4, lds5};
 
     const int tid = threadIdx.x;
-    const int t = (int)xcd_remap(blockIdx.x, nblocks);
-    const int per_c = tiles_m * tiles_n;
-    const int c = t / per_c;
-    const int rem = t - c * per_c;
-    const int tn = rem / tiles_m, tm = rem - tn * tiles_m;
     const int m0 = tm * TM, n0 = tn * BN;
 
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -600,6 +609,73 @@ __global__ __launch_bounds__(128 * WM, WM == 2 ? 2 : 1) void cgemm_f16_fast_kern
     store_tile_staged<WM, CIL>(acc, row_ptr, C + (int64_t)c * 2 * M * N, M, N, m0, n0, wave, lane);
 }
 
+template <int WM, int BK, int NS, int CIL>
+__global__ __launch_bounds__(128 * WM, WM == 2 ? 2 : 1) void cgemm_f16_fast_kernel(
+    const uint16_t *__restrict__ A, const uint16_t *__restrict__ B, float *__restrict__ C,
+    int M, int N, int K, int a_shared, int tiles_m, int tiles_n, int nblocks) {
+    TCBF_FAST_LDS(WM, BK, NS)
+    const int t = (int)xcd_remap(blockIdx.x, nblocks);
+    const int per_c = tiles_m * tiles_n;
+    const int c = t / per_c;
+    const int rem = t - c * per_c;
+    const int tn = rem / tiles_m, tm = rem - tn * tiles_m;
+    fast_tile<WM, BK, NS, CIL>(A, B, C, M, N, K, a_shared, c, tm, tn, lds0, lds1, lds2, lds3, lds4, lds5);
+}
+
+// ===========================================================================
+// Grouped persistent kernel: many problems of different shapes in one launch.
+// ===========================================================================
+//
+// The problems' tiles form one list (problem by problem, each in the order of
+// the plain kernel); a workgroup takes the next tile index from a device
+// counter, finds its problem among the problem table's first-tile offsets,
+// runs the same tile code as the fast kernel (128 x 128, 32 receivers per
+// stage, 2-deep ring) and asks again until the list is exhausted.  The table
+// travels in the kernel arguments, so a captured graph replays it unchanged.
+struct GroupProblem {
+    const uint16_t *A;
+    const uint16_t *B;
+    float *C;
+    int M, N, K, a_shared;
+    int tiles_m, tiles_n;  // per channel
+    int first_tile;        // index of this problem's first tile in the list
+    int pad;
+};
+struct GroupArgs {
+    GroupProblem p[TCBF_GROUP_MAX];
+    int count, total_tiles;
+};
+
+template <int CIL>
+__global__ __launch_bounds__(256, 2) void cgemm_f16_group_kernel(const GroupArgs args,
+                                                                 unsigned int *__restrict__ counter) {
+    TCBF_FAST_LDS(2, 32, 2)
+    __shared__ int next_tile;
+    for (;;) {
+        if (threadIdx.x == 0) next_tile = (int)atomicAdd(counter, 1u);
+        // the index is visible, and every wave has finished the previous
+        // tile's LDS use before the next tile's loads land in the ring
+        lds_barrier();
+        const int t = __builtin_amdgcn_readfirstlane(next_tile);
+        if (t >= args.total_tiles) break;
+        int pi = 0;
+        for (int i = 1; i < args.count; ++i)
+            if (t >= args.p[i].first_tile) pi = i;
+        const GroupProblem &q = args.p[pi];
+        const int local = t - q.first_tile;
+        const int per_c = q.tiles_m * q.tiles_n;
+        const int c = local / per_c;
+        const int rem = local - c * per_c;
+        const int tn = rem / q.tiles_m, tm = rem - tn * q.tiles_m;
+        fast_tile<2, 32, 2, CIL>(q.A, q.B, q.C, q.M, q.N, q.K, q.a_shared, c, tm, tn, lds0, lds1, lds2, lds3, lds4,
+                                 lds5);
+        // next_tile is rewritten only after the tile's own barriers, which
+        // every wave passes after reading it
+    }
+}
+
+__global__ void group_reset_kernel(unsigned int *counter) { *counter = 0u; }
+
 typedef void (*KernFn)(const uint16_t *, const uint16_t *, float *, int64_t, int64_t, int64_t, int,
                        int, int, int64_t, int, int);
 typedef void (*FastFn)(const uint16_t *, const uint16_t *, float *, int, int, int, int, int, int, int);
@@ -702,6 +778,42 @@ hipError_t f16_launch(const Problem &p, const F16Config &cfg, const void *A, con
     hipLaunchKernelGGL(fn, dim3((uint32_t)nblocks), dim3(NT), 0, stream,
                        (const uint16_t *)A, (const uint16_t *)B, (float *)C, p.M, p.N, p.K,
                        p.a_shared, tiles_m, tiles_n, nblocks, (int)cfg.a_vec, (int)cfg.b_vec);
+    return hipGetLastError();
+}
+
+bool f16_group_problem_ok(const Problem &p) { return fast_ok(p); }
+
+int64_t f16_group_tiles(const Problem &p) { return p.batch * ((p.M + BM - 1) / BM) * ((p.N + BN - 1) / BN); }
+
+hipError_t f16_group_launch(const Problem *probs, const void *const *A, const void *const *B, void *const *C,
+                            const int *order, int count, int c_layout, int grid, unsigned int *counter,
+                            hipStream_t stream) {
+    GroupArgs args;
+    memset(&args, 0, sizeof(args));
+    int64_t first = 0;
+    for (int j = 0; j < count; ++j) {
+        const int i = order[j];
+        const Problem &p = probs[i];
+        GroupProblem &q = args.p[j];
+        q.A = (const uint16_t *)A[i];
+        q.B = (const uint16_t *)B[i];
+        q.C = (float *)C[i];
+        q.M = (int)p.M;
+        q.N = (int)p.N;
+        q.K = (int)p.K;
+        q.a_shared = p.a_shared;
+        q.tiles_m = (int)((p.M + BM - 1) / BM);
+        q.tiles_n = (int)((p.N + BN - 1) / BN);
+        q.first_tile = (int)first;
+        first += f16_group_tiles(p);
+    }
+    args.count = count;
+    args.total_tiles = (int)first;
+    hipLaunchKernelGGL(group_reset_kernel, dim3(1), dim3(1), 0, stream, counter);
+    if (c_layout == TCBF_INTERLEAVED)
+        hipLaunchKernelGGL(cgemm_f16_group_kernel<1>, dim3((uint32_t)grid), dim3(NT), 0, stream, args, counter);
+    else
+        hipLaunchKernelGGL(cgemm_f16_group_kernel<0>, dim3((uint32_t)grid), dim3(NT), 0, stream, args, counter);
     return hipGetLastError();
 }
 

@@ -1,7 +1,9 @@
 // C ABI of the beamforming library: plan creation (validation and kernel
 // choice, host only), execution (argument checks and one kernel launch), sign
-// packing, FP8 quantisation and steering weights.  No entry point throws,
-// aborts or allocates device memory.
+// packing, FP8 quantisation, steering weights and the grouped launch.  No
+// entry point throws, aborts or allocates device memory.
+#include <algorithm>
+#include <atomic>
 #include <new>
 #include <stdio.h>
 #include <string.h>
@@ -27,13 +29,21 @@ bool aligned8(const void *p) { return ((uintptr_t)p & 7u) == 0; }
 bool is_f8(int32_t dtype) { return dtype == TCBF_F8_E4M3 || dtype == TCBF_MXF8_E4M3; }
 bool is_src_type(int32_t t) { return t == TCBF_SRC_I8 || t == TCBF_SRC_F16 || t == TCBF_SRC_F32; }
 
+// Architecture check per device, remembered once it succeeded (plans are
+// created per job in a serving loop; reading the device properties each time
+// would dominate plan creation).
+constexpr int kMaxDevices = 64;
+std::atomic<int> g_device_ok[kMaxDevices];
+
 tcbf_status device_check(int device) {
     int count = 0;
     if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return TCBF_ERROR_DEVICE;
     if (device < 0 || device >= count) return TCBF_ERROR_INVALID_VALUE;
+    if (device < kMaxDevices && g_device_ok[device].load(std::memory_order_acquire) == 1) return TCBF_SUCCESS;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) != hipSuccess) return TCBF_ERROR_DEVICE;
     if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return TCBF_ERROR_NOT_SUPPORTED;
+    if (device < kMaxDevices) g_device_ok[device].store(1, std::memory_order_release);
     return TCBF_SUCCESS;
 }
 
@@ -245,6 +255,46 @@ tcbf_status tcbf_steering_weights(const double *positions, const double *directi
     if (tcbf::steering_blocks(batch, M, K) >= kMaxIndex) return TCBF_ERROR_NOT_SUPPORTED;
     hipError_t e = tcbf::steering_launch(positions, directions, frequencies, wave_speed, batch, M, K, out_type, W,
                                          (hipStream_t)stream);
+    return e == hipSuccess ? TCBF_SUCCESS : TCBF_ERROR_DEVICE;
+}
+
+tcbf_status tcbf_group_execute(int32_t device, int32_t dtype, int32_t c_layout, const tcbf_group_problem *problems,
+                               int32_t count, void *workspace, void *stream) {
+    if (problems == nullptr || workspace == nullptr) return TCBF_ERROR_INVALID_VALUE;
+    if (dtype != TCBF_F16 || !is_layout(c_layout)) return TCBF_ERROR_INVALID_VALUE;
+    if (count < 1 || count > TCBF_GROUP_MAX) return TCBF_ERROR_INVALID_VALUE;
+    if (!aligned16(workspace)) return TCBF_ERROR_INVALID_VALUE;
+    tcbf::Problem probs[TCBF_GROUP_MAX];
+    const void *A[TCBF_GROUP_MAX];
+    const void *B[TCBF_GROUP_MAX];
+    void *C[TCBF_GROUP_MAX];
+    int order[TCBF_GROUP_MAX];
+    int64_t total = 0;
+    for (int i = 0; i < count; ++i) {
+        const tcbf_group_problem &g = problems[i];
+        if (g.A == nullptr || g.B == nullptr || g.C == nullptr || g.reserved != 0) return TCBF_ERROR_INVALID_VALUE;
+        if (!aligned16(g.A) || !aligned16(g.B) || !aligned16(g.C)) return TCBF_ERROR_INVALID_VALUE;
+        if (g.batch < 1 || g.M < 1 || g.N < 1 || g.K < 1) return TCBF_ERROR_INVALID_VALUE;
+        if (g.K % 8 != 0 || g.N % 8 != 0) return TCBF_ERROR_INVALID_VALUE;
+        probs[i] = tcbf::Problem{g.batch, g.M, g.N, g.K, TCBF_PLANAR, TCBF_PLANAR, c_layout, g.a_shared != 0};
+        if (!tcbf::f16_group_problem_ok(probs[i])) return TCBF_ERROR_NOT_SUPPORTED;
+        total += tcbf::f16_group_tiles(probs[i]);
+        if (total >= kMaxIndex) return TCBF_ERROR_NOT_SUPPORTED;
+        A[i] = g.A;
+        B[i] = g.B;
+        C[i] = g.C;
+        order[i] = i;
+    }
+    // longest tiles (most receivers) first, so the list ends on short tiles
+    std::stable_sort(order, order + count, [&](int a, int b) { return probs[a].K > probs[b].K; });
+    tcbf_status st = current_device_is(device);
+    if (st != TCBF_SUCCESS) return st;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1)
+        return TCBF_ERROR_DEVICE;
+    const int grid = (int)std::min<int64_t>(total, 2 * (int64_t)cus);
+    hipError_t e = tcbf::f16_group_launch(probs, A, B, C, order, count, c_layout, grid, (unsigned int *)workspace,
+                                          (hipStream_t)stream);
     return e == hipSuccess ? TCBF_SUCCESS : TCBF_ERROR_DEVICE;
 }
 

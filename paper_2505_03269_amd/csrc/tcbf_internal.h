@@ -28,6 +28,14 @@ const char *f16_kernel_name(const F16Config &cfg);
 hipError_t f16_launch(const Problem &p, const F16Config &cfg, const void *A, const void *B,
                       void *C, hipStream_t stream);
 
+// Grouped persistent fp16 launch: problems of different shapes share one
+// launch; `order` lists the problems in queue order.
+bool f16_group_problem_ok(const Problem &p);
+int64_t f16_group_tiles(const Problem &p);
+hipError_t f16_group_launch(const Problem *probs, const void *const *A, const void *const *B, void *const *C,
+                            const int *order, int count, int c_layout, int grid, unsigned int *counter,
+                            hipStream_t stream);
+
 // FP8 modes (e4m3 codes in, fp32 out): per-row fp32 scales or per-32-block
 // E8M0 scales (mx).  Operands are receiver-contiguous with row pitch f8_kp(K).
 struct F8Config {

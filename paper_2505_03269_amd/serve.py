@@ -1,0 +1,261 @@
+"""Serving loop: continuous batching of beamforming jobs on one GPU.
+
+A job asks for B = W . X with one of the resident weight sets (fp16, FP8 or
+1-bit) and its own data X of N samples.  The server
+
+  * keeps every weight set resident on the device in the form its kernel
+    reads (fp16 planes; e4m3 codes with per-row scales; packed sign words),
+    built once at start-up;
+  * admits arrived jobs in arrival order while the device-memory budget and
+    the slot count allow (a job's budget is its input and output buffers);
+  * launches the admitted jobs as soon as a stream is free: the fp16 jobs of
+    a batch go into one grouped persistent launch (tcbf_group_execute), FP8 and
+    1-bit jobs into their own plan launches on the same stream;
+  * runs several streams, so a batch formed while others are still on the
+    GPU overlaps with them, and frees a job's memory and slot when the host
+    sees its batch complete (an event query, no blocking wait);
+  * reports per-job latency (completion seen by the host minus arrival, both
+    on the host clock, queueing included), p50 / p99, and throughput as useful
+    operations (8 per complex multiply-accumulate) over the makespan.
+
+Every product runs in the library; this module only schedules.
+"""
+import time
+
+import numpy as np
+
+from . import (F8_E4M3, F16, INT1, GROUP_MAX, GROUP_WORKSPACE_BYTES, PLANAR, Plan, group_execute, pack1bit,
+               quantize_e4m3)
+
+DTYPE_NAMES = {F16: "f16", F8_E4M3: "f8", INT1: "int1"}
+
+
+class WeightSet:
+    """One resident weight matrix (M beams x K receivers) in its kernel's form."""
+
+    def __init__(self, wid, dtype, M, K, seed, device):
+        import torch
+        self.wid, self.dtype, self.M, self.K = wid, dtype, M, K
+        g = torch.Generator(device=device)
+        g.manual_seed(seed)
+        # unit-modulus phasors (steering-like weights), fp16
+        phi = torch.rand((M, K), device=device, generator=g, dtype=torch.float64) * (2 * np.pi)
+        W16 = torch.stack([torch.cos(phi), torch.sin(phi)])[None].to(torch.float16).contiguous()
+        self.scale = None
+        if dtype == F16:
+            self.A = W16
+        elif dtype == F8_E4M3:
+            self.A, self.scale = quantize_e4m3(W16, k_major=True, block=0)
+        else:
+            self.A = pack1bit(W16, k_major=True)
+        self.bytes = self.A.numel() * self.A.element_size() + (0 if self.scale is None else
+                                                               self.scale.numel() * self.scale.element_size())
+
+
+class Job:
+    __slots__ = ("jid", "arrival", "dtype", "wid", "N", "seed", "t_done", "out", "X", "xs", "nbytes", "M", "K")
+
+    def __init__(self, jid, arrival, dtype, wid, N, seed):
+        self.jid, self.arrival, self.dtype, self.wid, self.N, self.seed = jid, arrival, dtype, wid, N, seed
+        self.t_done = None
+        self.out = self.X = self.xs = None
+
+    @property
+    def ops(self):
+        return 8.0 * self.M * self.N * self.K
+
+
+def job_input(job, device):
+    """The job's data X [1, 2, K, N] fp16, drawn from its seed (8-bit range)."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(job.seed))
+    return torch.randint(-127, 128, (1, 2, job.K, job.N), device=device, generator=g).to(torch.float16)
+
+
+class Server:
+    def __init__(self, pool_per_dtype=16, dtypes=(F16, F8_E4M3, INT1), budget_frac=0.5, budget_bytes=None,
+                 streams=3, max_slots=64, seed=0, device=0):
+        import torch
+        self.device = "cuda:%d" % device
+        self.dev_index = device
+        torch.cuda.set_device(device)
+        rng = np.random.default_rng(np.random.SeedSequence([5, 0, seed]))
+        self.pool = {}
+        for d in dtypes:
+            for i in range(pool_per_dtype):
+                M = int(-(-rng.integers(128, 4097) // 8) * 8)
+                K = int(-(-rng.integers(64, 2049) // 8) * 8)
+                self.pool[(d, i)] = WeightSet(i, d, M, K, seed * 1000 + d * 100 + i, self.device)
+        self.dtypes = tuple(dtypes)
+        self.pool_per_dtype = pool_per_dtype
+        if budget_bytes is None:
+            free, _ = torch.cuda.mem_get_info(device)
+            budget_bytes = int(free * budget_frac)
+        self.budget = budget_bytes
+        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(streams)]
+        self.workspaces = [torch.empty(GROUP_WORKSPACE_BYTES, dtype=torch.uint8, device=self.device)
+                           for _ in range(streams)]
+        self.max_slots = max_slots
+        self.plans = {}
+
+    # -- jobs ---------------------------------------------------------------
+    def make_jobs(self, count, rate, seed=1):
+        """`count` jobs with Poisson arrivals at `rate` jobs/s (rate None: all at
+        t = 0), dtype and weight set uniform, N ~ U[256, 8192] (multiple of 8)."""
+        rng = np.random.default_rng(np.random.SeedSequence([5, 1, seed]))
+        gaps = rng.exponential(1.0 / rate, count) if rate else np.zeros(count)
+        arrivals = np.cumsum(gaps) - (gaps[0] if rate else 0.0)
+        jobs = []
+        for j in range(count):
+            d = self.dtypes[rng.integers(len(self.dtypes))]
+            w = int(rng.integers(self.pool_per_dtype))
+            N = int(-(-rng.integers(256, 8193) // 8) * 8)
+            job = Job(j, float(arrivals[j]), d, w, N, int(rng.integers(2**31)))
+            ws = self.pool[(d, w)]
+            job.M, job.K = ws.M, ws.K
+            job.nbytes = self.job_bytes(job)
+            jobs.append(job)
+        return jobs
+
+    def job_bytes(self, job):
+        M, N, K = job.M, job.N, job.K
+        b = 2 * K * N * 2 + 8 * M * N           # fp16 data in, fp32 complex out
+        if job.dtype == F8_E4M3:
+            b += 2 * N * (-(-K // 32) * 32) + 4 * N
+        elif job.dtype == INT1:
+            b += 8 * N * (-(-K // 32))
+        return b
+
+    def _plan(self, dtype, M, N, K):
+        key = (dtype, M, N, K)
+        p = self.plans.get(key)
+        if p is None:
+            p = Plan(1, M, N, K, dtype, device=self.dev_index)
+            self.plans[key] = p
+        return p
+
+    # -- one batch ------------------------------------------------------------
+    def launch(self, batch, si):
+        """Enqueue the jobs of one batch on stream si; returns its done-event."""
+        import torch
+        s = self.streams[si]
+        with torch.cuda.stream(s):
+            f16 = []
+            for job in batch:
+                ws = self.pool[(job.dtype, job.wid)]
+                X = job_input(job, self.device)
+                job.out = torch.empty((1, 2, job.M, job.N), dtype=torch.float32, device=self.device)
+                if job.dtype == F16:
+                    job.X = X
+                    f16.append((ws.A, X, job.out))
+                elif job.dtype == F8_E4M3:
+                    job.X, job.xs = quantize_e4m3(X, k_major=False, block=0)
+                    self._plan(F8_E4M3, job.M, job.N, job.K).execute(ws.A, job.X, job.out, ws.scale, job.xs)
+                else:
+                    job.X = pack1bit(X, k_major=False)
+                    self._plan(INT1, job.M, job.N, job.K).execute(ws.A, job.X, job.out)
+            for i in range(0, len(f16), GROUP_MAX):
+                group_execute(f16[i:i + GROUP_MAX], workspace=self.workspaces[si], device=self.dev_index)
+            ev = torch.cuda.Event()
+            ev.record(s)
+        return ev
+
+    # -- the loop -------------------------------------------------------------
+    def run(self, jobs, keep_outputs=False, max_batch=GROUP_MAX):
+        """Serve `jobs` in real time (their arrival times are relative to the
+        start of the call).  Returns a summary dict; job.t_done is filled."""
+        import torch
+        torch.cuda.synchronize()
+        n = len(jobs)
+        pending = []          # arrived, not yet admitted
+        admitted = []         # admitted, not yet launched
+        inflight = []         # (stream index, event, jobs)
+        busy = [0] * len(self.streams)
+        used_bytes, used_slots = 0, 0
+        nxt, done = 0, 0
+        self.batch_sizes, self.max_inflight = [], 0
+        t0 = time.perf_counter()
+        while done < n:
+            now = time.perf_counter() - t0
+            while nxt < n and jobs[nxt].arrival <= now:
+                pending.append(jobs[nxt])
+                nxt += 1
+            # completions
+            still = []
+            for si, ev, batch in inflight:
+                if ev.query():
+                    t = time.perf_counter() - t0
+                    for job in batch:
+                        job.t_done = t
+                        used_bytes -= job.nbytes
+                        used_slots -= 1
+                        if not keep_outputs:
+                            job.out = None
+                        job.X = job.xs = None
+                    done += len(batch)
+                    busy[si] -= 1
+                else:
+                    still.append((si, ev, batch))
+            inflight = still
+            # admission in arrival order
+            while pending and used_slots < self.max_slots and used_bytes + pending[0].nbytes <= self.budget:
+                job = pending.pop(0)
+                used_bytes += job.nbytes
+                used_slots += 1
+                admitted.append(job)
+            if pending and used_slots == 0 and pending[0].nbytes > self.budget:
+                raise RuntimeError("job %d needs more than the memory budget" % pending[0].jid)
+            # launch on a free stream
+            if admitted:
+                si = min(range(len(self.streams)), key=lambda i: busy[i])
+                if busy[si] == 0:
+                    batch, admitted = admitted[:max_batch], admitted[max_batch:]
+                    ev = self.launch(batch, si)
+                    busy[si] += 1
+                    inflight.append((si, ev, batch))
+                    self.batch_sizes.append(len(batch))
+                    self.max_inflight = max(self.max_inflight, len(inflight))
+                    continue
+            if not inflight and not admitted and nxt < n:
+                wait = jobs[nxt].arrival - (time.perf_counter() - t0)
+                if wait > 2e-4:
+                    time.sleep(wait - 1e-4)
+        makespan = max(j.t_done for j in jobs) - min(j.arrival for j in jobs)
+        lat = np.array([j.t_done - j.arrival for j in jobs])
+        ops = sum(j.ops for j in jobs)
+        return {"jobs": n, "makespan_s": makespan, "tops": ops / makespan / 1e12,
+                "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                "mean_ms": float(lat.mean() * 1e3),
+                "by_dtype": {DTYPE_NAMES[d]: int(sum(1 for j in jobs if j.dtype == d)) for d in self.dtypes}}
+
+    def run_alone(self, job):
+        """The job's product on its own (one plain launch), for comparison."""
+        import torch
+        ws = self.pool[(job.dtype, job.wid)]
+        X = job_input(job, self.device)
+        out = torch.empty((1, 2, job.M, job.N), dtype=torch.float32, device=self.device)
+        if job.dtype == F16:
+            self._plan(F16, job.M, job.N, job.K).execute(ws.A, X, out)
+        elif job.dtype == F8_E4M3:
+            Xq, xs = quantize_e4m3(X, k_major=False, block=0)
+            self._plan(F8_E4M3, job.M, job.N, job.K).execute(ws.A, Xq, out, ws.scale, xs)
+        else:
+            self._plan(INT1, job.M, job.N, job.K).execute(ws.A, pack1bit(X, k_major=False), out)
+        torch.cuda.synchronize()
+        return out
+
+
+def serve_benchmark(warmup=1000, measured=10000, load=0.8, seed=0, device=0, server=None):
+    """Closed-loop capacity run, then an open-loop Poisson run at `load` x
+    capacity; returns both summaries."""
+    srv = server or Server(seed=seed, device=device)
+    warm = srv.make_jobs(warmup, None, seed=seed + 100)
+    srv.run(warm)
+    closed_jobs = srv.make_jobs(measured, None, seed=seed + 200)
+    closed = srv.run(closed_jobs)
+    capacity = measured / closed["makespan_s"]
+    open_jobs = srv.make_jobs(measured, load * capacity, seed=seed + 300)
+    opened = srv.run(open_jobs)
+    return {"closed_loop": closed, "capacity_jobs_per_s": capacity, "load": load, "open_loop": opened,
+            "budget_bytes": srv.budget, "streams": len(srv.streams), "max_slots": srv.max_slots}

@@ -1,0 +1,146 @@
+"""Autotuner: choose the fastest kernel variant for one problem shape by timing
+every valid candidate on the device, and remember the choice in a JSON cache.
+
+The paper tunes its kernel's compile-time parameters per GPU and shape with an
+external tuner and ships the best points (Sec. IV-A, Table 3).  Here the
+candidate configurations are the variants compiled into the library; the
+sweep starts from the variant closest to Table 3's MI300X/MI300A float16 point
+(128 x 128 complex outputs per workgroup, 64-row wave tiles), then tries the
+rest.  Timing uses HIP events on the stream the library launches on, over
+inputs resident on the device; the cache key is the device architecture, the
+dtype and the exact problem shape and layouts.
+
+Only timing and bookkeeping happen here; every product runs in the library.
+"""
+import json
+import os
+
+from . import F16, F8_E4M3, INT1, MXF8_E4M3, PLANAR, Plan, TcbfError
+
+# candidate variants per dtype, seed first
+CANDIDATES = {
+    F16: [2, 6, 3, 4, 5, 7, 1],      # 2: Table 3's MI300X point (128 x 128 tile, 2 x 2 waves of 64 x 64)
+    F8_E4M3: [1, 2],
+    MXF8_E4M3: [1, 2],
+    INT1: [1, 2],
+}
+
+
+def cache_key(arch, dtype, batch, M, N, K, c_layout=PLANAR, a_shared=False):
+    return "%s|dtype%d|%dx%dx%dx%d|c%d|s%d" % (arch, int(dtype), batch, M, N, K, int(c_layout), int(bool(a_shared)))
+
+
+def load_cache(path):
+    if path is None or not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        return json.load(f)
+
+
+def save_cache(path, cache):
+    if path is None:
+        return
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def valid_candidates(batch, M, N, K, dtype, c_layout=PLANAR, a_shared=False, device=0):
+    """Variants the library accepts for this problem (plan creation succeeds)."""
+    out = []
+    for v in CANDIDATES[dtype]:
+        try:
+            Plan(batch, M, N, K, dtype, c_layout=c_layout, a_shared=a_shared, variant=v, device=device)
+        except TcbfError:
+            continue
+        out.append(v)
+    return out
+
+
+def _device_inputs(plan):
+    import torch
+    dev = "cuda:%d" % plan.device
+    g = torch.Generator(device=dev)
+    g.manual_seed(1234)
+    ta, tb, _ = plan._dtypes()
+    if plan.dtype == INT1:
+        A = torch.randint(-2**31, 2**31 - 1, plan.shape_a(), dtype=torch.int32, device=dev, generator=g)
+        B = torch.randint(-2**31, 2**31 - 1, plan.shape_b(), dtype=torch.int32, device=dev, generator=g)
+        kw = (plan.K + 31) // 32
+        if plan.K % 32:
+            mask = (1 << (plan.K % 32)) - 1
+            A[..., kw - 1] &= mask
+            B[..., kw - 1] &= mask
+        return A, B, None, None
+    if plan.dtype in (F8_E4M3, MXF8_E4M3):
+        A = torch.randint(0, 0x7F, plan.shape_a(), dtype=torch.uint8, device=dev, generator=g)
+        B = torch.randint(0, 0x7F, plan.shape_b(), dtype=torch.uint8, device=dev, generator=g)
+        if plan.dtype == F8_E4M3:
+            sa = torch.ones(plan.shape_a_scale(), dtype=torch.float32, device=dev)
+            sb = torch.ones(plan.shape_b_scale(), dtype=torch.float32, device=dev)
+        else:
+            sa = torch.full(plan.shape_a_scale(), 127, dtype=torch.uint8, device=dev)
+            sb = torch.full(plan.shape_b_scale(), 127, dtype=torch.uint8, device=dev)
+        return A, B, sa, sb
+    A = torch.randn(plan.shape_a(), device=dev, generator=g).to(ta)
+    B = torch.randn(plan.shape_b(), device=dev, generator=g).to(tb)
+    return A, B, None, None
+
+
+def measure(plan, reps=10, warmup=2, inputs=None):
+    """Mean milliseconds per launch of `plan` (HIP events on the current stream)."""
+    import torch
+    A, B, sa, sb = inputs if inputs is not None else _device_inputs(plan)
+    C = plan.empty_output()
+    run = (lambda: plan.execute(A, B, C, sa, sb)) if sa is not None else (lambda: plan.execute(A, B, C))
+    for _ in range(warmup):
+        run()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for _ in range(reps):
+        run()
+    t1.record(stream)
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1) / reps
+
+
+def tune(batch, M, N, K, dtype=F16, c_layout=PLANAR, a_shared=False, cache_path=None, reps=10, warmup=2,
+         device=0, arch=None, measure_fn=None, force=False):
+    """Time every valid variant (seed first) and return
+    {"variant": best, "ms": {variant: ms}}; cached under cache_path."""
+    if arch is None:
+        import torch
+        arch = torch.cuda.get_device_properties(device).gcnArchName.split(":")[0]
+    key = cache_key(arch, dtype, batch, M, N, K, c_layout, a_shared)
+    cache = load_cache(cache_path)
+    if key in cache and not force:
+        return cache[key]
+    cands = valid_candidates(batch, M, N, K, dtype, c_layout, a_shared, device)
+    if not cands:
+        raise TcbfError(2, "no kernel variant accepts this problem")
+    timings = {}
+    inputs = None
+    for v in cands:
+        plan = Plan(batch, M, N, K, dtype, c_layout=c_layout, a_shared=a_shared, variant=v, device=device)
+        if measure_fn is not None:
+            ms = measure_fn(plan)
+        else:
+            if inputs is None:
+                inputs = _device_inputs(plan)
+            ms = measure(plan, reps, warmup, inputs)
+        timings[str(v)] = round(float(ms), 5)
+    best = min(cands, key=lambda v: timings[str(v)])
+    entry = {"variant": best, "ms": timings, "seed": cands[0]}
+    cache = load_cache(cache_path)  # re-read: another process may have added keys
+    cache[key] = entry
+    save_cache(cache_path, cache)
+    return entry
+
+
+def tuned_plan(batch, M, N, K, dtype=F16, c_layout=PLANAR, a_shared=False, cache_path=None, device=0, **kw):
+    """A Plan with the cached (or freshly tuned) variant for this shape."""
+    entry = tune(batch, M, N, K, dtype, c_layout, a_shared, cache_path=cache_path, device=device, **kw)
+    return Plan(batch, M, N, K, dtype, c_layout=c_layout, a_shared=a_shared, variant=entry["variant"], device=device)

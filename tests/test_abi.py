@@ -135,6 +135,25 @@ def test_steering_argument_checks():
     assert L.tcbf_steering_weights(p, p, p, 3e8, 1, 1, 1, 1, ctypes.c_void_p(addr + 8), None) == 1
 
 
+def test_group_argument_checks():
+    L = tcbf.lib()
+    buf = ctypes.create_string_buffer(1024)
+    addr = (ctypes.addressof(buf) + 15) & ~15
+    p = ctypes.c_void_p(addr)
+    good = tcbf.GroupProblem(addr, addr, addr, 1, 8, 8, 8, 0, 0)
+    one = (tcbf.GroupProblem * 1)(good)
+    assert L.tcbf_group_execute(0, tcbf.F16, 0, None, 1, p, None) == 1                 # no problems
+    assert L.tcbf_group_execute(0, tcbf.F16, 0, one, 0, p, None) == 1                  # count 0
+    assert L.tcbf_group_execute(0, tcbf.F16, 0, one, tcbf.GROUP_MAX + 1, p, None) == 1
+    assert L.tcbf_group_execute(0, tcbf.INT1, 0, one, 1, p, None) == 1                 # fp16 only
+    assert L.tcbf_group_execute(0, tcbf.F16, 0, one, 1, ctypes.c_void_p(addr + 4), None) == 1
+    for bad in (dict(K=12), dict(N=4), dict(batch=0), dict(reserved=1), dict(A=addr + 2)):
+        d = dict(A=addr, B=addr, C=addr, batch=1, M=8, N=8, K=8, a_shared=0, reserved=0)
+        d.update(bad)
+        arr = (tcbf.GroupProblem * 1)(tcbf.GroupProblem(**d))
+        assert L.tcbf_group_execute(0, tcbf.F16, 0, arr, 1, p, None) == 1, bad
+
+
 def test_valid_descriptor_without_gpu_reports_device():
     import torch
     if torch.cuda.is_available():

@@ -1,0 +1,132 @@
+"""Grouped persistent launch (tcbf_group_execute) and HIP-graph capture.
+
+The grouped kernel runs the same tile code as the plain fast kernel, so every
+problem's output must equal its own single plan's output bit for bit, whatever
+else shares the launch; one problem is also checked against the FP64 oracle.
+Graph tests capture launches, replay them several times with eager work and
+synchronisations between replays, and compare every replay with the eager
+result."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+from gpu_util import check_fp_full, log, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_2505_03269_amd as tcbf  # noqa: E402
+
+# (batch, M, N, K, shared W): uneven shapes, ragged tiles, one shared-W problem
+MIX = [(1, 300, 264, 576), (2, 128, 128, 64), (1, 1000, 40, 8), (3, 200, 392, 200), (1, 64, 1024, 2048),
+       (2, 513, 136, 96), (4, 96, 256, 576), (1, 130, 8, 1032)]
+
+
+def make(seed, batch, M, N, K, shared=False, layout=tcbf.PLANAR):
+    W, X = wl.random_f16_case(seed, batch, M, N, K, shared_w=shared)
+    Cshape = (batch, 2, M, N) if layout == tcbf.PLANAR else (batch, M, N, 2)
+    return W, X, to_dev(W), to_dev(X), torch.full(Cshape, float("nan"), device="cuda:0")
+
+
+def single(Wd, Xd, batch, M, N, K, shared=False, layout=tcbf.PLANAR):
+    plan = tcbf.Plan(batch, M, N, K, tcbf.F16, c_layout=layout, a_shared=shared)
+    C = plan.empty_output()
+    plan.execute(Wd, Xd, C)
+    return C
+
+
+@pytest.mark.parametrize("layout", [tcbf.PLANAR, tcbf.INTERLEAVED])
+def test_group_equals_single_plans(layout):
+    cases = []
+    for i, (b, M, N, K) in enumerate(MIX):
+        shared = i == 3
+        cases.append((b, M, N, K, shared) + make(40 + i, b, M, N, K, shared, layout))
+    log("group of %d problems, layout %d" % (len(cases), layout))
+    tcbf.group_execute([(c[7], c[8], c[9], c[4]) for c in cases], c_layout=layout)
+    torch.cuda.synchronize()
+    for (b, M, N, K, shared, W, X, Wd, Xd, C) in cases:
+        ref = single(Wd, Xd, b, M, N, K, shared, layout)
+        torch.cuda.synchronize()
+        got = C.cpu().numpy()
+        assert not np.isnan(got).any(), (b, M, N, K)
+        assert np.array_equal(got, ref.cpu().numpy()), (b, M, N, K)
+    # and one against the oracle
+    b, M, N, K, shared, W, X, Wd, Xd, C = cases[0]
+    Ch = C.cpu().numpy().astype(np.float64)
+    got = Ch[:, 0] + 1j * Ch[:, 1] if layout == tcbf.PLANAR else Ch[..., 0] + 1j * Ch[..., 1]
+    Wc, Xc = wl.planar_to_complex(W), wl.planar_to_complex(X)
+    check_fp_full(got, oracle.cgemm(Wc, Xc), np.matmul(np.abs(Wc), np.abs(Xc)), K)
+
+
+def test_group_single_problem_and_full_list():
+    """One problem alone, and a list of GROUP_MAX small problems."""
+    b, M, N, K = 2, 256, 256, 128
+    W, X, Wd, Xd, C = make(60, b, M, N, K)
+    tcbf.group_execute([(Wd, Xd, C)])
+    ref = single(Wd, Xd, b, M, N, K)
+    torch.cuda.synchronize()
+    assert np.array_equal(C.cpu().numpy(), ref.cpu().numpy())
+    probs, refs = [], []
+    for i in range(tcbf.GROUP_MAX):
+        M, N, K = 8 + 8 * i, 16 + 8 * (i % 5), 8 * (1 + i % 7)
+        W, X, Wd, Xd, C = make(70 + i, 1, M, N, K)
+        probs.append((Wd, Xd, C))
+        refs.append(single(Wd, Xd, 1, M, N, K))
+    tcbf.group_execute(probs)
+    torch.cuda.synchronize()
+    for (Wd, Xd, C), r in zip(probs, refs):
+        assert np.array_equal(C.cpu().numpy(), r.cpu().numpy())
+
+
+def test_graph_capture_replays_match_eager():
+    """Capture a grouped launch and a plain launch in one graph; change the
+    inputs eagerly between replays; every replay must equal an eager run on
+    the current inputs."""
+    shapes = [(2, 200, 264, 576), (1, 96, 128, 64), (3, 128, 136, 200)]
+    cases = [make(80 + i, *s) for i, s in enumerate(shapes)]
+    W1, X1, Wd1, Xd1, _ = make(90, 2, 130, 128, 96)
+    plan = tcbf.Plan(2, 130, 128, 96, tcbf.F16)
+    C1 = plan.empty_output()
+    ws = torch.empty(tcbf.GROUP_WORKSPACE_BYTES, dtype=torch.uint8, device="cuda:0")
+    probs = [(c[2], c[3], c[4]) for c in cases]
+    # warm up outside the capture, then capture on a side stream
+    tcbf.group_execute(probs, workspace=ws)
+    plan.execute(Wd1, Xd1, C1)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            tcbf.group_execute(probs, workspace=ws)
+            plan.execute(Wd1, Xd1, C1)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(5)
+    for rep in range(4):
+        # eager work between replays: new input values in the same buffers
+        for (_, _, Wd, Xd, _) in cases + [(None, None, Wd1, Xd1, None)]:
+            Xd.copy_(torch.randint(-127, 128, Xd.shape, device="cuda:0", generator=gen).half())
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for (W, X, Wd, Xd, C), (b, M, N, K) in zip(cases, shapes):
+            ref = single(Wd, Xd, b, M, N, K)
+            torch.cuda.synchronize()
+            assert np.array_equal(C.cpu().numpy(), ref.cpu().numpy()), "replay %d" % rep
+        ref1 = single(Wd1, Xd1, 2, 130, 128, 96)
+        torch.cuda.synchronize()
+        assert np.array_equal(C1.cpu().numpy(), ref1.cpu().numpy()), "replay %d" % rep
+
+
+def test_group_rejects_bad_problems():
+    W, X, Wd, Xd, C = make(99, 1, 64, 64, 64)
+    with pytest.raises(ValueError):
+        tcbf.group_execute([])
+    with pytest.raises(ValueError):
+        tcbf.group_execute([(Wd, Xd, C[:, :, :32])])
+    W2, X2, Wd2, Xd2, C2 = make(98, 1, 64, 60, 64)       # N not a multiple of 8
+    with pytest.raises(tcbf.TcbfError):
+        tcbf.group_execute([(Wd2, Xd2, C2)])

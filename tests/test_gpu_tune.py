@@ -1,0 +1,45 @@
+"""Autotuner on the device: it times every valid variant, caches the fastest
+and hands back a plan that uses it."""
+import numpy as np
+import pytest
+
+import workloads as wl
+from gpu_util import to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+import paper_2505_03269_amd as tcbf  # noqa: E402
+from paper_2505_03269_amd import tune  # noqa: E402
+
+
+def test_tune_picks_a_measured_variant_and_caches(tmp_path):
+    path = str(tmp_path / "tune.json")
+    e = tune.tune(2, 256, 256, 192, tcbf.F16, cache_path=path, reps=3, warmup=1)
+    assert str(e["variant"]) in e["ms"] and e["seed"] == 2
+    assert set(e["ms"]) == {"1", "2", "3", "4", "5", "6", "7"}
+    assert e["ms"][str(e["variant"])] == min(e["ms"].values())
+    cache = tune.load_cache(path)
+    assert len(cache) == 1 and list(cache.values())[0] == e
+    # a cached entry is used as is (no new timing)
+    key = list(cache)[0]
+    cache[key]["variant"] = 5
+    tune.save_cache(path, cache)
+    plan = tune.tuned_plan(2, 256, 256, 192, tcbf.F16, cache_path=path)
+    assert plan.info()["variant"] == 5
+    # and the tuned plan computes the same result as the default one
+    W, X = wl.random_f16_case(3, 2, 256, 256, 192)
+    A, B = to_dev(W), to_dev(X)
+    C1 = plan.empty_output()
+    plan.execute(A, B, C1)
+    d = tcbf.Plan(2, 256, 256, 192, tcbf.F16)
+    C2 = d.empty_output()
+    d.execute(A, B, C2)
+    torch.cuda.synchronize()
+    assert np.array_equal(C1.cpu().numpy(), C2.cpu().numpy())
+
+
+@pytest.mark.parametrize("dtype", [tcbf.F8_E4M3, tcbf.MXF8_E4M3, tcbf.INT1])
+def test_tune_other_dtypes(tmp_path, dtype):
+    e = tune.tune(1, 256, 256, 512, dtype, cache_path=str(tmp_path / "t.json"), reps=2, warmup=1)
+    assert set(e["ms"]) == {"1", "2"}

@@ -28,6 +28,9 @@ Workload recipes (synthetic stand-ins; no instrument data is used):
   C4  ultrasound FP16: 1 ch, M=32768 voxels, K=8192, N=256 frames; W re, im
       ~ N(0, 1) (Rayleigh(1) magnitude, uniform phase) rounded to fp16; X re,
       im ~ N(0, 512^2) rounded and clipped to [-2048, 2047] (12-bit range).
+  C5  served mixed stream: job shapes M ~ U[128, 4096], K ~ U[64, 2048],
+      N ~ U[256, 8192] (integers; rounded up to multiples of 8 where a kernel
+      needs it), see mixed_shapes().
 """
 import numpy as np
 
@@ -193,3 +196,16 @@ def generate_c3(batch=64, threads=8):
         W[c], X[c] = c3_channel(c, M, K, N)
     _parallel(one, batch, threads)
     return W, X
+
+
+# ---- C5 shapes -------------------------------------------------------------
+
+def mixed_shapes(seed, count, align=8):
+    """`count` job shapes (M, N, K) drawn from the served-stream distribution,
+    each rounded up to a multiple of `align`."""
+    g = rng(5, 3, seed)
+    up = lambda v: int(-(-int(v) // align) * align)  # noqa: E731
+    M = g.integers(128, 4097, count)
+    K = g.integers(64, 2049, count)
+    N = g.integers(256, 8193, count)
+    return [(up(m), up(n), up(k)) for m, n, k in zip(M, N, K)]
