@@ -1,7 +1,8 @@
 #!/usr/bin/env python3
 """Benchmark of the batched complex beamforming product on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-secondary] [--sweep]
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline] [--no-secondary]
+                    [--no-serving] [--sweep]
 
 One step = one tcbf_execute of the radio-astronomy workload (256 channels,
 M=1024 beams, K=576 receivers, N=4096 samples, fp16 in, fp32 complex out),
@@ -39,12 +40,20 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash(name):
-    p = os.path.join(ROOT, "paper_2505_03269_amd", "csrc", name)
-    return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
+# the sources each profiled kernel is compiled from (hashed together, in order)
+KERNEL_SOURCES = {
+    "cgemm_f16_fast_kernel": ("cgemm_f16.hip", "tcbf_tile.h", "tcbf_internal.h"),
+}
 
 
-def recorded_traffic(kernel, source):
+def kernel_source_hash(kernel):
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES[kernel]:
+        h.update(open(os.path.join(ROOT, "paper_2505_03269_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(kernel):
     """HBM bytes per launch from the committed rocprofv3 counter summary
     (profiles/hbm_traffic_<kernel>.txt, "key: value" lines), or None when there
     is none or the kernel source changed since the counters were taken."""
@@ -56,7 +65,7 @@ def recorded_traffic(kernel, source):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             rec[k.strip()] = v.strip()
-    if rec.get("kernel_source_sha256_16") != kernel_source_hash(source):
+    if rec.get("kernel_source_sha256_16") != kernel_source_hash(kernel):
         return None
     try:
         return float(rec["traffic_bytes_per_launch"])
@@ -139,7 +148,7 @@ def bench_c2(steps, warmup):
     return W, X, info, ms, tops
 
 
-def bench_secondary(steps):
+def bench_secondary(steps, serving=True):
     """1-bit config (both variants), ultrasound-shaped fp16, sign packing."""
     import torch
     import paper_2505_03269_amd as tcbf
@@ -260,7 +269,8 @@ def bench_secondary(steps):
                              "frac": round(ops / (ms_g * 1e-3) / 1e12 / PEAK_F16_TFLOPS, 4)}})
     del probs, plans
     torch.cuda.empty_cache()
-    out.append(bench_serving())
+    if serving:
+        out.append(bench_serving())
     return out
 
 
@@ -335,6 +345,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--no-serving", action="store_true", help="skip the served-stream line (for kernel traces)")
     ap.add_argument("--sweep", action="store_true",
                     help="print one JSON line per paper measurement shape (LOFAR station sweep, roofline shapes)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -363,14 +374,14 @@ def main():
     W, X, info, ms, tops = bench_c2(args.steps, args.warmup)
     log("c2: %.4f ms/launch, %.1f TeraOps/s" % (ms, tops))
     ach_flops = tops  # useful ops are the MFMA flops (8 per complex MAC)
-    traffic = recorded_traffic(info["kernel_name"], "cgemm_f16.hip")
+    traffic = recorded_traffic(info["kernel_name"])
     if traffic is not None:
         traffic = round(traffic)
     roofline = {"bound": "mfma", "achieved": round(ach_flops, 1), "peak": PEAK_F16_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(ach_flops / PEAK_F16_TFLOPS, 4), "traffic": traffic,
                 "algorithmic_bytes": info["algorithmic_bytes"],
                 "hbm_gbs_at_algorithmic_bytes": round(info["algorithmic_bytes"] / (ms * 1e-3) / 1e9, 1)}
-    secondary = [] if args.no_secondary else bench_secondary(args.steps)
+    secondary = [] if args.no_secondary else bench_secondary(args.steps, serving=not args.no_serving)
     cpu = None if args.no_cpu_baseline else cpu_baseline(W, X)
     line = {
         "metric": METRIC, "value": round(tops, 2), "unit": "TeraOps/s", "n_gpus": 1,

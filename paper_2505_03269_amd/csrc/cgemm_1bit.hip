@@ -100,7 +100,8 @@ __global__ __launch_bounds__(U_NT, 2) void cgemm_1bit_mfma_kernel(
     const int64_t per_c = (int64_t)tiles_m * tiles_n;
     const int64_t c = t / per_c;
     const int rem = (int)(t - c * per_c);
-    const int tn = rem / tiles_m, tm = rem - tn * tiles_m;
+    int tm, tn;
+    tile_coords(rem, tiles_m, tiles_n, tm, tn);
     const int64_t m0 = (int64_t)tm * U_BM, n0 = (int64_t)tn * U_BN;
 
     // loader: thread -> (plane, row) of both tiles; 4 words per stage each
@@ -240,7 +241,8 @@ __global__ __launch_bounds__(V_NT, 2) void cgemm_1bit_valu_kernel(
     const int64_t per_c = (int64_t)tiles_m * tiles_n;
     const int64_t c = t / per_c;
     const int rem = (int)(t - c * per_c);
-    const int tn = rem / tiles_m, tm = rem - tn * tiles_m;
+    int tm, tn;
+    tile_coords(rem, tiles_m, tiles_n, tm, tn);
     const int64_t m0 = (int64_t)tm * V_BM, n0 = (int64_t)tn * V_BN;
 
     // loader: threads 0..127 -> W (plane, row), 128..255 -> X (plane, row)

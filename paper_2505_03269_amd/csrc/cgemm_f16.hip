@@ -318,7 +318,8 @@ __global__ __launch_bounds__(NT, 2) void cgemm_f16_kernel(
     const int64_t per_c = (int64_t)tiles_m * tiles_n;
     const int64_t c = t / per_c;
     const int rem = (int)(t - c * per_c);
-    const int tn = rem / tiles_m, tm = rem - tn * tiles_m;
+    int tm, tn;
+    tile_coords(rem, tiles_m, tiles_n, tm, tn);
     const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
 
     const uint16_t *Wc = A + (a_shared ? 0 : c * 2 * M * K);
@@ -618,7 +619,8 @@ __global__ __launch_bounds__(128 * WM, WM == 2 ? 2 : 1) void cgemm_f16_fast_kern
     const int per_c = tiles_m * tiles_n;
     const int c = t / per_c;
     const int rem = t - c * per_c;
-    const int tn = rem / tiles_m, tm = rem - tn * tiles_m;
+    int tm, tn;
+    tile_coords(rem, tiles_m, tiles_n, tm, tn);
     fast_tile<WM, BK, NS, CIL>(A, B, C, M, N, K, a_shared, c, tm, tn, lds0, lds1, lds2, lds3, lds4, lds5);
 }
 
@@ -666,7 +668,8 @@ __global__ __launch_bounds__(256, 2) void cgemm_f16_group_kernel(const GroupArgs
         const int per_c = q.tiles_m * q.tiles_n;
         const int c = local / per_c;
         const int rem = local - c * per_c;
-        const int tn = rem / q.tiles_m, tm = rem - tn * q.tiles_m;
+        int tm, tn;
+        tile_coords(rem, q.tiles_m, q.tiles_n, tm, tn);
         fast_tile<2, 32, 2, CIL>(q.A, q.B, q.C, q.M, q.N, q.K, q.a_shared, c, tm, tn, lds0, lds1, lds2, lds3, lds4,
                                  lds5);
         // next_tile is rewritten only after the tile's own barriers, which

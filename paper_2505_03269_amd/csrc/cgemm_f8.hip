@@ -83,7 +83,8 @@ __global__ __launch_bounds__(NT, 2) void cgemm_f8_kernel(
     const int per_c = tiles_m * tiles_n;
     const int c = t / per_c;
     const int rem = t - c * per_c;
-    const int tn = rem / tiles_m, tm = rem - tn * tiles_m;
+    int tm, tn;
+    tile_coords(rem, tiles_m, tiles_n, tm, tn);
     const int m0 = tm * BM, n0 = tn * BN;
 
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);

@@ -76,6 +76,21 @@ hipError_t pack1bit_launch(const void *src, int src_type, int src_layout, int64_
                            int64_t rows, int64_t K, int src_k_major, uint32_t *dst,
                            hipStream_t stream);
 
+// Coordinates of tile `rem` of one channel.  Consecutive tiles walk the
+// dimension with fewer tiles first, so the workgroups that run at the same
+// time on one XCD (see xcd_remap) share an operand block: with few beam tiles
+// they share an X column block, with few sample tiles (tall, narrow problems)
+// a W row block, which then comes from HBM once instead of once per column.
+__device__ __forceinline__ void tile_coords(int rem, int tiles_m, int tiles_n, int &tm, int &tn) {
+    if (tiles_n < tiles_m) {
+        tm = rem / tiles_n;
+        tn = rem - tm * tiles_n;
+    } else {
+        tn = rem / tiles_m;
+        tm = rem - tn * tiles_m;
+    }
+}
+
 // Workgroup order: consecutive logical tiles land on the same XCD (each of the
 // 8 XCDs has its own L2).  Hardware hands workgroup ids to XCDs round-robin.
 __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nblocks) {

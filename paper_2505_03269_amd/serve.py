@@ -65,6 +65,12 @@ class Job:
         return 8.0 * self.M * self.N * self.K
 
 
+def out_dtype(dtype):
+    """Element type of a job's output: fp32 complex, exact int32 for 1-bit."""
+    import torch
+    return torch.int32 if dtype == INT1 else torch.float32
+
+
 def job_input(job, device):
     """The job's data X [1, 2, K, N] fp16, drawn from its seed (8-bit range)."""
     import torch
@@ -145,7 +151,7 @@ class Server:
             for job in batch:
                 ws = self.pool[(job.dtype, job.wid)]
                 X = job_input(job, self.device)
-                job.out = torch.empty((1, 2, job.M, job.N), dtype=torch.float32, device=self.device)
+                job.out = torch.empty((1, 2, job.M, job.N), dtype=out_dtype(job.dtype), device=self.device)
                 if job.dtype == F16:
                     job.X = X
                     f16.append((ws.A, X, job.out))
@@ -234,7 +240,7 @@ class Server:
         import torch
         ws = self.pool[(job.dtype, job.wid)]
         X = job_input(job, self.device)
-        out = torch.empty((1, 2, job.M, job.N), dtype=torch.float32, device=self.device)
+        out = torch.empty((1, 2, job.M, job.N), dtype=out_dtype(job.dtype), device=self.device)
         if job.dtype == F16:
             self._plan(F16, job.M, job.N, job.K).execute(ws.A, X, out)
         elif job.dtype == F8_E4M3:

@@ -16,12 +16,14 @@ from paper_2505_03269_amd import serve  # noqa: E402
 
 @pytest.fixture(scope="module")
 def server():
-    # small pool; a budget of 192 MiB forces queueing behind the memory limit
-    return serve.Server(pool_per_dtype=3, budget_bytes=192 << 20, streams=3, max_slots=24, seed=3)
+    return serve.Server(pool_per_dtype=3, budget_bytes=1 << 30, streams=3, max_slots=24, seed=3)
 
 
 def test_results_same_alone_and_in_the_mix(server):
     jobs = server.make_jobs(48, rate=3000.0, seed=7)
+    # a budget of 1.5 largest jobs admits every job but makes most of them
+    # wait for memory held by others
+    server.budget = int(1.5 * max(j.nbytes for j in jobs))
     log("serving %d jobs" % len(jobs))
     summary = server.run(jobs, keep_outputs=True)
     log("summary %s, batches %s, max in flight %d" % (summary, server.batch_sizes, server.max_inflight))
@@ -36,6 +38,7 @@ def test_results_same_alone_and_in_the_mix(server):
 
 def test_mixed_results_match_oracle(server):
     jobs = server.make_jobs(12, rate=None, seed=8)
+    server.budget = 1 << 34
     server.run(jobs, keep_outputs=True)
     seen = set()
     for job in jobs:
