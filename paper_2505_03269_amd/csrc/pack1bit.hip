@@ -13,7 +13,9 @@
 //  * N-major (X-like, [K][rows] with rows contiguous): consecutive threads take
 //    consecutive rows so every sample row is read coalesced; each thread
 //    builds 4 consecutive words (128 samples along K) per plane and writes
-//    them as one 16-byte store.
+//    them as one 16-byte store.  When the row count allows, a thread takes 8
+//    bytes' worth of consecutive rows per plane, so each receiver step is one
+//    16-byte (or two 8-byte) loads per lane.
 #include "tcbf_internal.h"
 
 namespace tcbf {
@@ -101,6 +103,92 @@ __global__ __launch_bounds__(NT) void pack_nmajor_kernel(const T *__restrict__ s
     }
 }
 
+// N-major, vectorised: each thread owns R consecutive rows (R * sizeof(T) =
+// 8 bytes per plane, so interleaved sources give one 16-byte load and planar
+// sources two 8-byte loads per receiver), 128 receivers, both planes; a wave
+// load covers 64 * 8 consecutive row bytes per plane.  Needs rows % R == 0.
+template <typename T, int IL> struct VecLoad;
+template <typename T> struct VecLoad<T, 1> {
+    static constexpr int R = 8 / sizeof(T);
+    // re and im of rows r..r+R-1 at receiver row `p` (interleaved pairs)
+    static __device__ __forceinline__ void load(const T *p, int64_t, T (&re)[R], T (&im)[R]) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(p);
+        const T *e = reinterpret_cast<const T *>(&v);
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            re[j] = e[2 * j];
+            im[j] = e[2 * j + 1];
+        }
+    }
+};
+template <typename T> struct VecLoad<T, 0> {
+    static constexpr int R = 8 / sizeof(T);
+    static __device__ __forceinline__ void load(const T *p, int64_t plane, T (&re)[R], T (&im)[R]) {
+        const uint2 a = *reinterpret_cast<const uint2 *>(p);
+        const uint2 b = *reinterpret_cast<const uint2 *>(p + plane);
+        const T *ea = reinterpret_cast<const T *>(&a);
+        const T *eb = reinterpret_cast<const T *>(&b);
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            re[j] = ea[j];
+            im[j] = eb[j];
+        }
+    }
+};
+
+template <typename T, int IL>
+__global__ __launch_bounds__(NT) void pack_nmajor_vec_kernel(const T *__restrict__ src, uint32_t *__restrict__ dst,
+                                                             int64_t batch, int64_t rows, int64_t K, int64_t kw) {
+    typedef VecLoad<T, IL> L;
+    constexpr int R = L::R;
+    const int64_t gid = (int64_t)blockIdx.x * NT + threadIdx.x;
+    const int64_t ngroups = (kw + 3) / 4;
+    const int64_t rgroups = rows / R;
+    if (gid >= batch * ngroups * rgroups) return;
+    const int64_t r0 = (gid % rgroups) * R;
+    const int64_t g = (gid / rgroups) % ngroups;
+    const int64_t c = gid / (rgroups * ngroups);
+    uint32_t wr[R][4], wi[R][4];
+#pragma unroll
+    for (int j = 0; j < R; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) wr[j][q] = wi[j][q] = 0u;
+    const int64_t k0 = g * 128;
+    const int n = (int)((K - k0) < 128 ? (K - k0) : 128);
+    // element (k, row) of plane 0: interleaved ((c K + k) rows + row) * 2, planar (c 2 K + k) rows + row
+    const T *base = IL ? src + ((c * K + k0) * rows + r0) * 2 : src + (c * 2 * K + k0) * rows + r0;
+    const int64_t kstep = IL ? rows * 2 : rows, plane = K * rows;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        if (32 * q >= n) break;
+        const int m = n - 32 * q < 32 ? n - 32 * q : 32;
+        for (int b = 0; b < m; ++b) {
+            T re[R], im[R];
+            L::load(base + (int64_t)(32 * q + b) * kstep, plane, re, im);
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                wr[j][q] |= Bits<T>::pos(re[j]) << b;
+                wi[j][q] |= Bits<T>::pos(im[j]) << b;
+            }
+        }
+    }
+    const bool full = g * 4 + 4 <= kw;
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        uint32_t *dr = dst + ((c * 2 + 0) * rows + r0 + j) * kw + g * 4;
+        uint32_t *di = dst + ((c * 2 + 1) * rows + r0 + j) * kw + g * 4;
+        if (full && (kw % 4) == 0) {
+            *reinterpret_cast<uint4 *>(dr) = make_uint4(wr[j][0], wr[j][1], wr[j][2], wr[j][3]);
+            *reinterpret_cast<uint4 *>(di) = make_uint4(wi[j][0], wi[j][1], wi[j][2], wi[j][3]);
+        } else {
+            for (int q = 0; q < 4 && g * 4 + q < kw; ++q) {
+                dr[q] = wr[j][q];
+                di[q] = wi[j][q];
+            }
+        }
+    }
+}
+
 template <typename T>
 hipError_t launch_typed(const void *src, int il, int64_t batch, int64_t rows, int64_t K, int kmajor,
                         uint32_t *dst, hipStream_t stream) {
@@ -111,6 +199,11 @@ hipError_t launch_typed(const void *src, int il, int64_t batch, int64_t rows, in
         dim3 grid((uint32_t)((total + NT - 1) / NT));
         if (il) hipLaunchKernelGGL((pack_kmajor_kernel<T, 1>), grid, dim3(NT), 0, stream, s, dst, batch, rows, K, kw);
         else    hipLaunchKernelGGL((pack_kmajor_kernel<T, 0>), grid, dim3(NT), 0, stream, s, dst, batch, rows, K, kw);
+    } else if (rows % (8 / (int64_t)sizeof(T)) == 0) {
+        const int64_t total = batch * ((kw + 3) / 4) * (rows / (8 / (int64_t)sizeof(T)));
+        dim3 grid((uint32_t)((total + NT - 1) / NT));
+        if (il) hipLaunchKernelGGL((pack_nmajor_vec_kernel<T, 1>), grid, dim3(NT), 0, stream, s, dst, batch, rows, K, kw);
+        else    hipLaunchKernelGGL((pack_nmajor_vec_kernel<T, 0>), grid, dim3(NT), 0, stream, s, dst, batch, rows, K, kw);
     } else {
         const int64_t total = batch * ((kw + 3) / 4) * rows;
         dim3 grid((uint32_t)((total + NT - 1) / NT));

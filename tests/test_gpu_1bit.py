@@ -112,9 +112,11 @@ def _src(g, dtype, shape):
 @pytest.mark.parametrize("k_major", [True, False])
 @pytest.mark.parametrize("layout", [tcbf.PLANAR, tcbf.INTERLEAVED])
 @pytest.mark.parametrize("K", [1, 31, 32, 33, 100, 129, 600])
-def test_pack_matches_oracle(dtype, k_major, layout, K):
+@pytest.mark.parametrize("rows", [37, 64])
+def test_pack_matches_oracle(dtype, k_major, layout, K, rows):
+    """rows = 37 takes the per-row N-major kernel, rows = 64 the vectorised one."""
     g = np.random.default_rng(K)
-    batch, rows = 2, 37
+    batch = 2
     if layout == tcbf.PLANAR:
         shape = (batch, 2, rows, K) if k_major else (batch, 2, K, rows)
     else:
