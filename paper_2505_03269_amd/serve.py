@@ -71,12 +71,12 @@ def out_dtype(dtype):
     return torch.int32 if dtype == INT1 else torch.float32
 
 
-def job_input(job, device):
+def job_input(job, device, gen=None):
     """The job's data X [1, 2, K, N] fp16, drawn from its seed (8-bit range)."""
     import torch
-    g = torch.Generator(device=device)
+    g = gen if gen is not None else torch.Generator(device=device)
     g.manual_seed(int(job.seed))
-    return torch.randint(-127, 128, (1, 2, job.K, job.N), device=device, generator=g).to(torch.float16)
+    return torch.randint(-127, 128, (1, 2, job.K, job.N), device=device, generator=g, dtype=torch.float16)
 
 
 class Server:
@@ -104,6 +104,7 @@ class Server:
                            for _ in range(streams)]
         self.max_slots = max_slots
         self.plans = {}
+        self.gen = torch.Generator(device=self.device)
 
     # -- jobs ---------------------------------------------------------------
     def make_jobs(self, count, rate, seed=1):
@@ -150,7 +151,7 @@ class Server:
             f16 = []
             for job in batch:
                 ws = self.pool[(job.dtype, job.wid)]
-                X = job_input(job, self.device)
+                X = job_input(job, self.device, self.gen)
                 job.out = torch.empty((1, 2, job.M, job.N), dtype=out_dtype(job.dtype), device=self.device)
                 if job.dtype == F16:
                     job.X = X
