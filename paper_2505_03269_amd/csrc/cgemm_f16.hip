@@ -400,8 +400,8 @@ __global__ __launch_bounds__(NT, 2) void cgemm_f16_kernel(
 //     16-byte chunks; chunk ch of beam m sits at ch ^ swzW(m);
 //   X region [2 planes][BK][128 samples] fp16: rows of 256 bytes (16 chunks);
 //     chunk ch of row k sits at ch ^ swzX(k).
-// The swizzles keep the MFMA operand reads free of bank conflicts for 8- and
-// 16-lane access phases.
+// The swizzles keep the MFMA operand reads free of bank conflicts (the W
+// reads in 16-lane phases, the transposing X reads in 32-lane phases).
 template <int WM, int BK> struct FastGeo {
     static constexpr int TM = 64 * WM;                 // beams per workgroup
     static constexpr int NW = 2 * WM;                  // waves
@@ -413,7 +413,10 @@ template <int WM, int BK> struct FastGeo {
     __device__ static int swzW(int m) {
         return BK == 32 ? (((m >> 1) ^ ((m >> 3) & 1)) & 3) : (((m >> 2) ^ (m >> 3)) & 1);
     }
-    __device__ static int swzX(int k) { return 2 * (k & 3); }
+    // receiver rows k..k+3 get chunk offsets 0, 4, 8, 12: the transposing
+    // fragment read of 32 lanes (4 rows x 64 bytes) then touches every bank
+    // once (measured: no LDS bank conflicts)
+    __device__ static int swzX(int k) { return 4 * (k & 3); }
 };
 
 __device__ __forceinline__ half8 tr_frag(const char *lds_bytes, int off0, int off1) {
