@@ -113,9 +113,11 @@ def test_plane_wave_beamformed_end_to_end():
     g = np.random.default_rng(6)
     K, M, N, f = 192, 64, 64, 150e6
     pos = np.column_stack([g.uniform(-400, 400, (K, 2)), np.zeros(K)])
-    r = 0.05 * np.sqrt(g.uniform(0, 1, M))
-    t = g.uniform(0, 2 * np.pi, M)
-    dirs = np.column_stack([r * np.cos(t), r * np.sin(t), np.zeros(M)])
+    # beams on an 8 x 8 grid of direction cosines 0.01 apart: several beam
+    # widths (wavelength / aperture ~ 0.0025) between neighbours
+    gl = (np.arange(8) - 3.5) * 0.01
+    L, Mm = np.meshgrid(gl, gl)
+    dirs = np.column_stack([L.ravel(), Mm.ravel(), np.zeros(M)])
     W = tcbf.steering_weights(to_dev(pos), to_dev(dirs), to_dev(np.array([f])), C0)
     A = 40.0 - 25.0j
     tau = pos @ dirs[:N].T / C0                        # sample n: wave from beam n's direction
@@ -131,7 +133,7 @@ def test_plane_wave_beamformed_end_to_end():
     # fp16 weights and samples: each term carries ~1e-3 relative error, the sum is K terms
     assert np.allclose(gain, K * abs(A), rtol=2e-3)
     off = np.abs(Bc[:N, :N][~np.eye(N, dtype=bool)])
-    assert off.max() < 0.9 * K * abs(A)
+    assert off.max() < 0.5 * K * abs(A)     # the grid keeps other beams below ~0.18 of the main lobe
 
 
 def test_rejects_bad_arguments():

@@ -54,9 +54,8 @@ def test_plane_wave_sums_coherently_in_its_own_beam():
     g = np.random.default_rng(2)
     K, M, f = 96, 8, 150e6
     pos = np.column_stack([g.uniform(-300, 300, (K, 2)), np.zeros(K)])
-    r = 0.05 * np.sqrt(g.uniform(0, 1, M))
-    t = g.uniform(0, 2 * np.pi, M)
-    dirs = np.column_stack([r * np.cos(t), r * np.sin(t), np.zeros(M)])
+    # well separated beams (0.02 apart in direction cosine, several beam widths)
+    dirs = np.column_stack([(np.arange(M) - 3.5) * 0.02, np.zeros(M), np.zeros(M)])
     W = oracle.steering_weights(pos, dirs, [f], C0)[0]          # [M, K]
     A = 0.75 - 0.5j
     tau = pos @ dirs.T / C0                                      # [K, M] delays of each source direction
