@@ -240,34 +240,37 @@ def bench_secondary(steps, serving=True):
         del Wq, Ws, Xq, Xs, C
     del A, B
     torch.cuda.empty_cache()
-    # grouped persistent launch: 16 uneven job shapes from the served-stream
-    # distribution in one launch, against one launch per job
-    shapes = wl.mixed_shapes(0, 16)
+    # grouped persistent launch: uneven job shapes in one launch, against one
+    # launch per job; served-stream sizes (each job fills the GPU alone) and
+    # small jobs (each leaves most CUs idle alone)
+    ws = torch.empty(tcbf.GROUP_WORKSPACE_BYTES, dtype=torch.uint8, device="cuda:0")
     g = torch.Generator(device="cuda:0")
     g.manual_seed(7)
-    probs = []
-    for (M, N, K) in shapes:
-        Wg = torch.randn((1, 2, M, K), device="cuda:0", generator=g).half()
-        Xg = torch.randint(-127, 128, (1, 2, K, N), device="cuda:0", generator=g).half()
-        probs.append((Wg, Xg, torch.empty((1, 2, M, N), device="cuda:0")))
-    plans = [tcbf.Plan(1, M, N, K, tcbf.F16) for (M, N, K) in shapes]
-    ws = torch.empty(tcbf.GROUP_WORKSPACE_BYTES, dtype=torch.uint8, device="cuda:0")
-    ops = sum(8.0 * M * N * K for (M, N, K) in shapes)
-    ms_g = time_launches(lambda: tcbf.group_execute(probs, workspace=ws), st, 1)
+    for label, count, ranges in (("16 jobs, M~U[128,4096] N~U[256,8192] K~U[64,2048]", 16, {}),
+                                 ("32 small jobs, M~U[128,512] N~U[256,1024] K~U[64,512]", 32,
+                                  dict(m_range=(128, 512), n_range=(256, 1024), k_range=(64, 512)))):
+        shapes = wl.mixed_shapes(0, count, **ranges)
+        probs = []
+        for (M, N, K) in shapes:
+            Wg = torch.randn((1, 2, M, K), device="cuda:0", generator=g).half()
+            Xg = torch.randint(-127, 128, (1, 2, K, N), device="cuda:0", generator=g).half()
+            probs.append((Wg, Xg, torch.empty((1, 2, M, N), device="cuda:0")))
+        plans = [tcbf.Plan(1, M, N, K, tcbf.F16) for (M, N, K) in shapes]
+        ops = sum(8.0 * M * N * K for (M, N, K) in shapes)
+        ms_g = time_launches(lambda: tcbf.group_execute(probs, workspace=ws), st, 1)
 
-    def each():
-        for pl, (Wg, Xg, Cg) in zip(plans, probs):
-            pl.execute(Wg, Xg, Cg)
-    ms_s = time_launches(each, st, 1)
-    out.append({"workload": "grouped fp16: 16 jobs, M~U[128,4096] N~U[256,8192] K~U[64,2048]",
-                "kernel": "cgemm_f16_group_kernel", "value": round(ops / (ms_g * 1e-3) / 1e12, 1),
-                "unit": "TeraOps/s", "ms_per_launch": round(ms_g, 4),
-                "separate_launches_tops": round(ops / (ms_s * 1e-3) / 1e12, 1),
-                "separate_launches_ms": round(ms_s, 4), "dtype": "f16",
-                "roofline": {"bound": "mfma", "achieved": round(ops / (ms_g * 1e-3) / 1e12, 1),
-                             "peak": PEAK_F16_TFLOPS, "unit": "TFLOP/s",
-                             "frac": round(ops / (ms_g * 1e-3) / 1e12 / PEAK_F16_TFLOPS, 4)}})
-    del probs, plans
+        def each():
+            for pl, (Wg, Xg, Cg) in zip(plans, probs):
+                pl.execute(Wg, Xg, Cg)
+        ms_s = time_launches(each, st, 1)
+        tops = ops / (ms_g * 1e-3) / 1e12
+        out.append({"workload": "grouped fp16: " + label, "kernel": "cgemm_f16_group_kernel", "value": round(tops, 1),
+                    "unit": "TeraOps/s", "ms_per_launch": round(ms_g, 4),
+                    "separate_launches_tops": round(ops / (ms_s * 1e-3) / 1e12, 1),
+                    "separate_launches_ms": round(ms_s, 4), "dtype": "f16",
+                    "roofline": {"bound": "mfma", "achieved": round(tops, 1), "peak": PEAK_F16_TFLOPS,
+                                 "unit": "TFLOP/s", "frac": round(tops / PEAK_F16_TFLOPS, 4)}})
+        del probs, plans
     torch.cuda.empty_cache()
     if serving:
         out.append(bench_serving())

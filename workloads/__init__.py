@@ -200,12 +200,13 @@ def generate_c3(batch=64, threads=8):
 
 # ---- C5 shapes -------------------------------------------------------------
 
-def mixed_shapes(seed, count, align=8):
-    """`count` job shapes (M, N, K) drawn from the served-stream distribution,
-    each rounded up to a multiple of `align`."""
+def mixed_shapes(seed, count, align=8, m_range=(128, 4096), n_range=(256, 8192), k_range=(64, 2048)):
+    """`count` job shapes (M, N, K) drawn uniformly from the given ranges
+    (default: the served-stream distribution), each rounded up to a multiple
+    of `align`."""
     g = rng(5, 3, seed)
     up = lambda v: int(-(-int(v) // align) * align)  # noqa: E731
-    M = g.integers(128, 4097, count)
-    K = g.integers(64, 2049, count)
-    N = g.integers(256, 8193, count)
+    M = g.integers(m_range[0], m_range[1] + 1, count)
+    K = g.integers(k_range[0], k_range[1] + 1, count)
+    N = g.integers(n_range[0], n_range[1] + 1, count)
     return [(up(m), up(n), up(k)) for m, n, k in zip(M, N, K)]
