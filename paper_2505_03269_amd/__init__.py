@@ -13,7 +13,7 @@ import os
 
 __all__ = [
     "F16", "INT1", "F8_E4M3", "MXF8_E4M3", "PLANAR", "INTERLEAVED", "SRC_I8", "SRC_F16", "SRC_F32",
-    "TcbfError", "Plan", "pack1bit", "quantize_e4m3", "steering_weights", "group_execute", "f8_kp", "lib",
+    "TcbfError", "Plan", "pack1bit", "quantize_e4m3", "steering_weights", "group_execute", "f8_kp", "mx_scale_pitch", "lib",
     "status_string", "EXPORTS", "GROUP_MAX", "GROUP_WORKSPACE_BYTES",
 ]
 
@@ -103,6 +103,12 @@ def f8_kp(K):
     return (int(K) + 31) // 32 * 32
 
 
+def mx_scale_pitch(K):
+    """Row pitch (bytes) of per-block E8M0 scales: the Kp / 32 block codes
+    padded to a multiple of 16 (16 * ceil(Kp / 512))."""
+    return (f8_kp(K) // 32 + 15) // 16 * 16
+
+
 def _is_f8(dtype):
     return dtype in (F8_E4M3, MXF8_E4M3)
 
@@ -181,12 +187,12 @@ class Plan:
         return (self.batch, 2, self.K, self.N) if self.b_layout == PLANAR else (self.batch, self.K, self.N, 2)
 
     def shape_a_scale(self):
-        """FP8 modes: W scales ([nb, M] fp32 per row, [nb, M, Kp/32] uint8 per block)."""
+        """FP8 modes: W scales ([nb, M] fp32 per row, [nb, M, Ks] uint8 per block)."""
         nb = 1 if self.a_shared else self.batch
-        return (nb, self.M) if self.dtype == F8_E4M3 else (nb, self.M, f8_kp(self.K) // 32)
+        return (nb, self.M) if self.dtype == F8_E4M3 else (nb, self.M, mx_scale_pitch(self.K))
 
     def shape_b_scale(self):
-        return (self.batch, self.N) if self.dtype == F8_E4M3 else (self.batch, self.N, f8_kp(self.K) // 32)
+        return (self.batch, self.N) if self.dtype == F8_E4M3 else (self.batch, self.N, mx_scale_pitch(self.K))
 
     def shape_c(self):
         return (self.batch, 2, self.M, self.N) if self.c_layout == PLANAR else (self.batch, self.M, self.N, 2)
@@ -285,7 +291,8 @@ def quantize_e4m3(src, k_major=True, layout=PLANAR, block=0, out=None, scales=No
 
     Source orientation as for pack1bit.  Returns (codes, scales): uint8 codes
     [batch, 2, rows, Kp] and fp32 scales [batch, rows] (block=0) or uint8 E8M0
-    codes [batch, rows, Kp/32] (block=32).
+    codes [batch, rows, Ks] (block=32; Ks = mx_scale_pitch(K), bytes past
+    Kp/32 not written).
     """
     import torch
     types = {torch.int8: SRC_I8, torch.float16: SRC_F16, torch.float32: SRC_F32}
@@ -299,10 +306,10 @@ def quantize_e4m3(src, k_major=True, layout=PLANAR, block=0, out=None, scales=No
         if block == 0:
             scales = torch.empty((batch, rows), dtype=torch.float32, device=src.device)
         else:
-            scales = torch.empty((batch, rows, kp // 32), dtype=torch.uint8, device=src.device)
+            scales = torch.empty((batch, rows, mx_scale_pitch(kk)), dtype=torch.uint8, device=src.device)
     if tuple(out.shape) != (batch, 2, rows, kp) or out.dtype != torch.uint8:
         raise ValueError("out must be uint8 [batch, 2, rows, Kp]")
-    want = ((batch, rows), torch.float32) if block == 0 else ((batch, rows, kp // 32), torch.uint8)
+    want = ((batch, rows), torch.float32) if block == 0 else ((batch, rows, mx_scale_pitch(kk)), torch.uint8)
     if tuple(scales.shape) != want[0] or scales.dtype != want[1]:
         raise ValueError("scales must be %s %s" % (want[1], want[0]))
     _check(lib().tcbf_quantize_e4m3(_dev_ptr(src, "src"), types[src.dtype], int(layout), int(batch), int(rows),

@@ -8,7 +8,9 @@
 //   per-row scales (TCBF_F8_E4M3): C[m][n] = a_scale[m] * b_scale[n] * sum_k W8 X8
 //     -- the scales factor out of the sum, so they are applied in the epilogue;
 //   per-block scales (TCBF_MXF8_E4M3): every 32-receiver block carries its own
-//     power-of-two scales, applied inside the scaled MFMA per lane.
+//     power-of-two scales, applied inside the scaled MFMA per lane.  Scale
+//     codes are [batch][rows][Ks] bytes, Ks = 16 * ceil(Kp / 512): the row's
+//     Kp / 32 block codes, then padding that is never used.
 // As in the 16-bit kernel, the imaginary part of the product uses W's
 // imaginary plane negated in registers (a sign-bit flip, exact in e4m3).
 //
@@ -47,6 +49,9 @@ constexpr int PIECES_PER_WAVE = REG / 1024 / 4;  // 1 KiB wave loads per operand
 constexpr int PIECE_ROWS = 1024 / ROWB;          // rows per wave load
 constexpr uint32_t NEG = 0x80808080u;   // sign bits of four e4m3 codes
 constexpr int SCALE_ONE = 127;          // E8M0 code of 2^0
+constexpr int SLAB_STAGES = 8;          // stages whose block scales one slab holds
+constexpr int SLAB_ROWB = 2 * SLAB_STAGES;  // scale bytes per row per slab (16)
+constexpr int SLAB = 2 * BM * SLAB_ROWB;    // W rows then X rows: 4 KiB
 
 static_assert(BM == BN, "both operands share the staged geometry");
 
@@ -71,11 +76,13 @@ __global__ __launch_bounds__(NT, 2) void cgemm_f8_kernel(
     const uint8_t *__restrict__ A, const uint8_t *__restrict__ B, float *__restrict__ C,
     const void *__restrict__ a_scale, const void *__restrict__ b_scale, int M, int N, int Kp, int a_shared,
     int tiles_m, int tiles_n, int nblocks) {
-    static_assert(NS >= 2 && NS <= 4, "ring depth");
+    static_assert(NS >= 2 && NS <= 4 && NS <= SLAB_STAGES + 1, "ring depth");
     __shared__ __attribute__((aligned(1024))) char lds0[STAGE];
     __shared__ __attribute__((aligned(1024))) char lds1[STAGE];
     __shared__ __attribute__((aligned(NS > 2 ? 1024 : 4))) char lds2[NS > 2 ? STAGE : 4];
     __shared__ __attribute__((aligned(NS > 3 ? 1024 : 4))) char lds3[NS > 3 ? STAGE : 4];
+    // block-scale slabs (MX only): two slots of SLAB_STAGES stages each
+    __shared__ __attribute__((aligned(MX ? 1024 : 4))) char slabs[MX ? 2 * SLAB : 4];
     char *const bufs[4] = {lds0, lds1, lds2, lds3};
 
     const int tid = threadIdx.x;
@@ -120,30 +127,30 @@ __global__ __launch_bounds__(NT, 2) void cgemm_f8_kernel(
     const int ox0 = REG + fx * ROWB + ((hl ^ swz(fx)) * 16);
     const int ox1 = REG + fx * ROWB + (((2 + hl) ^ swz(fx)) * 16);
 
-    // Per-block scale bytes: this lane reads block 2*kt + hl of beams fw, fw+32
-    // and samples fx, fx+32 ([rows][Kp/32] per channel).
+    // Block scales travel through LDS: every SLAB_STAGES stages one direct
+    // 16-byte load per lane brings the next 16 block codes of one staged row
+    // (waves 0, 1: W rows 0..63, 64..127; waves 2, 3: the same X rows) into
+    // the slab slot (kt / SLAB_STAGES) % 2.  A slot's next load is issued
+    // SLAB_STAGES + 2 - NS steps after the step that read its last stage, so
+    // a ring barrier lies between them.  Compute reads this
+    // lane's four codes (beams fw, fw + 32; samples fx, fx + 32; block
+    // 2 kt + hl) from the slot.
     const int nkb = Kp / 32;
-    const uint8_t *ASc = MX ? (const uint8_t *)a_scale + (int64_t)cw * M * nkb : nullptr;
-    const uint8_t *BSc = MX ? (const uint8_t *)b_scale + (int64_t)c * N * nkb : nullptr;
-    const __amdgpu_buffer_rsrc_t rsa = __builtin_amdgcn_make_buffer_rsrc((void *)ASc, 0, MX ? M * nkb : 0, RSRC_FLAGS);
-    const __amdgpu_buffer_rsrc_t rsb = __builtin_amdgcn_make_buffer_rsrc((void *)BSc, 0, MX ? N * nkb : 0, RSRC_FLAGS);
-    uint32_t sa_off[2] = {OOB, OOB}, sb_off[2] = {OOB, OOB};
+    const int ks = (int)mx_scale_pitch(Kp);
+    static_assert(SLAB_ROWB == 16, "one slab row is the pitch granule");
+    const int so = wave >> 1;                                       // slab operand of this wave
+    __amdgpu_buffer_rsrc_t rss = __builtin_amdgcn_make_buffer_rsrc((void *)a_scale, 0, 0, RSRC_FLAGS);
+    uint32_t slab_off = OOB;
     if (MX) {
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const int m = m0 + fw + 32 * i, n = n0 + fx + 32 * i;
-            sa_off[i] = m < M ? (uint32_t)(m * nkb + hl) : OOB;
-            sb_off[i] = n < N ? (uint32_t)(n * nkb + hl) : OOB;
-        }
+        const int rows = so ? N : M;
+        const uint8_t *base = so ? (const uint8_t *)b_scale + (int64_t)c * N * ks
+                                 : (const uint8_t *)a_scale + (int64_t)cw * M * ks;
+        rss = __builtin_amdgcn_make_buffer_rsrc((void *)base, 0, rows * ks, RSRC_FLAGS);
+        const int r = (so ? n0 : m0) + 64 * (wave & 1) + lane;
+        slab_off = r < rows ? (uint32_t)(r * ks) : OOB;
     }
-    // [stage slot][W tile i, X tile j]; whole-ring static indices only
-    int sreg[NS][4];
-#pragma unroll
-    for (int u = 0; u < NS; ++u)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) sreg[u][q] = SCALE_ONE;
 
-    auto issue = [&](char *base, int kt, int u) {
+    auto issue = [&](char *base, int kt) {
         const int k0 = kt * BK;
         const bool kin = k0 + kc < Kp;
 #pragma unroll
@@ -160,22 +167,32 @@ __global__ __launch_bounds__(NT, 2) void cgemm_f8_kernel(
             __builtin_amdgcn_raw_ptr_buffer_load_lds(
                 rx, (TCBF_LDS_AS void *)(base + REG + (wave * PIECES_PER_WAVE + q) * 1024), 16, off, k0, 0, 0);
         }
-        if (MX) {
-            // a block past Kp/32 (second half of the last stage when Kp % 64
-            // == 32) has zero data; it reads scale code 0 instead of a
-            // neighbour's byte
-            const bool bin = 2 * kt + hl < nkb;
-#pragma unroll
-            for (int i = 0; i < 2; ++i) {
-                sreg[u][i] = __builtin_amdgcn_raw_buffer_load_b8(rsa, bin ? sa_off[i] + 2 * kt : OOB, 0, 0);
-                sreg[u][2 + i] = __builtin_amdgcn_raw_buffer_load_b8(rsb, bin ? sb_off[i] + 2 * kt : OOB, 0, 0);
-            }
-        }
+        if (MX && kt % SLAB_STAGES == 0)
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                rss, (TCBF_LDS_AS void *)(slabs + (kt / SLAB_STAGES % 2) * SLAB + so * (SLAB / 2) + (wave & 1) * 1024),
+                16, slab_off, 2 * kt, 0, 0);
     };
 
     Acc acc;
     acc.zero();
-    auto compute = [&](const char *st, int u) {
+    // Block codes of stage kt: [W tile i, X tile j].  A block past Kp / 32
+    // (the second half of the last stage when Kp % 64 == 32) has zero data
+    // and takes 2^0.  Read before the step issues its loads: the compiler
+    // makes an LDS read wait for every direct load into the same array still
+    // in flight; with a two-stage ring none is at that point (with three, the
+    // next stage's loads are waited for here).
+    auto read_scales = [&](int kt, int *sc) {
+        const char *sl = slabs + (kt / SLAB_STAGES % 2) * SLAB + 2 * (kt % SLAB_STAGES) + hl;
+        const bool bin = 2 * kt + hl < nkb;
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int w = ((const uint8_t *)sl)[(fw + 32 * i) * SLAB_ROWB];
+            const int x = ((const uint8_t *)sl)[SLAB / 2 + (fx + 32 * i) * SLAB_ROWB];
+            sc[i] = bin ? w : SCALE_ONE;
+            sc[2 + i] = bin ? x : SCALE_ONE;
+        }
+    };
+    auto compute = [&](const char *st, const int *sc) {
         i32x8 xr[2], xi[2];
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
@@ -187,10 +204,10 @@ __global__ __launch_bounds__(NT, 2) void cgemm_f8_kernel(
             const i32x8 wr = frag(st, ow0 + i * 32 * ROWB, ow1 + i * 32 * ROWB);
             const i32x8 wi = frag(st, ow0 + i * 32 * ROWB + PLANE, ow1 + i * 32 * ROWB + PLANE);
             const i32x8 wn = wi ^ (int)NEG;
-            const int sw = sreg[u][i];
+            const int sw = sc[i];
 #pragma unroll
             for (int j = 0; j < 2; ++j) {
-                const int sx = sreg[u][2 + j];
+                const int sx = sc[2 + j];
                 acc.re[i][j] = mma(xr[j], wr, acc.re[i][j], sx, sw);
                 acc.im[i][j] = mma(xi[j], wr, acc.im[i][j], sx, sw);
                 acc.re[i][j] = mma(xi[j], wn, acc.re[i][j], sx, sw);
@@ -200,7 +217,9 @@ __global__ __launch_bounds__(NT, 2) void cgemm_f8_kernel(
     };
 
     // Ring: stage kt lives in buffer kt % NS; NS-1 stages are in flight.
-    constexpr int PER_STAGE = 2 * PIECES_PER_WAVE + (MX ? 4 : 0);  // loads per wave per stage
+    // loads per wave per stage; a slab load every SLAB_STAGES stages only
+    // makes the count of later loads larger, which keeps the wait safe
+    constexpr int PER_STAGE = 2 * PIECES_PER_WAVE;
     static_assert((NS - 2) * PER_STAGE < 64, "vmcnt range");
     constexpr int kWaitRing = vmcnt_imm((NS - 2) * PER_STAGE), kWaitAll = vmcnt_imm(0);
     const int nk = (Kp + BK - 1) / BK;
@@ -209,12 +228,14 @@ __global__ __launch_bounds__(NT, 2) void cgemm_f8_kernel(
         else __builtin_amdgcn_s_waitcnt(kWaitAll);
         // all waves' loads for stage kt landed, stage kt-1 fully read
         asm volatile("s_barrier" ::: "memory");
-        if (kt + NS - 1 < nk) issue(bufs[(u + NS - 1) % NS], kt + NS - 1, (u + NS - 1) % NS);
-        compute(bufs[u], u);
+        int sc[4] = {SCALE_ONE, SCALE_ONE, SCALE_ONE, SCALE_ONE};
+        if (MX) read_scales(kt, sc);
+        if (kt + NS - 1 < nk) issue(bufs[(u + NS - 1) % NS], kt + NS - 1);
+        compute(bufs[u], sc);
     };
 #pragma unroll
     for (int s = 0; s < NS - 1; ++s)
-        if (s < nk) issue(bufs[s], s, s);
+        if (s < nk) issue(bufs[s], s);
     int kt0 = 0;
     for (; kt0 + NS <= nk; kt0 += NS) {
 #pragma unroll

@@ -83,6 +83,22 @@ def dequant(codes, scales, block, K):
     return d[:, 0] + 1j * d[:, 1]
 
 
+def host_scales(scales, block, kp):
+    """Device scales -> numpy; per-block codes without the row padding."""
+    s = scales.cpu().numpy()
+    return s if block == 0 else np.ascontiguousarray(s[..., :kp // 32])
+
+
+def pitched(codes, K):
+    """Per-block codes [..., Kp/32] -> the library's [..., Ks] layout, the
+    padding filled with 255 (the E8M0 NaN code): a kernel that read any
+    padding byte would produce NaN."""
+    ks = tcbf.mx_scale_pitch(K)
+    out = np.full(codes.shape[:-1] + (ks,), 255, np.uint8)
+    out[..., :codes.shape[-1]] = codes
+    return out
+
+
 def gpu_quantize(src_np, k_major, layout, block):
     src = to_dev(src_np)
     codes, scales = tcbf.quantize_e4m3(src, k_major=k_major, layout=layout, block=block)
@@ -147,7 +163,9 @@ def test_quantiser_bit_exact(kind, layout, k_major, block):
     codes, scales = gpu_quantize(src, k_major, layout, block)
     ecodes, escales = quant_expected(src, k_major, layout, block)
     assert np.array_equal(codes.cpu().numpy(), ecodes)
-    s = scales.cpu().numpy()
+    if block:
+        assert scales.shape[-1] == tcbf.mx_scale_pitch(K) and scales.shape[-1] % 16 == 0
+    s = host_scales(scales, block, codes.shape[-1])
     if block == 0:
         assert np.array_equal(s.view(np.uint32), escales.astype(np.float32).view(np.uint32))
     else:
@@ -178,7 +196,7 @@ def test_quantiser_special_values(k_major, block):
     codes, scales = gpu_quantize(src, k_major, tcbf.PLANAR, block)
     ecodes, escales = quant_expected(src, k_major, tcbf.PLANAR, block)
     assert np.array_equal(codes.cpu().numpy(), ecodes)
-    s = scales.cpu().numpy()
+    s = host_scales(scales, block, codes.shape[-1])
     if block == 0:
         assert np.array_equal(s.view(np.uint32), escales.astype(np.float32).view(np.uint32))
     else:
@@ -192,10 +210,11 @@ def test_quantiser_larger_ragged(block):
         codes, scales = gpu_quantize(src, k_major, tcbf.PLANAR, block)
         ecodes, escales = quant_expected(src, k_major, tcbf.PLANAR, block)
         assert np.array_equal(codes.cpu().numpy(), ecodes)
+        s = host_scales(scales, block, codes.shape[-1])
         if block == 0:
-            assert np.array_equal(scales.cpu().numpy().view(np.uint32), escales.astype(np.float32).view(np.uint32))
+            assert np.array_equal(s.view(np.uint32), escales.astype(np.float32).view(np.uint32))
         else:
-            assert np.array_equal(scales.cpu().numpy(), escales)
+            assert np.array_equal(s, escales)
 
 
 # --------------------------------------------------------------------------
@@ -216,8 +235,13 @@ def f8_case(seed, batch, M, N, K, block, shared=False):
     X = random_source(seed + 1, (batch, 2, K, N), "f16", 30.0)
     Wq, Ws = gpu_quantize(W, True, tcbf.PLANAR, block)
     Xq, Xs = gpu_quantize(X, False, tcbf.PLANAR, block)
-    Wd = dequant(Wq.cpu().numpy(), Ws.cpu().numpy(), block, K)
-    Xd = dequant(Xq.cpu().numpy(), Xs.cpu().numpy(), block, K)
+    kp = tcbf.f8_kp(K)
+    Wd = dequant(Wq.cpu().numpy(), host_scales(Ws, block, kp), block, K)
+    Xd = dequant(Xq.cpu().numpy(), host_scales(Xs, block, kp), block, K)
+    if block:
+        # poison the padding the quantiser leaves unwritten: it must never be read
+        Ws[..., kp // 32:] = 255
+        Xs[..., kp // 32:] = 255
     return (Wq, Ws, Xq, Xs), (W, X), (Wd, Xd)
 
 
@@ -271,7 +295,7 @@ def test_gemm_exact_small_integers():
     # within 2^-2..2^7 and the instruction's group sums stay exact
     wsb = g.integers(126, 129, (batch, M, kp // 32)).astype(np.uint8)
     xsb = g.integers(126, 129, (batch, N, kp // 32)).astype(np.uint8)
-    got = run_f8(to_dev(Wc), to_dev(wsb), to_dev(Xc), to_dev(xsb), tcbf.MXF8_E4M3)
+    got = run_f8(to_dev(Wc), to_dev(pitched(wsb, K)), to_dev(Xc), to_dev(pitched(xsb, K)), tcbf.MXF8_E4M3)
     Wd, Xd = dequant(Wc, wsb, 32, K), dequant(Xc, xsb, 32, K)
     ref = oracle.cgemm(Wd, np.ascontiguousarray(Xd.transpose(0, 2, 1)))
     assert np.array_equal(got, ref)
@@ -295,7 +319,7 @@ def test_block_scales_apply_per_block():
     for m in range(M):
         ws[0, m, :] = 127 + np.arange(nb) - 3     # distinct exponent per block
     xs = np.full((batch, N, nb), 127, np.uint8)
-    got = run_f8(to_dev(Wc), to_dev(ws), to_dev(Xc), to_dev(xs), tcbf.MXF8_E4M3)
+    got = run_f8(to_dev(Wc), to_dev(pitched(ws, K)), to_dev(Xc), to_dev(pitched(xs, K)), tcbf.MXF8_E4M3)
     Wd, Xd = dequant(Wc, ws, 32, K), dequant(Xc, xs, 32, K)
     ref = oracle.cgemm(Wd, np.ascontiguousarray(Xd.transpose(0, 2, 1)))
     assert np.array_equal(got, ref)
@@ -358,8 +382,9 @@ def test_c4_full_size_sampled(c4_inputs, dtype):
     g = np.random.default_rng(11)
     ms = np.unique(np.concatenate([[0, M - 1], g.choice(M, 48, replace=False)]))
     Wq_s = Wq[:, :, torch.from_numpy(ms).cuda()].cpu().numpy()
-    Ws_s = Ws[:, torch.from_numpy(ms).cuda()].cpu().numpy()
-    Xq_h, Xs_h = Xq.cpu().numpy(), Xs.cpu().numpy()
+    kp = tcbf.f8_kp(K)
+    Ws_s = host_scales(Ws[:, torch.from_numpy(ms).cuda()], block, kp)
+    Xq_h, Xs_h = Xq.cpu().numpy(), host_scales(Xs, block, kp)
     # quantiser parity on the sampled rows and on all of X
     sub = np.ascontiguousarray(W[:, :, ms])
     ec, es = quant_expected(sub, True, tcbf.PLANAR, block)
