@@ -100,6 +100,51 @@ def time_launches(fn, steps, warmup):
     return start.elapsed_time(stop) / steps  # ms per launch
 
 
+def measure_peak(kind, random=False, target_ms=40.0, blocks=2048):
+    """Measured ceiling of one instruction kind (tcbf_peak_probe): a short
+    launch sizes the run to about target_ms, then the median of three timed
+    launches (HIP events on the launch stream).  The clock is the median over
+    workgroups of the shader-clock counter's advance over the constant 100 MHz
+    counter's during that workgroup's loop (each workgroup reads both on its
+    own compute unit)."""
+    import torch
+    import paper_2505_03269_amd as tcbf
+    stream = torch.cuda.current_stream()
+    sink = torch.empty(blocks * 256 * 4 + blocks * 32, dtype=torch.uint8, device="cuda:0")
+
+    def run(iters):
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        ops, _, marks = tcbf.peak_probe(kind, blocks, iters, operand_bits=None if not random else 2025, random=random,
+                                        sink=sink)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        return ops, t0.elapsed_time(t1), marks.cpu().numpy()
+    iters = 256
+    for _ in range(2):  # the first sizing run is dominated by launch overhead
+        _, ms, _ = run(iters)
+        iters = max(256, int(iters * min(target_ms / max(ms, 1e-3), 64.0)))
+    runs = sorted((run(iters) for _ in range(3)), key=lambda r: r[1])
+    ops, ms, m = runs[1]
+    ticks = (m[:, 2] - m[:, 0]).astype(np.float64)
+    real = (m[:, 3] - m[:, 1]).astype(np.float64)
+    ok = real > 0
+    clock = round(float(np.median(100.0 * ticks[ok] / real[ok])), 1) if ok.any() else None
+    return {"tops": round(ops / (ms * 1e-3) / 1e12, 1), "ms": round(ms, 3), "iterations": iters,
+            "shader_clock_mhz": clock}
+
+
+def peak_probes():
+    import paper_2505_03269_amd as tcbf
+    kinds = (("f16", tcbf.PROBE_F16), ("i8", tcbf.PROBE_I8), ("f8_e4m3", tcbf.PROBE_F8),
+             ("f4_e2m1", tcbf.PROBE_F4), ("valu_xor_popc", tcbf.PROBE_VALU_XOR_POPC))
+    out = {}
+    for name, kind in kinds:
+        out[name] = {"uniform": measure_peak(kind), "random": measure_peak(kind, random=True)}
+        log("peak probe %s: %s" % (name, out[name]))
+    return out
+
+
 def cpu_baseline(W, X, budget_s=12.0):
     """The oracle as it stands, timed on host cores on a bounded sample of the
     same workload: consecutive beam rows of the first channels."""
@@ -384,6 +429,11 @@ def main():
                 "frac": round(ach_flops / PEAK_F16_TFLOPS, 4), "traffic": traffic,
                 "algorithmic_bytes": info["algorithmic_bytes"],
                 "hbm_gbs_at_algorithmic_bytes": round(info["algorithmic_bytes"] / (ms * 1e-3) / 1e9, 1)}
+    probes = None if args.no_secondary else peak_probes()
+    if probes is not None:
+        roofline["measured_peak"] = probes["f16"]["uniform"]["tops"]
+        roofline["frac_of_measured_peak"] = round(ach_flops / probes["f16"]["uniform"]["tops"], 4)
+        roofline["measured_peak_random_operands"] = probes["f16"]["random"]["tops"]
     secondary = [] if args.no_secondary else bench_secondary(args.steps, serving=not args.no_serving)
     cpu = None if args.no_cpu_baseline else cpu_baseline(W, X)
     line = {
@@ -396,6 +446,7 @@ def main():
                    "kernel": info["kernel_name"], "workgroups": info["workgroups"]},
         "pct_of_fp16_peak": round(100.0 * tops / PEAK_F16_TFLOPS, 2),
         "roofline": roofline,
+        "peak_probe": probes,
         "cpu_baseline": cpu,
         "secondary": secondary,
     }

@@ -263,6 +263,50 @@ tcbf_status tcbf_group_execute(int32_t device, int32_t dtype, int32_t c_layout,
                                const tcbf_group_problem *problems, int32_t count,
                                void *workspace, void *stream);
 
+/*
+ * Peak probe (measurement tool, not a step of the product): the throughput of
+ * one matrix instruction (or of the VALU xor/popcount pair) on register
+ * operands with no global-memory traffic, the measured ceiling the paper
+ * places its kernels against (Sec. III-A, Table 1; Sec. IV-B).  Every wave
+ * of `blocks` workgroups of 256 threads runs `iterations` rounds of 4
+ * independent accumulations (VALU: 8 words per lane per round).  Operands:
+ *   TCBF_PROBE_UNIFORM: every element has the bit pattern `operand_bits`
+ *     (unit operands give closed-form accumulator values);
+ *   TCBF_PROBE_RANDOM: two sets of pseudo-random elements per lane (seeded
+ *     by operand_bits; fp16 and e4m3 in +-[0.5, 1)), alternated from one
+ *     instruction to the next as real data changes them -- the chip's power
+ *     draw and sustained clock depend on it.
+ * Kinds:
+ *   TCBF_PROBE_F16  v_mfma_f32_32x32x16_f16, element = operand_bits & 0xffff
+ *   TCBF_PROBE_I8   v_mfma_i32_32x32x32_i8, four int8 per 32-bit word
+ *   TCBF_PROBE_F8   scaled 32x32x64 f8f6f4 MFMA with e4m3 operands, scale 2^0
+ *   TCBF_PROBE_F4   the same instruction with e2m1 operands
+ *   TCBF_PROBE_VALU_XOR_POPC  per lane cnt += popcount(word ^ b), b changing
+ *                   every round (32 bit-products, counted as 64 operations)
+ *   sink (device, 16-byte aligned, sink_bytes >= blocks * 1056): first
+ *     uint32 [blocks * 256], one accumulator value per thread (float bits for
+ *     F16/F8/F4: the sum over the 4 chains of accumulator element
+ *     thread % 16;
+ *     int32 for I8; the VALU popcount total); then uint64 [blocks][4]: the
+ *     shader-clock counter and the constant 100 MHz counter read by thread 0
+ *     before and after its loop.
+ *   ops (host, may be NULL): the useful operations of the launch (2 per
+ *     multiply-add), to divide by the launch time the caller measures.
+ * Enqueues one kernel on `stream` of the current device; allocation-free.
+ */
+enum tcbf_probe_operands { TCBF_PROBE_UNIFORM = 0, TCBF_PROBE_RANDOM = 1 };
+
+enum tcbf_probe_kind {
+    TCBF_PROBE_F16 = 0,
+    TCBF_PROBE_I8 = 1,
+    TCBF_PROBE_F8 = 2,
+    TCBF_PROBE_F4 = 3,
+    TCBF_PROBE_VALU_XOR_POPC = 4
+};
+
+tcbf_status tcbf_peak_probe(int32_t kind, int64_t blocks, int64_t iterations, uint32_t operand_bits,
+                            int32_t operand_mode, void *sink, int64_t sink_bytes, double *ops, void *stream);
+
 /* Report the plan's choice.  info->struct_size must be set by the caller. */
 tcbf_status tcbf_plan_query(tcbf_plan_t plan, tcbf_plan_info *info);
 

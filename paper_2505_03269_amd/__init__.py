@@ -13,7 +13,7 @@ import os
 
 __all__ = [
     "F16", "INT1", "F8_E4M3", "MXF8_E4M3", "PLANAR", "INTERLEAVED", "SRC_I8", "SRC_F16", "SRC_F32",
-    "TcbfError", "Plan", "pack1bit", "quantize_e4m3", "steering_weights", "group_execute", "f8_kp", "mx_scale_pitch", "lib",
+    "TcbfError", "Plan", "pack1bit", "quantize_e4m3", "steering_weights", "group_execute", "peak_probe", "f8_kp", "mx_scale_pitch", "lib",
     "status_string", "EXPORTS", "GROUP_MAX", "GROUP_WORKSPACE_BYTES",
 ]
 
@@ -26,9 +26,14 @@ SRC_I8, SRC_F16, SRC_F32 = 0, 1, 2
 
 # every symbol include/tcbf.h declares
 EXPORTS = ("tcbf_plan", "tcbf_execute", "tcbf_pack1bit", "tcbf_quantize_e4m3", "tcbf_steering_weights",
-           "tcbf_group_execute", "tcbf_plan_query", "tcbf_plan_destroy", "tcbf_status_string", "tcbf_version")
+           "tcbf_peak_probe", "tcbf_group_execute", "tcbf_plan_query", "tcbf_plan_destroy", "tcbf_status_string",
+           "tcbf_version")
 GROUP_MAX = 32
 GROUP_WORKSPACE_BYTES = 256
+# peak-probe kinds, and the operand pattern of each whose products are all 1
+PROBE_F16, PROBE_I8, PROBE_F8, PROBE_F4, PROBE_VALU_XOR_POPC = 0, 1, 2, 3, 4
+PROBE_UNIT_OPERAND = {PROBE_F16: 0x3C00, PROBE_I8: 0x01010101, PROBE_F8: 0x38383838, PROBE_F4: 0x22222222,
+                      PROBE_VALU_XOR_POPC: 0x5A5A5A5A}
 
 _STATUS = {0: "TCBF_SUCCESS", 1: "TCBF_ERROR_INVALID_VALUE", 2: "TCBF_ERROR_NOT_SUPPORTED",
            3: "TCBF_ERROR_OUT_OF_MEMORY", 4: "TCBF_ERROR_DEVICE", 5: "TCBF_ERROR_INTERNAL"}
@@ -84,6 +89,8 @@ def lib():
     L.tcbf_quantize_e4m3.restype = i32
     L.tcbf_steering_weights.argtypes = [vp, vp, vp, ctypes.c_double, i64, i64, i64, i32, vp, vp]
     L.tcbf_steering_weights.restype = i32
+    L.tcbf_peak_probe.argtypes = [i32, i64, i64, ctypes.c_uint32, i32, vp, i64, ctypes.POINTER(ctypes.c_double), vp]
+    L.tcbf_peak_probe.restype = i32
     L.tcbf_group_execute.argtypes = [i32, i32, i32, ctypes.POINTER(GroupProblem), i32, vp, vp]
     L.tcbf_group_execute.restype = i32
     L.tcbf_plan_query.argtypes = [vp, ctypes.POINTER(PlanInfo)]
@@ -343,6 +350,32 @@ def steering_weights(positions, directions, frequencies, wave_speed, dtype=None,
                                        int(K), types[dtype], _dev_ptr(out, "out"), _stream_handle(stream)),
            "tcbf_steering_weights")
     return out
+
+
+def peak_probe(kind, blocks, iterations, operand_bits=None, random=False, sink=None, stream=None):
+    """Enqueue one peak-probe launch (measurement tool).  `random`: pseudo-random
+    operands alternating every instruction (seeded by operand_bits) instead of
+    uniform ones.  Returns (ops, values,
+    marks): the launch's useful operations, the uint32 [blocks * 256]
+    per-thread results and the uint64 [blocks, 4] clock marks (shader-clock
+    counter and 100 MHz counter before and after each workgroup's loop).
+    The caller times the launch on the stream."""
+    import torch
+    if kind not in PROBE_UNIT_OPERAND:
+        raise ValueError("unknown probe kind %r" % (kind,))
+    bits = PROBE_UNIT_OPERAND[kind] if operand_bits is None else int(operand_bits)
+    nbytes = int(blocks) * 256 * 4 + int(blocks) * 32
+    if sink is None:
+        sink = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    if sink.dtype != torch.uint8 or sink.numel() < nbytes:
+        raise ValueError("sink must be uint8 with at least %d bytes" % nbytes)
+    ops = ctypes.c_double(0.0)
+    _check(lib().tcbf_peak_probe(int(kind), int(blocks), int(iterations), bits & 0xFFFFFFFF, int(bool(random)),
+                                 _dev_ptr(sink, "sink"), int(sink.numel()), ctypes.byref(ops), _stream_handle(stream)),
+           "tcbf_peak_probe")
+    values = sink[:int(blocks) * 256 * 4].view(torch.int32)
+    marks = sink[int(blocks) * 256 * 4:nbytes].view(torch.int64).view(int(blocks), 4)
+    return ops.value, values, marks
 
 
 def group_execute(problems, c_layout=PLANAR, workspace=None, device=0, stream=None):

@@ -258,6 +258,19 @@ tcbf_status tcbf_steering_weights(const double *positions, const double *directi
     return e == hipSuccess ? TCBF_SUCCESS : TCBF_ERROR_DEVICE;
 }
 
+tcbf_status tcbf_peak_probe(int32_t kind, int64_t blocks, int64_t iterations, uint32_t operand_bits,
+                            int32_t operand_mode, void *sink, int64_t sink_bytes, double *ops, void *stream) {
+    if (kind < TCBF_PROBE_F16 || kind > TCBF_PROBE_VALU_XOR_POPC) return TCBF_ERROR_INVALID_VALUE;
+    if (operand_mode != TCBF_PROBE_UNIFORM && operand_mode != TCBF_PROBE_RANDOM) return TCBF_ERROR_INVALID_VALUE;
+    if (blocks < 1 || iterations < 1 || sink == nullptr || !aligned16(sink)) return TCBF_ERROR_INVALID_VALUE;
+    if (blocks >= kMaxIndex / 256 || iterations > ((int64_t)1 << 40)) return TCBF_ERROR_NOT_SUPPORTED;
+    if (sink_bytes < tcbf::peak_probe_sink_bytes(blocks)) return TCBF_ERROR_INVALID_VALUE;
+    if (ops != nullptr) *ops = tcbf::peak_probe_ops(kind, blocks, iterations);
+    hipError_t e = tcbf::peak_probe_launch(kind, blocks, iterations, operand_bits, operand_mode == TCBF_PROBE_RANDOM,
+                                           sink, (hipStream_t)stream);
+    return e == hipSuccess ? TCBF_SUCCESS : TCBF_ERROR_DEVICE;
+}
+
 tcbf_status tcbf_group_execute(int32_t device, int32_t dtype, int32_t c_layout, const tcbf_group_problem *problems,
                                int32_t count, void *workspace, void *stream) {
     if (problems == nullptr || workspace == nullptr) return TCBF_ERROR_INVALID_VALUE;

@@ -104,4 +104,10 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nblocks) {
     return (bid % kXcds) * (full / kXcds) + bid / kXcds;
 }
 
+// Peak probe (measurement tool): kinds as enum tcbf_probe_kind.
+double peak_probe_ops(int kind, int64_t blocks, int64_t iterations);
+int64_t peak_probe_sink_bytes(int64_t blocks);
+hipError_t peak_probe_launch(int kind, int64_t blocks, int64_t iterations, uint32_t operand_bits, int random,
+                             void *sink, hipStream_t stream);
+
 }  // namespace tcbf

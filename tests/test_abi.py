@@ -135,6 +135,23 @@ def test_steering_argument_checks():
     assert L.tcbf_steering_weights(p, p, p, 3e8, 1, 1, 1, 1, ctypes.c_void_p(addr + 8), None) == 1
 
 
+def test_peak_probe_argument_checks():
+    L = tcbf.lib()
+    buf = ctypes.create_string_buffer(2048)
+    addr = (ctypes.addressof(buf) + 15) & ~15
+    p = ctypes.c_void_p(addr)
+    need = 256 * 4 + 32
+    assert L.tcbf_peak_probe(5, 1, 1, 0, 0, p, need, None, None) == 1                       # unknown kind
+    assert L.tcbf_peak_probe(-1, 1, 1, 0, 0, p, need, None, None) == 1
+    assert L.tcbf_peak_probe(0, 1, 1, 0, 2, p, need, None, None) == 1                       # unknown operand mode
+    assert L.tcbf_peak_probe(0, 0, 1, 0, 0, p, need, None, None) == 1                       # no blocks
+    assert L.tcbf_peak_probe(0, 1, 0, 0, 0, p, need, None, None) == 1                       # no iterations
+    assert L.tcbf_peak_probe(0, 1, 1, 0, 0, None, need, None, None) == 1                    # no sink
+    assert L.tcbf_peak_probe(0, 1, 1, 0, 0, ctypes.c_void_p(addr + 4), need, None, None) == 1  # misaligned
+    assert L.tcbf_peak_probe(0, 1, 1, 0, 0, p, need - 1, None, None) == 1                   # sink too small
+    assert L.tcbf_peak_probe(0, 1, 1 << 41, 0, 0, p, need, None, None) == 2                 # too many rounds
+
+
 def test_group_argument_checks():
     L = tcbf.lib()
     buf = ctypes.create_string_buffer(1024)
