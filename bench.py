@@ -343,6 +343,7 @@ def bench_serving(warmup=1000, measured=10000):
             "value": round(r["tops"], 1), "unit": "TeraOps/s", "p50_ms": round(r["p50_ms"], 3),
             "p99_ms": round(r["p99_ms"], 3), "capacity_jobs_per_s": round(cap, 1),
             "closed_loop": rnd(closed), "load_0.8": rnd(runs[0.8]), "load_0.5": rnd(runs[0.5]),
+            "completed": r["completed"], "rejected": r["rejected"], "failed": r["failed"],
             "warmup_jobs": warmup, "measured_jobs": measured, "streams": len(srv.streams),
             "budget_bytes": srv.budget}
 

@@ -18,7 +18,20 @@ A job asks for B = W . X with one of the resident weight sets (fp16, FP8 or
     on the host clock, queueing included), p50 / p99, and throughput as useful
     operations (8 per complex multiply-accumulate) over the makespan.
 
-Every product runs in the library; this module only schedules.
+Failure handling: a job that can never run (unknown dtype or weight set, a
+sample count the kernels do not take, more memory than the whole budget) is
+rejected when it arrives and the others go on; a job that does not fit the
+memory still free waits; a job cancelled before its batch is launched gives
+its memory and slot back at once (after launch, when its batch completes,
+and its output is dropped); a launch or completion error fails that batch's
+jobs only.  Every job ends with a status: done, rejected, cancelled or
+failed.
+
+The admission and batching logic (Scheduler) is independent of the device:
+it drives an executor with launch / done / release calls.  GpuExecutor runs
+the batches through the library; tests drive the scheduler with a scripted
+executor on the CPU.  Every product runs in the library; this module only
+schedules.
 """
 import time
 
@@ -52,13 +65,21 @@ class WeightSet:
                                                                self.scale.numel() * self.scale.element_size())
 
 
-class Job:
-    __slots__ = ("jid", "arrival", "dtype", "wid", "N", "seed", "t_done", "out", "X", "xs", "nbytes", "M", "K")
+DONE, REJECTED, CANCELLED, FAILED = "done", "rejected", "cancelled", "failed"
 
-    def __init__(self, jid, arrival, dtype, wid, N, seed):
+
+class Job:
+    __slots__ = ("jid", "arrival", "dtype", "wid", "N", "seed", "t_done", "out", "X", "xs", "nbytes", "M", "K",
+                 "status", "error", "cancel_at")
+
+    def __init__(self, jid, arrival, dtype, wid, N, seed, cancel_at=None):
         self.jid, self.arrival, self.dtype, self.wid, self.N, self.seed = jid, arrival, dtype, wid, N, seed
         self.t_done = None
         self.out = self.X = self.xs = None
+        self.M = self.K = 0
+        self.nbytes = 0
+        self.status = self.error = None
+        self.cancel_at = cancel_at   # client cancels at this time (relative, like arrival), or never
 
     @property
     def ops(self):
@@ -142,99 +163,27 @@ class Server:
             self.plans[key] = p
         return p
 
-    # -- one batch ------------------------------------------------------------
-    def launch(self, batch, si):
-        """Enqueue the jobs of one batch on stream si; returns its done-event."""
-        import torch
-        s = self.streams[si]
-        with torch.cuda.stream(s):
-            f16 = []
-            for job in batch:
-                ws = self.pool[(job.dtype, job.wid)]
-                X = job_input(job, self.device, self.gen)
-                job.out = torch.empty((1, 2, job.M, job.N), dtype=out_dtype(job.dtype), device=self.device)
-                if job.dtype == F16:
-                    job.X = X
-                    f16.append((ws.A, X, job.out))
-                elif job.dtype == F8_E4M3:
-                    job.X, job.xs = quantize_e4m3(X, k_major=False, block=0)
-                    self._plan(F8_E4M3, job.M, job.N, job.K).execute(ws.A, job.X, job.out, ws.scale, job.xs)
-                else:
-                    job.X = pack1bit(X, k_major=False)
-                    self._plan(INT1, job.M, job.N, job.K).execute(ws.A, job.X, job.out)
-            for i in range(0, len(f16), GROUP_MAX):
-                group_execute(f16[i:i + GROUP_MAX], workspace=self.workspaces[si], device=self.dev_index)
-            ev = torch.cuda.Event()
-            ev.record(s)
-        return ev
+    def validate(self, job):
+        """Why `job` can never run here, or None."""
+        if job.dtype not in self.dtypes or (job.dtype, job.wid) not in self.pool:
+            return "unknown dtype or weight set"
+        if job.N < 1 or job.N % 8 != 0:
+            return "N must be a positive multiple of 8"
+        if job.nbytes > self.budget:
+            return "needs %d bytes, more than the memory budget of %d" % (job.nbytes, self.budget)
+        return None
 
-    # -- the loop -------------------------------------------------------------
     def run(self, jobs, keep_outputs=False, max_batch=GROUP_MAX):
         """Serve `jobs` in real time (their arrival times are relative to the
-        start of the call).  Returns a summary dict; job.t_done is filled."""
+        start of the call).  Returns a summary dict; every job gets a status,
+        and job.t_done when it left the server."""
         import torch
         torch.cuda.synchronize()
-        n = len(jobs)
-        pending = []          # arrived, not yet admitted
-        admitted = []         # admitted, not yet launched
-        inflight = []         # (stream index, event, jobs)
-        busy = [0] * len(self.streams)
-        used_bytes, used_slots = 0, 0
-        nxt, done = 0, 0
-        self.batch_sizes, self.max_inflight = [], 0
-        t0 = time.perf_counter()
-        while done < n:
-            now = time.perf_counter() - t0
-            while nxt < n and jobs[nxt].arrival <= now:
-                pending.append(jobs[nxt])
-                nxt += 1
-            # completions
-            still = []
-            for si, ev, batch in inflight:
-                if ev.query():
-                    t = time.perf_counter() - t0
-                    for job in batch:
-                        job.t_done = t
-                        used_bytes -= job.nbytes
-                        used_slots -= 1
-                        if not keep_outputs:
-                            job.out = None
-                        job.X = job.xs = None
-                    done += len(batch)
-                    busy[si] -= 1
-                else:
-                    still.append((si, ev, batch))
-            inflight = still
-            # admission in arrival order
-            while pending and used_slots < self.max_slots and used_bytes + pending[0].nbytes <= self.budget:
-                job = pending.pop(0)
-                used_bytes += job.nbytes
-                used_slots += 1
-                admitted.append(job)
-            if pending and used_slots == 0 and pending[0].nbytes > self.budget:
-                raise RuntimeError("job %d needs more than the memory budget" % pending[0].jid)
-            # launch on a free stream
-            if admitted:
-                si = min(range(len(self.streams)), key=lambda i: busy[i])
-                if busy[si] == 0:
-                    batch, admitted = admitted[:max_batch], admitted[max_batch:]
-                    ev = self.launch(batch, si)
-                    busy[si] += 1
-                    inflight.append((si, ev, batch))
-                    self.batch_sizes.append(len(batch))
-                    self.max_inflight = max(self.max_inflight, len(inflight))
-                    continue
-            if not inflight and not admitted and nxt < n:
-                wait = jobs[nxt].arrival - (time.perf_counter() - t0)
-                if wait > 2e-4:
-                    time.sleep(wait - 1e-4)
-        makespan = max(j.t_done for j in jobs) - min(j.arrival for j in jobs)
-        lat = np.array([j.t_done - j.arrival for j in jobs])
-        ops = sum(j.ops for j in jobs)
-        return {"jobs": n, "makespan_s": makespan, "tops": ops / makespan / 1e12,
-                "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
-                "mean_ms": float(lat.mean() * 1e3),
-                "by_dtype": {DTYPE_NAMES[d]: int(sum(1 for j in jobs if j.dtype == d)) for d in self.dtypes}}
+        sched = Scheduler(self.budget, self.max_slots, len(self.streams), max_batch, self.validate)
+        summary = sched.run(jobs, GpuExecutor(self), keep_outputs)
+        self.batch_sizes, self.max_inflight = sched.batch_sizes, sched.max_inflight
+        summary["by_dtype"] = {DTYPE_NAMES[d]: int(sum(1 for j in jobs if j.dtype == d)) for d in self.dtypes}
+        return summary
 
     def run_alone(self, job):
         """The job's product on its own (one plain launch), for comparison."""
@@ -251,6 +200,163 @@ class Server:
             self._plan(INT1, job.M, job.N, job.K).execute(ws.A, pack1bit(X, k_major=False), out)
         torch.cuda.synchronize()
         return out
+
+
+class GpuExecutor:
+    """Runs batches through the library on the server's streams: the fp16 jobs
+    of a batch in one grouped launch, FP8 and 1-bit jobs as plan launches.  A
+    batch's handle is an event recorded after its launches."""
+
+    def __init__(self, server):
+        self.srv = server
+
+    def launch(self, batch, si):
+        import torch
+        srv = self.srv
+        s = srv.streams[si]
+        with torch.cuda.stream(s):
+            f16 = []
+            for job in batch:
+                ws = srv.pool[(job.dtype, job.wid)]
+                X = job_input(job, srv.device, srv.gen)
+                job.out = torch.empty((1, 2, job.M, job.N), dtype=out_dtype(job.dtype), device=srv.device)
+                if job.dtype == F16:
+                    job.X = X
+                    f16.append((ws.A, X, job.out))
+                elif job.dtype == F8_E4M3:
+                    job.X, job.xs = quantize_e4m3(X, k_major=False, block=0)
+                    srv._plan(F8_E4M3, job.M, job.N, job.K).execute(ws.A, job.X, job.out, ws.scale, job.xs)
+                else:
+                    job.X = pack1bit(X, k_major=False)
+                    srv._plan(INT1, job.M, job.N, job.K).execute(ws.A, job.X, job.out)
+            for i in range(0, len(f16), GROUP_MAX):
+                group_execute(f16[i:i + GROUP_MAX], workspace=srv.workspaces[si], device=srv.dev_index)
+            ev = torch.cuda.Event()
+            ev.record(s)
+        return ev
+
+    def done(self, handle):
+        return handle.query()
+
+    def release(self, job, keep_output):
+        if not keep_output:
+            job.out = None
+        job.X = job.xs = None
+
+
+class Scheduler:
+    """Admission in arrival order under a memory budget and a slot limit,
+    batching of admitted jobs, one batch in flight per stream.  `validate(job)`
+    returns why a job can never run (it is rejected on arrival) or None.
+
+    The executor provides launch(batch, stream_index) -> handle,
+    done(handle) -> bool and release(job, keep_output); an exception from
+    launch or done fails that batch's jobs and the loop goes on."""
+
+    def __init__(self, budget, max_slots, streams, max_batch=GROUP_MAX, validate=None):
+        self.budget, self.max_slots, self.streams, self.max_batch = budget, max_slots, streams, max_batch
+        self.validate = validate or (lambda job: None)
+        self.batch_sizes, self.max_inflight = [], 0
+
+    def run(self, jobs, executor, keep_outputs=False, clock=time.perf_counter, sleep=time.sleep):
+        n = len(jobs)
+        order = sorted(range(n), key=lambda i: jobs[i].arrival)
+        pending = []          # arrived, waiting for memory or a slot
+        admitted = []         # holding memory and a slot, not yet launched
+        inflight = []         # (stream index, handle, jobs)
+        busy = [False] * self.streams
+        used = {"bytes": 0, "slots": 0}
+        nxt, left = 0, n
+        cancels = any(j.cancel_at is not None for j in jobs)
+        self.batch_sizes, self.max_inflight = [], 0
+        t0 = clock()
+
+        def finish(job, status, error=None, free=True):
+            nonlocal left
+            job.status, job.error, job.t_done = status, error, clock() - t0
+            if free:
+                used["bytes"] -= job.nbytes
+                used["slots"] -= 1
+            executor.release(job, keep_outputs and status == DONE)
+            left -= 1
+
+        while left > 0:
+            now = clock() - t0
+            while nxt < n and jobs[order[nxt]].arrival <= now:
+                job = jobs[order[nxt]]
+                nxt += 1
+                why = self.validate(job)
+                if why is not None:
+                    finish(job, REJECTED, why, free=False)
+                else:
+                    pending.append(job)
+            # client cancellations before launch: memory and slot come back now
+            for q, holds in (((pending, False), (admitted, True)) if cancels else ()):
+                for job in [j for j in q if j.cancel_at is not None and j.cancel_at <= now]:
+                    q.remove(job)
+                    finish(job, CANCELLED, free=holds)
+            # completions
+            still = []
+            for si, h, batch in inflight:
+                try:
+                    ok, err = executor.done(h), None
+                except Exception as e:  # noqa: BLE001 -- the batch fails, the server goes on
+                    ok, err = True, e
+                if not ok:
+                    still.append((si, h, batch))
+                    continue
+                for job in batch:
+                    if err is not None:
+                        finish(job, FAILED, repr(err))
+                    elif job.cancel_at is not None and job.cancel_at <= clock() - t0:
+                        finish(job, CANCELLED)
+                    else:
+                        finish(job, DONE)
+                busy[si] = False
+            inflight = still
+            # admission in arrival order
+            while pending and used["slots"] < self.max_slots and used["bytes"] + pending[0].nbytes <= self.budget:
+                job = pending.pop(0)
+                used["bytes"] += job.nbytes
+                used["slots"] += 1
+                admitted.append(job)
+            # launch on a free stream
+            free = [i for i in range(self.streams) if not busy[i]]
+            if admitted and free:
+                si = free[0]
+                batch, admitted = admitted[:self.max_batch], admitted[self.max_batch:]
+                try:
+                    h = executor.launch(batch, si)
+                except Exception as e:  # noqa: BLE001
+                    for job in batch:
+                        finish(job, FAILED, repr(e))
+                    continue
+                busy[si] = True
+                inflight.append((si, h, batch))
+                self.batch_sizes.append(len(batch))
+                self.max_inflight = max(self.max_inflight, len(inflight))
+                continue
+            if not inflight and not admitted and nxt < n:
+                wait = jobs[order[nxt]].arrival - (clock() - t0)
+                if wait > 2e-4:
+                    sleep(wait - 1e-4)
+        return summarise(jobs)
+
+
+def summarise(jobs):
+    """Latency and throughput over the completed jobs, counts by status."""
+    ok = [j for j in jobs if j.status == DONE]
+    out = {"jobs": len(jobs), "completed": len(ok)}
+    for st in (REJECTED, CANCELLED, FAILED):
+        out[st] = sum(1 for j in jobs if j.status == st)
+    if ok:
+        makespan = max(j.t_done for j in ok) - min(j.arrival for j in ok)
+        lat = np.array([j.t_done - j.arrival for j in ok])
+        ops = sum(j.ops for j in ok)
+        out.update({"makespan_s": makespan, "tops": ops / makespan / 1e12 if makespan > 0 else 0.0,
+                    "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                    "mean_ms": float(lat.mean() * 1e3)})
+    return out
 
 
 def serve_benchmark(warmup=1000, measured=10000, load=0.8, seed=0, device=0, server=None):

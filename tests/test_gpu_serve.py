@@ -61,7 +61,29 @@ def test_mixed_results_match_oracle(server):
 
 
 def test_budget_too_small_is_reported():
+    """Jobs larger than the whole budget are rejected with a reason; the run
+    still returns."""
     srv = serve.Server(pool_per_dtype=1, dtypes=(tcbf.F16,), budget_bytes=1 << 10, streams=1, seed=4)
     jobs = srv.make_jobs(2, rate=None, seed=9)
-    with pytest.raises(RuntimeError):
-        srv.run(jobs)
+    summary = srv.run(jobs)
+    assert summary["rejected"] == 2 and summary["completed"] == 0
+    assert all(j.status == serve.REJECTED and "budget" in j.error for j in jobs)
+
+
+def test_rejected_and_cancelled_jobs_leave_the_rest_intact(server):
+    """A mix with an unknown weight set, an odd sample count and a job
+    cancelled before it can start: those three leave with their status, every
+    other job completes with the same result as alone."""
+    jobs = server.make_jobs(10, rate=None, seed=12)
+    server.budget = 1 << 34
+    jobs[2].wid = 999
+    jobs[5].N = 300
+    jobs[5].nbytes = server.job_bytes(jobs[5])
+    jobs[7].cancel_at = 0.0
+    summary = server.run(jobs, keep_outputs=True)
+    assert jobs[2].status == serve.REJECTED and jobs[5].status == serve.REJECTED
+    assert jobs[7].status == serve.CANCELLED and jobs[7].out is None
+    assert summary["completed"] == 7
+    for job in jobs:
+        if job.status == serve.DONE:
+            assert torch.equal(job.out, server.run_alone(job))
