@@ -100,10 +100,12 @@ typedef enum tcbf_src_type {
  *                     b_scale [batch][N]; out = a_scale[m] * b_scale[n] *
  *                     sum_k decode(W[m][k]) * decode(X[n][k]) (complex)
  *     TCBF_MXF8_E4M3: uint8 E8M0 codes (2^(code-127), 255 not allowed)
- *                     a_scale [batch][M][Ks] (or [M][Ks]), b_scale
- *                     [batch][N][Ks], Ks = 16 * ceil(Kp / 512): codes of
- *                     blocks j = 0 .. Kp/32 - 1 (block j scales receivers
- *                     32j..32j+31), then padding the library never uses
+ *                     in groups of 16 blocks: a_scale [batch][Ks/16][M][16]
+ *                     (or [Ks/16][M][16]), b_scale [batch][Ks/16][N][16],
+ *                     Ks = 16 * ceil(Kp / 512); block j of row r (scaling
+ *                     receivers 32j..32j+31) is at [j / 16][r][j % 16];
+ *                     codes of blocks j >= Kp/32 are padding the library
+ *                     never uses
  *
  * a_shared != 0: W holds a single batch entry that every channel uses.
  * C is always overwritten (the output starts from zero, as in Sec. III-B).
@@ -194,8 +196,8 @@ tcbf_status tcbf_pack1bit(const void *src, int32_t src_type, int32_t src_layout,
  *   src (device), src_type, src_layout and src_k_major as for tcbf_pack1bit.
  *   dst (device): [batch][2][rows][Kp] bytes, Kp = 32 * ceil(K / 32), zero
  *   past K.  scales (device): block 0: fp32 [batch][rows]; block 32: uint8
- *   [batch][rows][Ks], Ks = 16 * ceil(Kp / 512) (the padding bytes past
- *   Kp / 32 are not written).
+ *   [batch][Ks / 16][rows][16], Ks = 16 * ceil(Kp / 512), block j of row r
+ *   at [j / 16][r][j % 16] (the padding codes j >= Kp / 32 are not written).
  * src, dst and scales must be 16-byte aligned device buffers that do not
  * overlap.  Enqueues several kernels on `stream`; allocation-free.
  */

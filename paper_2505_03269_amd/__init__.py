@@ -13,7 +13,8 @@ import os
 
 __all__ = [
     "F16", "INT1", "F8_E4M3", "MXF8_E4M3", "PLANAR", "INTERLEAVED", "SRC_I8", "SRC_F16", "SRC_F32",
-    "TcbfError", "Plan", "pack1bit", "quantize_e4m3", "steering_weights", "group_execute", "peak_probe", "f8_kp", "mx_scale_pitch", "lib",
+    "TcbfError", "Plan", "pack1bit", "quantize_e4m3", "steering_weights", "group_execute", "peak_probe", "f8_kp", "mx_scale_pitch", "mx_scales_to_rows",
+    "mx_scales_from_rows", "lib",
     "status_string", "EXPORTS", "GROUP_MAX", "GROUP_WORKSPACE_BYTES",
 ]
 
@@ -116,6 +117,29 @@ def mx_scale_pitch(K):
     return (f8_kp(K) // 32 + 15) // 16 * 16
 
 
+def mx_scales_to_rows(scales, K):
+    """Per-block scale codes in the library's grouped layout [..., Ks/16, rows,
+    16] -> [..., rows, Kp/32] (row-major blocks; works on numpy arrays and
+    tensors)."""
+    g = scales.shape[-3]
+    rows = scales.shape[-2]
+    lead = tuple(scales.shape[:-3])
+    t = scales.swapaxes(-3, -2) if hasattr(scales, "swapaxes") else scales.transpose(-3, -2)
+    return t.reshape(lead + (rows, 16 * g))[..., :f8_kp(K) // 32]
+
+
+def mx_scales_from_rows(codes, K, pad=0):
+    """Row-major per-block codes [..., rows, Kp/32] (numpy) -> the grouped
+    layout [..., Ks/16, rows, 16], padding codes set to `pad`."""
+    import numpy as np
+    ks = mx_scale_pitch(K)
+    rows = codes.shape[-2]
+    lead = tuple(codes.shape[:-2])
+    full = np.full(lead + (rows, ks), pad, np.uint8)
+    full[..., :codes.shape[-1]] = codes
+    return np.ascontiguousarray(full.reshape(lead + (rows, ks // 16, 16)).swapaxes(-3, -2))
+
+
 def _is_f8(dtype):
     return dtype in (F8_E4M3, MXF8_E4M3)
 
@@ -194,12 +218,14 @@ class Plan:
         return (self.batch, 2, self.K, self.N) if self.b_layout == PLANAR else (self.batch, self.K, self.N, 2)
 
     def shape_a_scale(self):
-        """FP8 modes: W scales ([nb, M] fp32 per row, [nb, M, Ks] uint8 per block)."""
+        """FP8 modes: W scales ([nb, M] fp32 per row; per block uint8 codes in
+        groups of 16, [nb, Ks/16, M, 16])."""
         nb = 1 if self.a_shared else self.batch
-        return (nb, self.M) if self.dtype == F8_E4M3 else (nb, self.M, mx_scale_pitch(self.K))
+        return (nb, self.M) if self.dtype == F8_E4M3 else (nb, mx_scale_pitch(self.K) // 16, self.M, 16)
 
     def shape_b_scale(self):
-        return (self.batch, self.N) if self.dtype == F8_E4M3 else (self.batch, self.N, mx_scale_pitch(self.K))
+        return ((self.batch, self.N) if self.dtype == F8_E4M3
+                else (self.batch, mx_scale_pitch(self.K) // 16, self.N, 16))
 
     def shape_c(self):
         return (self.batch, 2, self.M, self.N) if self.c_layout == PLANAR else (self.batch, self.M, self.N, 2)
@@ -298,8 +324,9 @@ def quantize_e4m3(src, k_major=True, layout=PLANAR, block=0, out=None, scales=No
 
     Source orientation as for pack1bit.  Returns (codes, scales): uint8 codes
     [batch, 2, rows, Kp] and fp32 scales [batch, rows] (block=0) or uint8 E8M0
-    codes [batch, rows, Ks] (block=32; Ks = mx_scale_pitch(K), bytes past
-    Kp/32 not written).
+    codes in groups of 16 blocks [batch, Ks/16, rows, 16] (block=32; Ks =
+    mx_scale_pitch(K); block j of row r at [j // 16, r, j % 16]; codes past
+    Kp/32 not written).  mx_scales_to_rows turns them into [batch, rows, Kp/32].
     """
     import torch
     types = {torch.int8: SRC_I8, torch.float16: SRC_F16, torch.float32: SRC_F32}
@@ -313,10 +340,11 @@ def quantize_e4m3(src, k_major=True, layout=PLANAR, block=0, out=None, scales=No
         if block == 0:
             scales = torch.empty((batch, rows), dtype=torch.float32, device=src.device)
         else:
-            scales = torch.empty((batch, rows, mx_scale_pitch(kk)), dtype=torch.uint8, device=src.device)
+            scales = torch.empty((batch, mx_scale_pitch(kk) // 16, rows, 16), dtype=torch.uint8, device=src.device)
     if tuple(out.shape) != (batch, 2, rows, kp) or out.dtype != torch.uint8:
         raise ValueError("out must be uint8 [batch, 2, rows, Kp]")
-    want = ((batch, rows), torch.float32) if block == 0 else ((batch, rows, mx_scale_pitch(kk)), torch.uint8)
+    want = (((batch, rows), torch.float32) if block == 0
+            else ((batch, mx_scale_pitch(kk) // 16, rows, 16), torch.uint8))
     if tuple(scales.shape) != want[0] or scales.dtype != want[1]:
         raise ValueError("scales must be %s %s" % (want[1], want[0]))
     _check(lib().tcbf_quantize_e4m3(_dev_ptr(src, "src"), types[src.dtype], int(layout), int(batch), int(rows),

@@ -9,8 +9,10 @@
 //     -- the scales factor out of the sum, so they are applied in the epilogue;
 //   per-block scales (TCBF_MXF8_E4M3): every 32-receiver block carries its own
 //     power-of-two scales, applied inside the scaled MFMA per lane.  Scale
-//     codes are [batch][rows][Ks] bytes, Ks = 16 * ceil(Kp / 512): the row's
-//     Kp / 32 block codes, then padding that is never used.
+//     codes are [batch][Ks / 16][rows][16] bytes, Ks = 16 * ceil(Kp / 512):
+//     group g holds blocks 16 g .. 16 g + 15 of every row (codes past Kp / 32
+//     are padding that is never used), so the codes a workgroup needs for 8
+//     stages are one contiguous run per 128 rows.
 // As in the 16-bit kernel, the imaginary part of the product uses W's
 // imaginary plane negated in registers (a sign-bit flip, exact in e4m3).
 //
@@ -129,8 +131,8 @@ __global__ __launch_bounds__(NT, 2) void cgemm_f8_kernel(
 
     // Block scales travel through LDS: every SLAB_STAGES stages one direct
     // 16-byte load per lane brings the next 16 block codes of one staged row
-    // (waves 0, 1: W rows 0..63, 64..127; waves 2, 3: the same X rows) into
-    // the slab slot (kt / SLAB_STAGES) % 2.  A slot's next load is issued
+    // (waves 0, 1: W rows 0..63, 64..127; waves 2, 3: the same X rows; one
+    // contiguous KiB per wave) into the slab slot (kt / SLAB_STAGES) % 2.  A slot's next load is issued
     // SLAB_STAGES + 2 - NS steps after the step that read its last stage, so
     // a ring barrier lies between them.  Compute reads this
     // lane's four codes (beams fw, fw + 32; samples fx, fx + 32; block
@@ -141,13 +143,15 @@ __global__ __launch_bounds__(NT, 2) void cgemm_f8_kernel(
     const int so = wave >> 1;                                       // slab operand of this wave
     __amdgpu_buffer_rsrc_t rss = __builtin_amdgcn_make_buffer_rsrc((void *)a_scale, 0, 0, RSRC_FLAGS);
     uint32_t slab_off = OOB;
+    int group_bytes = 0;  // one group of 16 codes of every row of this operand
     if (MX) {
         const int rows = so ? N : M;
         const uint8_t *base = so ? (const uint8_t *)b_scale + (int64_t)c * N * ks
                                  : (const uint8_t *)a_scale + (int64_t)cw * M * ks;
         rss = __builtin_amdgcn_make_buffer_rsrc((void *)base, 0, rows * ks, RSRC_FLAGS);
         const int r = (so ? n0 : m0) + 64 * (wave & 1) + lane;
-        slab_off = r < rows ? (uint32_t)(r * ks) : OOB;
+        slab_off = r < rows ? (uint32_t)(r * SLAB_ROWB) : OOB;
+        group_bytes = rows * SLAB_ROWB;
     }
 
     auto issue = [&](char *base, int kt) {
@@ -170,7 +174,7 @@ __global__ __launch_bounds__(NT, 2) void cgemm_f8_kernel(
         if (MX && kt % SLAB_STAGES == 0)
             __builtin_amdgcn_raw_ptr_buffer_load_lds(
                 rss, (TCBF_LDS_AS void *)(slabs + (kt / SLAB_STAGES % 2) * SLAB + so * (SLAB / 2) + (wave & 1) * 1024),
-                16, slab_off, 2 * kt, 0, 0);
+                16, slab_off, (kt / SLAB_STAGES) * group_bytes, 0, 0);
     };
 
     Acc acc;

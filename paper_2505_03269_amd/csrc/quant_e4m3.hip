@@ -15,8 +15,9 @@
 //
 // Destination: [batch][2][rows][Kp] e4m3 bytes, Kp = 32 * ceil(K / 32), bytes
 // past K zero.  Scales: per-row fp32 [batch][rows]; per-block uint8 E8M0
-// [batch][rows][Ks] (value 2^(code - 127)), Ks = mx_scale_pitch(Kp); the
-// padding bytes past Kp / 32 are not written.
+// [batch][Ks / 16][rows][16] (value 2^(code - 127), block kb of row r at
+// [kb / 16][r][kb % 16]), Ks = mx_scale_pitch(Kp); the padding codes past
+// Kp / 32 are not written.
 //
 // Work is cut into tiles of 64 rows x 64 receivers.  The tile loads follow the
 // source's contiguous axis (receivers for K-major W, rows for N-major X), the
@@ -225,7 +226,7 @@ __global__ __launch_bounds__(NT) void quantize_kernel(const T *__restrict__ src,
             const int r = t >> 1, blk = t & 1;
             const int64_t row = ti.r0 + r, kb = ti.k0 / 32 + blk;
             if (row < rows && kb < kp / 32)
-                ((uint8_t *)scales)[(ti.b * rows + row) * mx_scale_pitch(kp) + kb] =
+                ((uint8_t *)scales)[((ti.b * (mx_scale_pitch(kp) / 16) + kb / 16) * rows + row) * 16 + kb % 16] =
                     (uint8_t)(mx_exponent(__uint_as_float(bmax[r][blk])) + 127);
         }
     }

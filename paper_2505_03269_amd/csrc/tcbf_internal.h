@@ -43,9 +43,10 @@ struct F8Config {
     int tile_m, tile_n, tile_k, threads;
 };
 int64_t f8_kp(int64_t K);
-// Row pitch in bytes of per-block E8M0 scales for a code row pitch of kp
-// bytes: kp / 32 block codes, padded to a multiple of 16 so the product kernel
-// moves 16 codes per row with one aligned 16-byte load.
+// Per-row count of per-block E8M0 scale codes for a code row pitch of kp
+// bytes: kp / 32 block codes, padded to a multiple of 16 (the scales are
+// stored in groups of 16 codes per row, [Ks / 16][rows][16], so the product
+// kernel moves one group of consecutive rows with contiguous loads).
 __host__ __device__ inline int64_t mx_scale_pitch(int64_t kp) { return (kp / 32 + 15) / 16 * 16; }
 bool f8_select(const Problem &p, int forced_variant, F8Config *cfg);
 int64_t f8_workgroups(const Problem &p, const F8Config &cfg);

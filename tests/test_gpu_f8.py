@@ -84,19 +84,32 @@ def dequant(codes, scales, block, K):
 
 
 def host_scales(scales, block, kp):
-    """Device scales -> numpy; per-block codes without the row padding."""
+    """Device scales -> numpy; per-block codes as [..., rows, Kp/32]."""
     s = scales.cpu().numpy()
-    return s if block == 0 else np.ascontiguousarray(s[..., :kp // 32])
+    return s if block == 0 else np.ascontiguousarray(tcbf.mx_scales_to_rows(s, kp))
 
 
 def pitched(codes, K):
-    """Per-block codes [..., Kp/32] -> the library's [..., Ks] layout, the
-    padding filled with 255 (the E8M0 NaN code): a kernel that read any
-    padding byte would produce NaN."""
-    ks = tcbf.mx_scale_pitch(K)
-    out = np.full(codes.shape[:-1] + (ks,), 255, np.uint8)
-    out[..., :codes.shape[-1]] = codes
-    return out
+    """Per-block codes [..., rows, Kp/32] -> the library's grouped layout,
+    the padding filled with 255 (the E8M0 NaN code): a kernel that read any
+    padding code would produce NaN."""
+    return tcbf.mx_scales_from_rows(codes, K, pad=255)
+
+
+def test_grouped_scale_layout_of_the_quantiser():
+    """Block j of row r sits at [j // 16][r][j % 16] of the grouped layout."""
+    batch, rows, K = 1, 3, 1100                     # 35 blocks: three groups, the last one partial
+    src = np.zeros((batch, 2, rows, K), np.float32)
+    for r in range(rows):
+        for j in range(35):
+            src[0, 0, r, 32 * j] = 2.0 ** ((r * 7 + j) % 21 - 10)   # block amax sets the exponent
+    codes, scales = gpu_quantize(src, True, tcbf.PLANAR, 32)
+    s = scales.cpu().numpy()
+    assert s.shape == (1, 3, rows, 16)
+    _, _, sc = oracle.quantize_e4m3_blocks(src[0, 0], src[0, 1])
+    for r in range(rows):
+        for j in range(35):
+            assert s[0, j // 16, r, j % 16] == sc[r, j], (r, j)
 
 
 def gpu_quantize(src_np, k_major, layout, block):
@@ -164,7 +177,7 @@ def test_quantiser_bit_exact(kind, layout, k_major, block):
     ecodes, escales = quant_expected(src, k_major, layout, block)
     assert np.array_equal(codes.cpu().numpy(), ecodes)
     if block:
-        assert scales.shape[-1] == tcbf.mx_scale_pitch(K) and scales.shape[-1] % 16 == 0
+        assert tuple(scales.shape) == (batch, tcbf.mx_scale_pitch(K) // 16, rows, 16)
     s = host_scales(scales, block, codes.shape[-1])
     if block == 0:
         assert np.array_equal(s.view(np.uint32), escales.astype(np.float32).view(np.uint32))
@@ -240,8 +253,11 @@ def f8_case(seed, batch, M, N, K, block, shared=False):
     Xd = dequant(Xq.cpu().numpy(), host_scales(Xs, block, kp), block, K)
     if block:
         # poison the padding the quantiser leaves unwritten: it must never be read
-        Ws[..., kp // 32:] = 255
-        Xs[..., kp // 32:] = 255
+        nkb = kp // 32
+        for S in (Ws, Xs):
+            if nkb % 16:
+                S[:, nkb // 16, :, nkb % 16:] = 255
+            S[:, (nkb + 15) // 16:] = 255
     return (Wq, Ws, Xq, Xs), (W, X), (Wd, Xd)
 
 
@@ -383,7 +399,7 @@ def test_c4_full_size_sampled(c4_inputs, dtype):
     ms = np.unique(np.concatenate([[0, M - 1], g.choice(M, 48, replace=False)]))
     Wq_s = Wq[:, :, torch.from_numpy(ms).cuda()].cpu().numpy()
     kp = tcbf.f8_kp(K)
-    Ws_s = host_scales(Ws[:, torch.from_numpy(ms).cuda()], block, kp)
+    Ws_s = host_scales(Ws, block, kp)[:, ms]
     Xq_h, Xs_h = Xq.cpu().numpy(), host_scales(Xs, block, kp)
     # quantiser parity on the sampled rows and on all of X
     sub = np.ascontiguousarray(W[:, :, ms])
