@@ -18,6 +18,11 @@ typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 constexpr int BM = 128, BN = 128, NT = 256;  // complex outputs per workgroup, threads
 constexpr uint32_t OOB = 0x80000000u;         // buffer offset past every range: reads 0, writes dropped
 constexpr int RSRC_FLAGS = 0x00020000;        // raw buffer, 32-bit data format (gfx9 family)
+// Cache policy of the output stores: non-temporal.  The output is written
+// once and never read back by the kernel; marking it streaming keeps it from
+// displacing the operand tiles other workgroups re-read from L2 (measured on
+// the radio-astronomy fp16 shape: 1.7% faster, results identical).
+constexpr int kStoreStreaming = 2;
 
 // s_waitcnt immediates (gfx9 encoding: vmcnt bits [3:0] and [15:14], expcnt
 // [6:4], lgkmcnt [11:8]); fields not named are left at their maxima.
@@ -119,7 +124,7 @@ __device__ __forceinline__ void store_tile_staged(const Acc &acc, RowPtr row_ptr
                 const f32x4 v = *reinterpret_cast<const f32x4 *>(row_ptr(row) + ((lane ^ (row & 31)) * 16));
                 const int m = m0 + 32 * WM * round + row, n = n0 + 2 * lane;
                 const uint32_t off = (m < M && n < N) ? (uint32_t)((m * N + n) * 8) : OOB;
-                __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), rc, off, 0, 0);
+                __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), rc, off, 0, kStoreStreaming);
             }
         } else {
             // 64*WM rows of 512 B; one instruction covers two rows; wave w
@@ -134,7 +139,7 @@ __device__ __forceinline__ void store_tile_staged(const Acc &acc, RowPtr row_ptr
                 // compiler against its data registers being overwritten by
                 // the very next instruction, which corrupts the stored data
                 const uint32_t off = (m < M && n < N) ? (uint32_t)((round * M * N + m * N + n) * 4) : OOB;
-                __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), rc, off, 0, 0);
+                __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), rc, off, 0, kStoreStreaming);
             }
         }
     }
