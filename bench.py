@@ -145,6 +145,22 @@ def peak_probes():
     return out
 
 
+def launch_spread(fn, launches):
+    """Per-launch durations (HIP events around each launch on the current
+    stream): p10 / p50 / p90 in ms."""
+    import torch
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(launches)]
+    for a, b in ev:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    ms = np.array([a.elapsed_time(b) for a, b in ev])
+    return {"launches": launches, "p10_ms": round(float(np.percentile(ms, 10)), 4),
+            "p50_ms": round(float(np.percentile(ms, 50)), 4), "p90_ms": round(float(np.percentile(ms, 90)), 4)}
+
+
 def cpu_baseline(W, X, budget_s=12.0):
     """The oracle as it stands, timed on host cores on a bounded sample of the
     same workload: consecutive beam rows of the first channels."""
@@ -188,9 +204,10 @@ def bench_c2(steps, warmup):
     C = plan.empty_output()
     ms = time_launches(lambda: plan.execute(A, B, C), steps, warmup)
     tops = info["useful_ops"] / (ms * 1e-3) / 1e12
+    spread = launch_spread(lambda: plan.execute(A, B, C), max(steps, 20))
     del A, B, C
     torch.cuda.empty_cache()
-    return W, X, info, ms, tops
+    return W, X, info, ms, tops, spread
 
 
 def bench_secondary(steps, serving=True):
@@ -420,7 +437,7 @@ def main():
         sweep(args.steps)
         return
 
-    W, X, info, ms, tops = bench_c2(args.steps, args.warmup)
+    W, X, info, ms, tops, spread = bench_c2(args.steps, args.warmup)
     log("c2: %.4f ms/launch, %.1f TeraOps/s" % (ms, tops))
     ach_flops = tops  # useful ops are the MFMA flops (8 per complex MAC)
     traffic = recorded_traffic(info["kernel_name"])
@@ -446,6 +463,7 @@ def main():
                    "layout": "planar", "tile": [info["tile_m"], info["tile_n"], info["tile_k"]],
                    "kernel": info["kernel_name"], "workgroups": info["workgroups"]},
         "pct_of_fp16_peak": round(100.0 * tops / PEAK_F16_TFLOPS, 2),
+        "launch_spread": spread,
         "roofline": roofline,
         "peak_probe": probes,
         "cpu_baseline": cpu,

@@ -27,6 +27,8 @@ template <> struct Bits<uint16_t> { static __device__ uint32_t pos(uint16_t v) {
 template <> struct Bits<uint32_t> { static __device__ uint32_t pos(uint32_t v) { return (v >> 31) ^ 1u; } };
 
 constexpr int NT = 256;
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
 // K-major.  Thread -> (c, row, word); planar sources give plane stride rows*K,
 // interleaved sources hold (re, im) pairs.
@@ -104,50 +106,56 @@ __global__ __launch_bounds__(NT) void pack_nmajor_kernel(const T *__restrict__ s
 }
 
 // N-major, vectorised: each thread owns R consecutive rows (R * sizeof(T) =
-// 8 bytes per plane, so interleaved sources give one 16-byte load and planar
-// sources two 8-byte loads per receiver), 128 receivers, both planes; a wave
-// load covers 64 * 8 consecutive row bytes per plane.  Needs rows % R == 0.
-template <typename T, int IL> struct VecLoad;
-template <typename T> struct VecLoad<T, 1> {
-    static constexpr int R = 8 / sizeof(T);
-    // re and im of rows r..r+R-1 at receiver row `p` (interleaved pairs)
-    static __device__ __forceinline__ void load(const T *p, int64_t, T (&re)[R], T (&im)[R]) {
-        const uint4 v = *reinterpret_cast<const uint4 *>(p);
-        const T *e = reinterpret_cast<const T *>(&v);
-#pragma unroll
-        for (int j = 0; j < R; ++j) {
-            re[j] = e[2 * j];
-            im[j] = e[2 * j + 1];
-        }
+// 8 bytes per plane), 128 receivers, both planes.  Per receiver it loads the
+// R rows' 16 bytes (interleaved: one 16-byte load of (re, im) pairs; planar:
+// 8 bytes of each plane); a wave load covers 64 * 8 consecutive row bytes per
+// plane.  Needs rows % R == 0.
+//
+// Receivers go in rounds of 8 with all 8 loads issued before any is used, so
+// every thread keeps 8 loads in flight.  The sign bits of a round are
+// gathered without per-element work: shifting receiver u's dword right by
+// (element width - 1 - u) puts each element's sign bit at bit u of that
+// element's field, so OR-ing the 8 masked dwords collects, per element, its 8
+// receivers' signs in the low byte of its field; one complement turns sign
+// bits into the +1 bits, and each byte lands in its row's word at the
+// round's bit offset.
+template <int IL> struct RawRows;
+template <> struct RawRows<1> {
+    static __device__ __forceinline__ u32x4 load(const void *p, int64_t) {
+        return *reinterpret_cast<const u32x4 *>(p);
     }
 };
-template <typename T> struct VecLoad<T, 0> {
-    static constexpr int R = 8 / sizeof(T);
-    static __device__ __forceinline__ void load(const T *p, int64_t plane, T (&re)[R], T (&im)[R]) {
-        const uint2 a = *reinterpret_cast<const uint2 *>(p);
-        const uint2 b = *reinterpret_cast<const uint2 *>(p + plane);
-        const T *ea = reinterpret_cast<const T *>(&a);
-        const T *eb = reinterpret_cast<const T *>(&b);
-#pragma unroll
-        for (int j = 0; j < R; ++j) {
-            re[j] = ea[j];
-            im[j] = eb[j];
-        }
+template <> struct RawRows<0> {
+    static __device__ __forceinline__ u32x4 load(const void *p, int64_t plane_bytes) {
+        const u32x2 a = *reinterpret_cast<const u32x2 *>(p);
+        const u32x2 b = *reinterpret_cast<const u32x2 *>((const char *)p + plane_bytes);
+        return (u32x4){a[0], a[1], b[0], b[1]};
     }
 };
 
 template <typename T, int IL>
 __global__ __launch_bounds__(NT) void pack_nmajor_vec_kernel(const T *__restrict__ src, uint32_t *__restrict__ dst,
                                                              int64_t batch, int64_t rows, int64_t K, int64_t kw) {
-    typedef VecLoad<T, IL> L;
-    constexpr int R = L::R;
-    const int64_t gid = (int64_t)blockIdx.x * NT + threadIdx.x;
+    constexpr int R = 8 / (int)sizeof(T);      // rows per thread
+    constexpr int E = 2 * R;                   // elements in the 16 bytes of one receiver
+    constexpr int W = 8 * (int)sizeof(T);      // element width in bits
+    constexpr int EPD = 4 / (int)sizeof(T);    // elements per dword
+    constexpr uint32_t LOW = sizeof(T) == 1 ? 0x01010101u : sizeof(T) == 2 ? 0x00010001u : 1u;
+    // Workgroup -> (c, 4 word groups, 64 row groups): wave w takes word group
+    // 4 gb + w of the workgroup's rows, so the four waves write the four
+    // 16-byte pieces of each row's 64 output bytes together (whole lines
+    // instead of scattered quarter lines); consecutive workgroups take the
+    // next rows, so the reads in flight spread along each receiver's row of
+    // samples.
     const int64_t ngroups = (kw + 3) / 4;
     const int64_t rgroups = rows / R;
-    if (gid >= batch * ngroups * rgroups) return;
-    const int64_t r0 = (gid % rgroups) * R;
-    const int64_t g = (gid / rgroups) % ngroups;
-    const int64_t c = gid / (rgroups * ngroups);
+    const int64_t gblocks = (ngroups + 3) / 4, rblocks = (rgroups + 63) / 64;
+    const int64_t bid = blockIdx.x;
+    const int64_t rb = bid % rblocks, gb = (bid / rblocks) % gblocks, c = bid / (gblocks * rblocks);
+    const int64_t g = gb * 4 + (threadIdx.x >> 6);
+    const int64_t rg = rb * 64 + (threadIdx.x & 63);
+    if (c >= batch || g >= ngroups || rg >= rgroups) return;
+    const int64_t r0 = rg * R;
     uint32_t wr[R][4], wi[R][4];
 #pragma unroll
     for (int j = 0; j < R; ++j)
@@ -157,18 +165,43 @@ __global__ __launch_bounds__(NT) void pack_nmajor_vec_kernel(const T *__restrict
     const int n = (int)((K - k0) < 128 ? (K - k0) : 128);
     // element (k, row) of plane 0: interleaved ((c K + k) rows + row) * 2, planar (c 2 K + k) rows + row
     const T *base = IL ? src + ((c * K + k0) * rows + r0) * 2 : src + (c * 2 * K + k0) * rows + r0;
-    const int64_t kstep = IL ? rows * 2 : rows, plane = K * rows;
+    const int64_t kstep = IL ? rows * 2 : rows, plane_bytes = K * rows * (int64_t)sizeof(T);
+    // element e of a receiver's 16 bytes -> plane and row
+    auto place = [](int e, int &pl, int &row) {
+        pl = IL ? (e & 1) : (e >= R);
+        row = IL ? (e >> 1) : (e % R);
+    };
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         if (32 * q >= n) break;
         const int m = n - 32 * q < 32 ? n - 32 * q : 32;
-        for (int b = 0; b < m; ++b) {
-            T re[R], im[R];
-            L::load(base + (int64_t)(32 * q + b) * kstep, plane, re, im);
+        int b = 0;
+        for (; b + 8 <= m; b += 8) {
+            u32x4 d[8];
 #pragma unroll
-            for (int j = 0; j < R; ++j) {
-                wr[j][q] |= Bits<T>::pos(re[j]) << b;
-                wi[j][q] |= Bits<T>::pos(im[j]) << b;
+            for (int u = 0; u < 8; ++u) d[u] = RawRows<IL>::load(base + (int64_t)(32 * q + b + u) * kstep, plane_bytes);
+            u32x4 t = (u32x4){0u, 0u, 0u, 0u};
+#pragma unroll
+            for (int u = 0; u < 8; ++u) t |= (d[u] >> (uint32_t)(W - 1 - u)) & (LOW << u);
+            t = ~t;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                int pl, row;
+                place(e, pl, row);
+                const uint32_t byte = (t[e / EPD] >> (W * (e % EPD))) & 0xffu;
+                if (pl) wi[row][q] |= byte << b;
+                else wr[row][q] |= byte << b;
+            }
+        }
+        for (; b < m; ++b) {
+            const u32x4 t = ~RawRows<IL>::load(base + (int64_t)(32 * q + b) * kstep, plane_bytes);
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                int pl, row;
+                place(e, pl, row);
+                const uint32_t bit = (t[e / EPD] >> (W * (e % EPD) + W - 1)) & 1u;
+                if (pl) wi[row][q] |= bit << b;
+                else wr[row][q] |= bit << b;
             }
         }
     }
@@ -189,24 +222,27 @@ __global__ __launch_bounds__(NT) void pack_nmajor_vec_kernel(const T *__restrict
     }
 }
 
+// Workgroups of the kernel that takes (element size, rows, K, orientation).
+int64_t pack_workgroups(int64_t elem_bytes, int64_t batch, int64_t rows, int64_t K, int kmajor) {
+    const int64_t kw = (K + 31) / 32, ngroups = (kw + 3) / 4, R = 8 / elem_bytes;
+    if (kmajor) return (batch * rows * kw + NT - 1) / NT;
+    if (rows % R == 0) return batch * ((ngroups + 3) / 4) * ((rows / R + 63) / 64);
+    return (batch * ngroups * rows + NT - 1) / NT;
+}
+
 template <typename T>
 hipError_t launch_typed(const void *src, int il, int64_t batch, int64_t rows, int64_t K, int kmajor,
                         uint32_t *dst, hipStream_t stream) {
     const int64_t kw = (K + 31) / 32;
     const T *s = (const T *)src;
+    const dim3 grid((uint32_t)pack_workgroups(sizeof(T), batch, rows, K, kmajor));
     if (kmajor) {
-        const int64_t total = batch * rows * kw;
-        dim3 grid((uint32_t)((total + NT - 1) / NT));
         if (il) hipLaunchKernelGGL((pack_kmajor_kernel<T, 1>), grid, dim3(NT), 0, stream, s, dst, batch, rows, K, kw);
         else    hipLaunchKernelGGL((pack_kmajor_kernel<T, 0>), grid, dim3(NT), 0, stream, s, dst, batch, rows, K, kw);
     } else if (rows % (8 / (int64_t)sizeof(T)) == 0) {
-        const int64_t total = batch * ((kw + 3) / 4) * (rows / (8 / (int64_t)sizeof(T)));
-        dim3 grid((uint32_t)((total + NT - 1) / NT));
         if (il) hipLaunchKernelGGL((pack_nmajor_vec_kernel<T, 1>), grid, dim3(NT), 0, stream, s, dst, batch, rows, K, kw);
         else    hipLaunchKernelGGL((pack_nmajor_vec_kernel<T, 0>), grid, dim3(NT), 0, stream, s, dst, batch, rows, K, kw);
     } else {
-        const int64_t total = batch * ((kw + 3) / 4) * rows;
-        dim3 grid((uint32_t)((total + NT - 1) / NT));
         const int vec = (kw % 4) == 0;
         if (il) hipLaunchKernelGGL((pack_nmajor_kernel<T, 1>), grid, dim3(NT), 0, stream, s, dst, batch, rows, K, kw, vec);
         else    hipLaunchKernelGGL((pack_nmajor_kernel<T, 0>), grid, dim3(NT), 0, stream, s, dst, batch, rows, K, kw, vec);
@@ -215,6 +251,11 @@ hipError_t launch_typed(const void *src, int il, int64_t batch, int64_t rows, in
 }
 
 }  // namespace
+
+int64_t pack1bit_workgroups(int src_type, int64_t batch, int64_t rows, int64_t K, int src_k_major) {
+    const int64_t eb = src_type == TCBF_SRC_I8 ? 1 : src_type == TCBF_SRC_F16 ? 2 : 4;
+    return pack_workgroups(eb, batch, rows, K, src_k_major);
+}
 
 hipError_t pack1bit_launch(const void *src, int src_type, int src_layout, int64_t batch, int64_t rows,
                            int64_t K, int src_k_major, uint32_t *dst, hipStream_t stream) {

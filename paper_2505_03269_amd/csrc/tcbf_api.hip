@@ -219,9 +219,10 @@ tcbf_status tcbf_pack1bit(const void *src, int32_t src_type, int32_t src_layout,
     if (!is_layout(src_layout)) return TCBF_ERROR_INVALID_VALUE;
     if (batch < 1 || rows < 1 || K < 1) return TCBF_ERROR_INVALID_VALUE;
     if (!aligned16(src) || !aligned16(dst)) return TCBF_ERROR_INVALID_VALUE;
-    const int64_t kw = (K + 31) / 32;
-    const int64_t threads = src_k_major ? batch * rows * kw : batch * ((kw + 3) / 4) * rows;
-    if (threads / 256 + 1 >= kMaxIndex) return TCBF_ERROR_NOT_SUPPORTED;
+    // sizes whose products could overflow are refused before the workgroup count
+    if ((double)batch * (double)rows * (double)K >= 0x1p62) return TCBF_ERROR_NOT_SUPPORTED;
+    if (tcbf::pack1bit_workgroups(src_type, batch, rows, K, src_k_major != 0) >= kMaxIndex)
+        return TCBF_ERROR_NOT_SUPPORTED;
     hipError_t e = tcbf::pack1bit_launch(src, src_type, src_layout, batch, rows, K, src_k_major != 0, dst,
                                          (hipStream_t)stream);
     return e == hipSuccess ? TCBF_SUCCESS : TCBF_ERROR_DEVICE;

@@ -77,6 +77,8 @@ hipError_t int1_launch(const Problem &p, const Int1Config &cfg, const uint32_t *
                        const uint32_t *B, int32_t *C, hipStream_t stream);
 
 // Sign packing.
+// Workgroups the packing launch uses (what the argument checks bound).
+int64_t pack1bit_workgroups(int src_type, int64_t batch, int64_t rows, int64_t K, int src_k_major);
 hipError_t pack1bit_launch(const void *src, int src_type, int src_layout, int64_t batch,
                            int64_t rows, int64_t K, int src_k_major, uint32_t *dst,
                            hipStream_t stream);

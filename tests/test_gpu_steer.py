@@ -136,6 +136,45 @@ def test_plane_wave_beamformed_end_to_end():
     assert off.max() < 0.5 * K * abs(A)     # the grid keeps other beams below ~0.18 of the main lobe
 
 
+def test_e4m3_weights_from_geometry():
+    """Steering weights for the FP8 mode: generated in FP64 on the GPU, rounded
+    to fp32, quantised to e4m3 on the GPU (per-row scales) -- codes and scales
+    bit-exact against the oracle's quantiser on the same fp32 weights -- then
+    a plane wave from each beam's direction beamformed in FP8 adds up to
+    K |A| in that beam (within the e4m3 rounding of both operands)."""
+    g = np.random.default_rng(16)
+    K, M, N, f = 192, 64, 64, 150e6
+    pos = np.column_stack([g.uniform(-400, 400, (K, 2)), np.zeros(K)])
+    gl = (np.arange(8) - 3.5) * 0.01
+    L, Mm = np.meshgrid(gl, gl)
+    dirs = np.column_stack([L.ravel(), Mm.ravel(), np.zeros(M)])
+    W32 = tcbf.steering_weights(to_dev(pos), to_dev(dirs), to_dev(np.array([f])), C0, dtype=torch.float32)
+    Wq, Ws = tcbf.quantize_e4m3(W32, k_major=True, block=0)
+    torch.cuda.synchronize()
+    w = W32.cpu().numpy()[0]
+    qr, qi, sc = oracle.quantize_e4m3_rows(w[0], w[1])
+    kp = tcbf.f8_kp(K)
+    got = Wq.cpu().numpy()[0]
+    assert np.array_equal(got[0, :, :K], qr) and np.array_equal(got[1, :, :K], qi)
+    assert not got[:, :, K:].any()
+    assert np.array_equal(Ws.cpu().numpy()[0].view(np.uint32), sc.view(np.uint32))
+    A = 40.0 - 25.0j
+    tau = pos @ dirs[:N].T / C0
+    Xc = A * np.exp(-2j * np.pi * f * tau)                        # [K, N]
+    X = np.stack([Xc.real, Xc.imag])[None].astype(np.float32)
+    Xq, Xs = tcbf.quantize_e4m3(to_dev(X), k_major=False, block=0)
+    plan = tcbf.Plan(1, M, N, kp, tcbf.F8_E4M3)
+    C = plan.empty_output()
+    plan.execute(Wq, Xq, C, Ws, Xs)
+    torch.cuda.synchronize()
+    B = C.cpu().numpy()[0]
+    Bc = B[0] + 1j * B[1]
+    gain = np.abs(np.diag(Bc[:N, :N]))
+    assert np.allclose(gain, K * abs(A), rtol=3e-2)
+    off = np.abs(Bc[:N, :N][~np.eye(N, dtype=bool)])
+    assert off.max() < 0.5 * K * abs(A)
+
+
 def test_rejects_bad_arguments():
     pos = torch.zeros((4, 3), dtype=torch.float64, device="cuda:0")
     dirs = torch.zeros((2, 3), dtype=torch.float64, device="cuda:0")
