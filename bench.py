@@ -142,7 +142,32 @@ def peak_probes():
     for name, kind in kinds:
         out[name] = {"uniform": measure_peak(kind), "random": measure_peak(kind, random=True)}
         log("peak probe %s: %s" % (name, out[name]))
+    out["hbm_copy"] = measure_copy()
+    log("device copy: %s" % out["hbm_copy"])
     return out
+
+
+def measure_copy(nbytes=1 << 31):
+    """The memory system's practical streaming rate: a plain device-to-device
+    copy of 2 GiB (torch's copy kernel), bytes read plus written per second,
+    median of five."""
+    import torch
+    a = torch.ones(nbytes, dtype=torch.uint8, device="cuda:0")
+    b = torch.empty_like(a)
+    stream = torch.cuda.current_stream()
+    b.copy_(a)
+    ms = []
+    for _ in range(5):
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        b.copy_(a)
+        t1.record(stream)
+        torch.cuda.synchronize()
+        ms.append(t0.elapsed_time(t1))
+    del a, b
+    torch.cuda.empty_cache()
+    m = float(np.median(ms))
+    return {"gbs": round(2 * nbytes / (m * 1e-3) / 1e9, 1), "ms": round(m, 4), "bytes_each_way": nbytes}
 
 
 def launch_spread(fn, launches):
@@ -210,7 +235,7 @@ def bench_c2(steps, warmup):
     return W, X, info, ms, tops, spread
 
 
-def bench_secondary(steps, serving=True):
+def bench_secondary(steps, serving=True, copy_gbs=None):
     """1-bit config (both variants), ultrasound-shaped fp16, sign packing."""
     import torch
     import paper_2505_03269_amd as tcbf
@@ -259,10 +284,13 @@ def bench_secondary(steps, serving=True):
     ms = time_launches(lambda: tcbf.pack1bit(src, k_major=False, layout=tcbf.INTERLEAVED, out=dst), st, 1)
     nbytes = src.numel() + dst.numel() * 4
     gbs = nbytes / (ms * 1e-3) / 1e9
-    out.append({"workload": "pack1bit int8 interleaved [16][8192][8192][2] -> words", "kernel": "pack_nmajor_kernel",
-                "value": round(gbs, 1), "unit": "GB/s", "ms_per_launch": round(ms, 4),
-                "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                             "frac": round(gbs / PEAK_HBM_GBS, 4)}})
+    roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(gbs / PEAK_HBM_GBS, 4)}
+    if copy_gbs:
+        roof.update({"measured_peak": copy_gbs, "frac_of_measured_peak": round(gbs / copy_gbs, 4)})
+    out.append({"workload": "pack1bit int8 interleaved [16][8192][8192][2] -> words",
+                "kernel": "pack_nmajor_vec_kernel", "value": round(gbs, 1), "unit": "GB/s",
+                "ms_per_launch": round(ms, 4), "roofline": roof})
     del src, dst, A, B
     torch.cuda.empty_cache()
     # ultrasound shape, fp16: 1 x 32768 x 8192 x 256
@@ -452,7 +480,8 @@ def main():
         roofline["measured_peak"] = probes["f16"]["uniform"]["tops"]
         roofline["frac_of_measured_peak"] = round(ach_flops / probes["f16"]["uniform"]["tops"], 4)
         roofline["measured_peak_random_operands"] = probes["f16"]["random"]["tops"]
-    secondary = [] if args.no_secondary else bench_secondary(args.steps, serving=not args.no_serving)
+    secondary = [] if args.no_secondary else bench_secondary(
+        args.steps, serving=not args.no_serving, copy_gbs=probes["hbm_copy"]["gbs"])
     cpu = None if args.no_cpu_baseline else cpu_baseline(W, X)
     line = {
         "metric": METRIC, "value": round(tops, 2), "unit": "TeraOps/s", "n_gpus": 1,
