@@ -206,20 +206,25 @@ tcbf_status tcbf_quantize_e4m3(const void *src, int32_t src_type, int32_t src_la
                                int32_t block, uint8_t *dst, void *scales, void *stream);
 
 /*
- * tcbf_steering_weights -- the weights W of Eq. 3 from array geometry, in FP64
- * on the device.  Sec. II's far-field delay (Eq. 2), for sensor k at
+ * tcbf_steering_weights -- the weights W of Eq. 3 from array geometry, with
+ * the phase in FP64 on the device.  Sec. II's far-field delay (Eq. 2), for sensor k at
  * positions[k] = (x, y, z) metres and beam m along directions[m] = (l, m, n)
  * (direction cosines), is tau = (x l + y m + z n) / wave_speed; the weight
  * that re-aligns its phase at frequencies[c] is
  *     W[c][m][k] = exp(+i 2 pi frac(f tau)),   frac(v) = v - floor(v),
  * with s = x l + y m + z n summed left to right, cycles = (f s) / wave_speed,
- * every FP64 operation rounded on its own (nothing fused), cos/sin of
- * 2 pi frac(cycles) from the device math library.
+ * every FP64 operation rounded on its own (nothing fused).  cos/sin of
+ * 2 pi frac(cycles) come from the device math library: in FP64 for fp32
+ * output (each value rounded once, to nearest); for fp16 output, after an
+ * exact FP64 split of frac(cycles) into quarter turns and a remainder of at
+ * most 1/8 turn, from the fp32 sincospi of the remainder (relative error
+ * about 2^-21 before the rounding to fp16 nearest-even, so at most one fp16
+ * ulp from the correctly rounded value and equal to it except near rounding
+ * boundaries).
  *   positions (device) [K][3] double, directions (device) [M][3] double,
  *   frequencies (device) [batch] double, all 8-byte aligned;
  *   W (device, 16-byte aligned): planar [batch][2][M][K], element type
- *   out_type = TCBF_SRC_F16 (each value rounded once, to nearest even) or
- *   TCBF_SRC_F32 (nearest).  This is the TCBF_F16 operand layout of W; FP8
+ *   out_type = TCBF_SRC_F16 or TCBF_SRC_F32.  This is the TCBF_F16 operand layout of W; FP8
  *   weights follow with tcbf_quantize_e4m3.
  * Returns INVALID_VALUE for NULL or misaligned pointers, non-positive sizes,
  * a wave speed that is not positive and finite, or another out_type.

@@ -253,6 +253,7 @@ tcbf_status tcbf_steering_weights(const double *positions, const double *directi
     if (!(wave_speed > 0.0) || wave_speed > 1e300) return TCBF_ERROR_INVALID_VALUE;
     if (!aligned8(positions) || !aligned8(directions) || !aligned8(frequencies) || !aligned16(W))
         return TCBF_ERROR_INVALID_VALUE;
+    if ((double)batch * (double)M * (double)K >= 0x1p62) return TCBF_ERROR_NOT_SUPPORTED;
     if (tcbf::steering_blocks(batch, M, K) >= kMaxIndex) return TCBF_ERROR_NOT_SUPPORTED;
     hipError_t e = tcbf::steering_launch(positions, directions, frequencies, wave_speed, batch, M, K, out_type, W,
                                          (hipStream_t)stream);
