@@ -186,3 +186,31 @@ def test_c3_full_size():
     gi = C[idx[0], 1, idx[1], idx[2]].cpu().numpy().astype(np.int64)
     er, ei = oracle.cgemm_1bit_popc_entries(Wp[:, 0], Wp[:, 1], Xp[:, 0], Xp[:, 1], K, cs, ms, ns)
     assert np.array_equal(gr, er) and np.array_equal(gi, ei)
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_longest_supported_k(variant):
+    """K = 2^26 - 3 receivers (the library's limit is 2^26; a ragged last
+    word): 32 x 32 outputs from random words, bit-exact against the oracle's
+    popcount form on every output."""
+    M = N = 32
+    K = (1 << 26) - 3
+    kw = (K + 31) // 32
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(41)
+    log("1-bit K=%d variant %d" % (K, variant))
+    A = torch.randint(-2**31, 2**31 - 1, (1, 2, M, kw), dtype=torch.int32, device="cuda:0", generator=g)
+    B = torch.randint(-2**31, 2**31 - 1, (1, 2, N, kw), dtype=torch.int32, device="cuda:0", generator=g)
+    mask = (1 << (K % 32)) - 1
+    A[..., kw - 1] &= mask
+    B[..., kw - 1] &= mask
+    plan = tcbf.Plan(1, M, N, K, tcbf.INT1, variant=variant)
+    C = plan.empty_output()
+    plan.execute(A, B, C)
+    torch.cuda.synchronize()
+    Wp = A.cpu().numpy().view(np.uint32)
+    Xp = B.cpu().numpy().view(np.uint32)
+    rr, ri = oracle_1bit(Wp, Xp, K)
+    Ch = C.cpu().numpy().astype(np.int64)
+    assert np.array_equal(Ch[:, 0], rr) and np.array_equal(Ch[:, 1], ri)
+

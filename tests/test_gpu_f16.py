@@ -247,3 +247,35 @@ def test_plan_picks_fast_kernel_for_aligned_planar():
     assert tcbf.Plan(1, 64, 64, 64, tcbf.F16, a_layout=tcbf.INTERLEAVED).info()["variant"] == 1
     with pytest.raises(tcbf.TcbfError):
         tcbf.Plan(1, 64, 100, 64, tcbf.F16, variant=2)
+
+
+def test_largest_channel_takes_the_generic_kernel():
+    """A channel whose W plane pair is past the fast kernel's 2 GiB byte
+    offsets (M = 32768 beams x K = 24576 receivers: 3.2 GB of fp16) but
+    inside the 2^31-element planes the library supports: the plan falls back
+    to the generic kernel, and small-integer data makes every sampled entry
+    exact (all partial sums are integers below 2^24), so they must equal the
+    oracle bit for bit -- beams past the 32-bit byte-offset range included."""
+    M, N, K = 32768, 64, 24576
+    plan = tcbf.Plan(1, M, N, K, tcbf.F16)
+    assert plan.info()["kernel_name"] == "cgemm_f16_kernel"
+    g = torch.Generator(device="cuda:0")
+    g.manual_seed(31)
+    log("largest channel: generating 3.2 GB of weights")
+    A = torch.randint(-8, 9, plan.shape_a(), dtype=torch.float16, device="cuda:0", generator=g)
+    B = torch.randint(-8, 9, plan.shape_b(), dtype=torch.float16, device="cuda:0", generator=g)
+    C = plan.empty_output()
+    plan.execute(A, B, C)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(32)
+    ms = np.unique(np.concatenate([[0, M - 1, 21845, 21846], rng.integers(0, M, 60)]))
+    ns = rng.integers(0, N, ms.size)
+    ns[-1] = N - 1
+    Wsub = A[:, :, torch.from_numpy(ms).cuda()].cpu().numpy().astype(np.float64)   # [1, 2, S, K]
+    X = B.cpu().numpy().astype(np.float64)
+    got = C.cpu().numpy()[0]
+    Wc = Wsub[:, 0] + 1j * Wsub[:, 1]
+    Xc = X[:, 0] + 1j * X[:, 1]
+    ref = oracle.cgemm_entries(Wc, Xc, np.zeros(ms.size, np.int64), np.arange(ms.size), ns)
+    assert np.array_equal(got[0, ms, ns], ref.real) and np.array_equal(got[1, ms, ns], ref.imag)
+
