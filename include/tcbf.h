@@ -235,9 +235,10 @@ tcbf_status tcbf_steering_weights(const double *positions, const double *directi
                                   int64_t M, int64_t K, int32_t out_type, void *W, void *stream);
 
 /*
- * Grouped persistent launch (TCBF_F16): up to TCBF_GROUP_MAX independent
- * problems of different shapes -- channels, frames or jobs, each B = W . X in
- * the TCBF_F16 layouts with planar W and X -- run in ONE launch.  The
+ * Grouped persistent launch (TCBF_F16, TCBF_F8_E4M3, TCBF_MXF8_E4M3): up to
+ * TCBF_GROUP_MAX independent problems of different shapes -- channels, frames
+ * or jobs, each B = W . X in the layouts of `dtype` (planar W and X for fp16;
+ * the e4m3 codes and scales of that FP8 mode) -- run in ONE launch.  The
  * problems' output tiles form one work list, longest receiver count first
  * (the paper's Sec. IV-C size sweep shows per-shape padding and tail effects;
  * one shared list keeps every CU busy across shape boundaries); persistent
@@ -245,9 +246,11 @@ tcbf_status tcbf_steering_weights(const double *positions, const double *directi
  * empty.  The problem table travels in the launch's kernel arguments, so the
  * call can be captured in a HIP graph and replayed.
  *   problems: host array of `count` descriptors (1 <= count <= TCBF_GROUP_MAX);
- *     each needs batch, M, N, K >= 1, K and N multiples of 8, 16-byte
- *     aligned device pointers, per-channel W and X below 2 GiB and its
- *     output below 2 GiB.
+ *     each needs batch, M, N, K >= 1, 16-byte aligned device pointers and
+ *     the size limits of a plan of its dtype; fp16: K and N multiples of 8,
+ *     per-channel W and X below 2 GiB, a_scale = b_scale = NULL; FP8: N a
+ *     multiple of 4, a_scale and b_scale as for tcbf_execute.  Every
+ *     problem's output equals its own plan's (default variant) bit for bit.
  *   workspace: device memory of TCBF_GROUP_WORKSPACE_BYTES, 16-byte aligned,
  *     used for the tile counter; calls that overlap in time (on different
  *     streams) need different workspaces.
@@ -258,12 +261,14 @@ tcbf_status tcbf_steering_weights(const double *positions, const double *directi
 #define TCBF_GROUP_WORKSPACE_BYTES 256
 
 typedef struct tcbf_group_problem {
-    const void *A;     /* W, planar fp16 [batch|1][2][M][K]                */
-    const void *B;     /* X, planar fp16 [batch][2][K][N]                  */
-    void *C;           /* output fp32, layout c_layout                     */
+    const void *A;       /* W in the dtype's layout (shared: one batch entry) */
+    const void *B;       /* X in the dtype's layout                           */
+    void *C;             /* output fp32, layout c_layout                      */
     int64_t batch, M, N, K;
-    int32_t a_shared;  /* nonzero: one W for all batch entries             */
-    int32_t reserved;  /* must be 0                                        */
+    int32_t a_shared;    /* nonzero: one W for all batch entries              */
+    int32_t reserved;    /* must be 0                                         */
+    const void *a_scale; /* FP8 modes: W scales; fp16: NULL                   */
+    const void *b_scale; /* FP8 modes: X scales; fp16: NULL                   */
 } tcbf_group_problem;
 
 tcbf_status tcbf_group_execute(int32_t device, int32_t dtype, int32_t c_layout,

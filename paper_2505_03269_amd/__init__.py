@@ -57,7 +57,8 @@ class PlanDesc(ctypes.Structure):
 class GroupProblem(ctypes.Structure):
     _fields_ = [("A", ctypes.c_void_p), ("B", ctypes.c_void_p), ("C", ctypes.c_void_p),
                 ("batch", ctypes.c_int64), ("M", ctypes.c_int64), ("N", ctypes.c_int64), ("K", ctypes.c_int64),
-                ("a_shared", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("a_shared", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("a_scale", ctypes.c_void_p), ("b_scale", ctypes.c_void_p)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -140,6 +141,12 @@ def mx_scales_from_rows(codes, K, pad=0):
     return np.ascontiguousarray(full.reshape(lead + (rows, ks // 16, 16)).swapaxes(-3, -2))
 
 
+def _scale_shape(dtype, nb, rows, K):
+    """Scales of `rows` rows in an FP8 mode: fp32 [nb, rows] per row, or E8M0
+    codes in groups of 16 blocks [nb, Ks/16, rows, 16] per block."""
+    return (nb, rows) if dtype == F8_E4M3 else (nb, mx_scale_pitch(K) // 16, rows, 16)
+
+
 def _is_f8(dtype):
     return dtype in (F8_E4M3, MXF8_E4M3)
 
@@ -220,12 +227,10 @@ class Plan:
     def shape_a_scale(self):
         """FP8 modes: W scales ([nb, M] fp32 per row; per block uint8 codes in
         groups of 16, [nb, Ks/16, M, 16])."""
-        nb = 1 if self.a_shared else self.batch
-        return (nb, self.M) if self.dtype == F8_E4M3 else (nb, mx_scale_pitch(self.K) // 16, self.M, 16)
+        return _scale_shape(self.dtype, 1 if self.a_shared else self.batch, self.M, self.K)
 
     def shape_b_scale(self):
-        return ((self.batch, self.N) if self.dtype == F8_E4M3
-                else (self.batch, mx_scale_pitch(self.K) // 16, self.N, 16))
+        return _scale_shape(self.dtype, self.batch, self.N, self.K)
 
     def shape_c(self):
         return (self.batch, 2, self.M, self.N) if self.c_layout == PLANAR else (self.batch, self.M, self.N, 2)
@@ -406,40 +411,62 @@ def peak_probe(kind, blocks, iterations, operand_bits=None, random=False, sink=N
     return ops.value, values, marks
 
 
-def group_execute(problems, c_layout=PLANAR, workspace=None, device=0, stream=None):
-    """One grouped persistent launch over up to GROUP_MAX fp16 problems.
+def group_execute(problems, c_layout=PLANAR, workspace=None, device=0, stream=None, dtype=F16):
+    """One grouped persistent launch over up to GROUP_MAX problems of one dtype.
 
-    problems: list of (W, X, C) or (W, X, C, a_shared) device tensors with
-    W float16 [batch|1, 2, M, K], X float16 [batch, 2, K, N], C float32
-    [batch, 2, M, N] (planar) or [batch, M, N, 2] (interleaved).
+    dtype F16: problems are (W, X, C) or (W, X, C, a_shared) device tensors
+    with W float16 [batch|1, 2, M, K], X float16 [batch, 2, K, N].
+    dtype F8_E4M3 / MXF8_E4M3: (W, X, C, a_scale, b_scale) or
+    (W, X, C, a_scale, b_scale, a_shared) with e4m3 codes W uint8
+    [batch|1, 2, M, Kp], X uint8 [batch, 2, N, Kp] and the scales of that
+    mode (see Plan.shape_a_scale / shape_b_scale).
+    C: float32 [batch, 2, M, N] (planar) or [batch, M, N, 2] (interleaved).
     workspace: uint8 device tensor of GROUP_WORKSPACE_BYTES (allocated here
     if None; pass one to stay allocation-free).
     """
     import torch
     if not 1 <= len(problems) <= GROUP_MAX:
         raise ValueError("1..%d problems per launch" % GROUP_MAX)
+    f8 = _is_f8(dtype)
+    if dtype != F16 and not f8:
+        raise ValueError("grouped launches take F16, F8_E4M3 or MXF8_E4M3")
     arr = (GroupProblem * len(problems))()
     for i, pr in enumerate(problems):
         W, X, C = pr[0], pr[1], pr[2]
-        shared = bool(pr[3]) if len(pr) > 3 else False
-        if W.dtype != torch.float16 or X.dtype != torch.float16 or C.dtype != torch.float32:
-            raise ValueError("problem %d: W, X float16 and C float32 expected" % i)
+        nfix = 5 if f8 else 3
+        shared = bool(pr[nfix]) if len(pr) > nfix else False
+        elem = torch.uint8 if f8 else torch.float16
+        if W.dtype != elem or X.dtype != elem or C.dtype != torch.float32:
+            raise ValueError("problem %d: W, X %s and C float32 expected" % (i, elem))
         if W.dim() != 4 or X.dim() != 4 or W.shape[1] != 2 or X.shape[1] != 2:
-            raise ValueError("problem %d: planar W [b, 2, M, K] and X [b, 2, K, N] expected" % i)
-        batch, K, N = X.shape[0], X.shape[2], X.shape[3]
+            raise ValueError("problem %d: planar W [b, 2, M, K] and X [b, 2, ., .] expected" % i)
+        if f8:
+            batch, N, K = X.shape[0], X.shape[2], X.shape[3]
+            if K % 32:
+                raise ValueError("problem %d: FP8 rows must be Kp = 32 * ceil(K / 32) bytes" % i)
+        else:
+            batch, K, N = X.shape[0], X.shape[2], X.shape[3]
         M = W.shape[2]
         if W.shape[3] != K or W.shape[0] != (1 if shared else batch):
             raise ValueError("problem %d: W does not match X" % i)
         want = (batch, 2, M, N) if c_layout == PLANAR else (batch, M, N, 2)
         if tuple(C.shape) != want:
             raise ValueError("problem %d: C must have shape %s" % (i, want))
+        sa = sb = None
+        if f8:
+            st = torch.float32 if dtype == F8_E4M3 else torch.uint8
+            for t, shape, nm in ((pr[3], _scale_shape(dtype, 1 if shared else batch, M, K), "a_scale"),
+                                 (pr[4], _scale_shape(dtype, batch, N, K), "b_scale")):
+                if t.dtype != st or tuple(t.shape) != tuple(shape):
+                    raise ValueError("problem %d: %s must be %s %s" % (i, nm, st, tuple(shape)))
+            sa, sb = _dev_ptr(pr[3], "a_scale").value, _dev_ptr(pr[4], "b_scale").value
         arr[i] = GroupProblem(_dev_ptr(W, "W").value, _dev_ptr(X, "X").value, _dev_ptr(C, "C").value,
-                              batch, M, N, K, int(shared), 0)
+                              batch, M, N, K, int(shared), 0, sa, sb)
     if workspace is None:
         workspace = torch.empty(GROUP_WORKSPACE_BYTES, dtype=torch.uint8, device="cuda:%d" % device)
     if workspace.numel() * workspace.element_size() < GROUP_WORKSPACE_BYTES:
         raise ValueError("workspace too small")
-    _check(lib().tcbf_group_execute(int(device), F16, int(c_layout), arr, len(problems),
+    _check(lib().tcbf_group_execute(int(device), int(dtype), int(c_layout), arr, len(problems),
                                     _dev_ptr(workspace, "workspace"), _stream_handle(stream)),
            "tcbf_group_execute")
     return [pr[2] for pr in problems]

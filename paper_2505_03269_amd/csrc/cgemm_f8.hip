@@ -34,6 +34,8 @@
 // The instruction sums its products in groups of 8 and, within a group,
 // keeps about 14 bits below the leading product (measured: terms 2^-14 of the
 // leading one and smaller are dropped); group sums accumulate in fp32.
+#include <cstring>
+
 #include "tcbf_tile.h"
 
 namespace tcbf {
@@ -73,27 +75,26 @@ __device__ __forceinline__ f32x16 mma(const i32x8 &x, const i32x8 &w, const f32x
     return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(x, w, c, 0, 0, 0, sx, 0, sw);
 }
 
-template <int NS, int CIL, int MX>
-__global__ __launch_bounds__(NT, 2) void cgemm_f8_kernel(
-    const uint8_t *__restrict__ A, const uint8_t *__restrict__ B, float *__restrict__ C,
-    const void *__restrict__ a_scale, const void *__restrict__ b_scale, int M, int N, int Kp, int a_shared,
-    int tiles_m, int tiles_n, int nblocks) {
-    static_assert(NS >= 2 && NS <= 4 && NS <= SLAB_STAGES + 1, "ring depth");
-    __shared__ __attribute__((aligned(1024))) char lds0[STAGE];
-    __shared__ __attribute__((aligned(1024))) char lds1[STAGE];
-    __shared__ __attribute__((aligned(NS > 2 ? 1024 : 4))) char lds2[NS > 2 ? STAGE : 4];
-    __shared__ __attribute__((aligned(NS > 3 ? 1024 : 4))) char lds3[NS > 3 ? STAGE : 4];
-    // block-scale slabs (MX only): two slots of SLAB_STAGES stages each
-    __shared__ __attribute__((aligned(MX ? 1024 : 4))) char slabs[MX ? 2 * SLAB : 4];
-    char *const bufs[4] = {lds0, lds1, lds2, lds3};
+// LDS of one workgroup: the NS-deep stage ring and (MX only) two block-scale
+// slab slots; separate arrays, so the compiler sees that reads of one stage
+// and direct loads into another cannot alias.
+#define TCBF_F8_LDS(NS, MX)                                                                      \
+    __shared__ __attribute__((aligned(1024))) char lds0[STAGE];                                 \
+    __shared__ __attribute__((aligned(1024))) char lds1[STAGE];                                 \
+    __shared__ __attribute__((aligned((NS) > 2 ? 1024 : 4))) char lds2[(NS) > 2 ? STAGE : 4];   \
+    __shared__ __attribute__((aligned((NS) > 3 ? 1024 : 4))) char lds3[(NS) > 3 ? STAGE : 4];   \
+    __shared__ __attribute__((aligned((MX) ? 1024 : 4))) char slabs[(MX) ? 2 * SLAB : 4];
 
+// One 128 x 128 output tile of channel c.
+template <int NS, int CIL, int MX>
+__device__ __forceinline__ void f8_tile(const uint8_t *__restrict__ A, const uint8_t *__restrict__ B,
+                                        float *__restrict__ C, const void *__restrict__ a_scale,
+                                        const void *__restrict__ b_scale, int M, int N, int Kp, int a_shared,
+                                        int c, int tm, int tn, char *lds0, char *lds1, char *lds2, char *lds3,
+                                        char *slabs) {
+    static_assert(NS >= 2 && NS <= 4 && NS <= SLAB_STAGES + 1, "ring depth");
+    char *const bufs[4] = {lds0, lds1, lds2, lds3};
     const int tid = threadIdx.x;
-    const int t = (int)xcd_remap(blockIdx.x, nblocks);
-    const int per_c = tiles_m * tiles_n;
-    const int c = t / per_c;
-    const int rem = t - c * per_c;
-    int tm, tn;
-    tile_coords(rem, tiles_m, tiles_n, tm, tn);
     const int m0 = tm * BM, n0 = tn * BN;
 
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -291,6 +292,74 @@ __global__ __launch_bounds__(NT, 2) void cgemm_f8_kernel(
     store_tile_staged<2, CIL>(acc, row_ptr, C + (int64_t)c * 2 * M * N, M, N, m0, n0, wave, lane);
 }
 
+template <int NS, int CIL, int MX>
+__global__ __launch_bounds__(NT, 2) void cgemm_f8_kernel(
+    const uint8_t *__restrict__ A, const uint8_t *__restrict__ B, float *__restrict__ C,
+    const void *__restrict__ a_scale, const void *__restrict__ b_scale, int M, int N, int Kp, int a_shared,
+    int tiles_m, int tiles_n, int nblocks) {
+    TCBF_F8_LDS(NS, MX)
+    const int t = (int)xcd_remap(blockIdx.x, nblocks);
+    const int per_c = tiles_m * tiles_n;
+    const int c = t / per_c;
+    const int rem = t - c * per_c;
+    int tm, tn;
+    tile_coords(rem, tiles_m, tiles_n, tm, tn);
+    f8_tile<NS, CIL, MX>(A, B, C, a_scale, b_scale, M, N, Kp, a_shared, c, tm, tn, lds0, lds1, lds2, lds3, slabs);
+}
+
+// Grouped persistent launch: problems of different shapes (and their own
+// scales) in one launch; workgroups take tile indices from a device counter
+// and run the plain kernel's tile code (two-stage ring), so every problem's
+// output equals its own plan's bit for bit.  The table travels in the kernel
+// arguments.
+struct F8GroupProblem {
+    const uint8_t *A;
+    const uint8_t *B;
+    float *C;
+    const void *a_scale;
+    const void *b_scale;
+    int M, N, Kp, a_shared;
+    int tiles_m, tiles_n;  // per channel
+    int first_tile;        // index of this problem's first tile in the list
+    int pad;
+};
+struct F8GroupArgs {
+    F8GroupProblem p[TCBF_GROUP_MAX];
+    int count, total_tiles;
+};
+
+template <int CIL, int MX>
+__global__ __launch_bounds__(NT, 2) void cgemm_f8_group_kernel(const F8GroupArgs args,
+                                                                unsigned int *__restrict__ counter) {
+    TCBF_F8_LDS(2, MX)
+    __shared__ int next_tile;
+    for (;;) {
+        if (threadIdx.x == 0) next_tile = (int)atomicAdd(counter, 1u);
+        // the index is visible, and every wave has finished the previous
+        // tile's LDS use (epilogue staging, scale slabs) before the next
+        // tile's loads land
+        lds_barrier();
+        const int t = __builtin_amdgcn_readfirstlane(next_tile);
+        if (t >= args.total_tiles) break;
+        int pi = 0;
+        for (int i = 1; i < args.count; ++i)
+            if (t >= args.p[i].first_tile) pi = i;
+        const F8GroupProblem &q = args.p[pi];
+        const int local = t - q.first_tile;
+        const int per_c = q.tiles_m * q.tiles_n;
+        const int c = local / per_c;
+        const int rem = local - c * per_c;
+        int tm, tn;
+        tile_coords(rem, q.tiles_m, q.tiles_n, tm, tn);
+        f8_tile<2, CIL, MX>(q.A, q.B, q.C, q.a_scale, q.b_scale, q.M, q.N, q.Kp, q.a_shared, c, tm, tn, lds0, lds1,
+                            lds2, lds3, slabs);
+        // next_tile is rewritten only after the tile's own barriers, which
+        // every wave passes after reading it
+    }
+}
+
+__global__ void f8_group_reset_kernel(unsigned int *counter) { *counter = 0u; }
+
 typedef void (*F8Fn)(const uint8_t *, const uint8_t *, float *, const void *, const void *, int, int, int, int, int,
                      int, int);
 
@@ -336,6 +405,45 @@ hipError_t f8_launch(const Problem &p, const F8Config &cfg, bool mx, const void 
     hipLaunchKernelGGL(fn, dim3((uint32_t)nblocks), dim3(NT), 0, stream, (const uint8_t *)A, (const uint8_t *)B,
                        (float *)C, a_scale, b_scale, (int)p.M, (int)p.N, (int)f8_kp(p.K), p.a_shared, tiles_m,
                        tiles_n, (int)nblocks);
+    return hipGetLastError();
+}
+
+int64_t f8_group_tiles(const Problem &p) {
+    return p.batch * ((p.M + BM - 1) / BM) * ((p.N + BN - 1) / BN);
+}
+
+hipError_t f8_group_launch(const Problem *probs, const void *const *A, const void *const *B, void *const *C,
+                           const void *const *SA, const void *const *SB, const int *order, int count, bool mx,
+                           int c_layout, int grid, unsigned int *counter, hipStream_t stream) {
+    F8GroupArgs args;
+    memset(&args, 0, sizeof(args));
+    int64_t first = 0;
+    for (int j = 0; j < count; ++j) {
+        const int i = order[j];
+        const Problem &p = probs[i];
+        F8GroupProblem &q = args.p[j];
+        q.A = (const uint8_t *)A[i];
+        q.B = (const uint8_t *)B[i];
+        q.C = (float *)C[i];
+        q.a_scale = SA[i];
+        q.b_scale = SB[i];
+        q.M = (int)p.M;
+        q.N = (int)p.N;
+        q.Kp = (int)f8_kp(p.K);
+        q.a_shared = p.a_shared;
+        q.tiles_m = (int)((p.M + BM - 1) / BM);
+        q.tiles_n = (int)((p.N + BN - 1) / BN);
+        q.first_tile = (int)first;
+        first += f8_group_tiles(p);
+    }
+    args.count = count;
+    args.total_tiles = (int)first;
+    hipLaunchKernelGGL(f8_group_reset_kernel, dim3(1), dim3(1), 0, stream, counter);
+    const bool cil = c_layout == TCBF_INTERLEAVED;
+    void (*fn)(const F8GroupArgs, unsigned int *) =
+        mx ? (cil ? cgemm_f8_group_kernel<1, 1> : cgemm_f8_group_kernel<0, 1>)
+           : (cil ? cgemm_f8_group_kernel<1, 0> : cgemm_f8_group_kernel<0, 0>);
+    hipLaunchKernelGGL(fn, dim3((uint32_t)grid), dim3(NT), 0, stream, args, counter);
     return hipGetLastError();
 }
 

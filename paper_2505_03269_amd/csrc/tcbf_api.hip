@@ -276,13 +276,15 @@ tcbf_status tcbf_peak_probe(int32_t kind, int64_t blocks, int64_t iterations, ui
 tcbf_status tcbf_group_execute(int32_t device, int32_t dtype, int32_t c_layout, const tcbf_group_problem *problems,
                                int32_t count, void *workspace, void *stream) {
     if (problems == nullptr || workspace == nullptr) return TCBF_ERROR_INVALID_VALUE;
-    if (dtype != TCBF_F16 || !is_layout(c_layout)) return TCBF_ERROR_INVALID_VALUE;
+    if ((dtype != TCBF_F16 && !is_f8(dtype)) || !is_layout(c_layout)) return TCBF_ERROR_INVALID_VALUE;
     if (count < 1 || count > TCBF_GROUP_MAX) return TCBF_ERROR_INVALID_VALUE;
     if (!aligned16(workspace)) return TCBF_ERROR_INVALID_VALUE;
     tcbf::Problem probs[TCBF_GROUP_MAX];
     const void *A[TCBF_GROUP_MAX];
     const void *B[TCBF_GROUP_MAX];
     void *C[TCBF_GROUP_MAX];
+    const void *SA[TCBF_GROUP_MAX];
+    const void *SB[TCBF_GROUP_MAX];
     int order[TCBF_GROUP_MAX];
     int64_t total = 0;
     for (int i = 0; i < count; ++i) {
@@ -290,14 +292,28 @@ tcbf_status tcbf_group_execute(int32_t device, int32_t dtype, int32_t c_layout, 
         if (g.A == nullptr || g.B == nullptr || g.C == nullptr || g.reserved != 0) return TCBF_ERROR_INVALID_VALUE;
         if (!aligned16(g.A) || !aligned16(g.B) || !aligned16(g.C)) return TCBF_ERROR_INVALID_VALUE;
         if (g.batch < 1 || g.M < 1 || g.N < 1 || g.K < 1) return TCBF_ERROR_INVALID_VALUE;
-        if (g.K % 8 != 0 || g.N % 8 != 0) return TCBF_ERROR_INVALID_VALUE;
         probs[i] = tcbf::Problem{g.batch, g.M, g.N, g.K, TCBF_PLANAR, TCBF_PLANAR, c_layout, g.a_shared != 0};
-        if (!tcbf::f16_group_problem_ok(probs[i])) return TCBF_ERROR_NOT_SUPPORTED;
-        total += tcbf::f16_group_tiles(probs[i]);
+        if (dtype == TCBF_F16) {
+            if (g.K % 8 != 0 || g.N % 8 != 0) return TCBF_ERROR_INVALID_VALUE;
+            if (g.a_scale != nullptr || g.b_scale != nullptr) return TCBF_ERROR_INVALID_VALUE;
+            if (!tcbf::f16_group_problem_ok(probs[i])) return TCBF_ERROR_NOT_SUPPORTED;
+            total += tcbf::f16_group_tiles(probs[i]);
+        } else {
+            if (g.N % 4 != 0) return TCBF_ERROR_INVALID_VALUE;
+            if (g.a_scale == nullptr || g.b_scale == nullptr) return TCBF_ERROR_INVALID_VALUE;
+            if (!aligned16(g.a_scale) || !aligned16(g.b_scale)) return TCBF_ERROR_INVALID_VALUE;
+            // the plan limits: byte offsets of per-channel operands and output fit 31 bits
+            const int64_t kp = tcbf::f8_kp(g.K);
+            if (2 * g.M * kp >= kMaxIndex || 2 * g.N * kp >= kMaxIndex || 8 * g.M * g.N >= kMaxIndex)
+                return TCBF_ERROR_NOT_SUPPORTED;
+            total += tcbf::f8_group_tiles(probs[i]);
+        }
         if (total >= kMaxIndex) return TCBF_ERROR_NOT_SUPPORTED;
         A[i] = g.A;
         B[i] = g.B;
         C[i] = g.C;
+        SA[i] = g.a_scale;
+        SB[i] = g.b_scale;
         order[i] = i;
     }
     // longest tiles (most receivers) first, so the list ends on short tiles
@@ -308,8 +324,11 @@ tcbf_status tcbf_group_execute(int32_t device, int32_t dtype, int32_t c_layout, 
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1)
         return TCBF_ERROR_DEVICE;
     const int grid = (int)std::min<int64_t>(total, 2 * (int64_t)cus);
-    hipError_t e = tcbf::f16_group_launch(probs, A, B, C, order, count, c_layout, grid, (unsigned int *)workspace,
-                                          (hipStream_t)stream);
+    hipError_t e = dtype == TCBF_F16
+                       ? tcbf::f16_group_launch(probs, A, B, C, order, count, c_layout, grid,
+                                                (unsigned int *)workspace, (hipStream_t)stream)
+                       : tcbf::f8_group_launch(probs, A, B, C, SA, SB, order, count, dtype == TCBF_MXF8_E4M3, c_layout,
+                                               grid, (unsigned int *)workspace, (hipStream_t)stream);
     return e == hipSuccess ? TCBF_SUCCESS : TCBF_ERROR_DEVICE;
 }
 

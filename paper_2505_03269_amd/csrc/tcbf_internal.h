@@ -51,6 +51,11 @@ __host__ __device__ inline int64_t mx_scale_pitch(int64_t kp) { return (kp / 32 
 bool f8_select(const Problem &p, int forced_variant, F8Config *cfg);
 int64_t f8_workgroups(const Problem &p, const F8Config &cfg);
 const char *f8_kernel_name(const F8Config &cfg);
+// Grouped FP8 launch (per-row or per-block scales, one kind per launch).
+int64_t f8_group_tiles(const Problem &p);
+hipError_t f8_group_launch(const Problem *probs, const void *const *A, const void *const *B, void *const *C,
+                           const void *const *SA, const void *const *SB, const int *order, int count, bool mx,
+                           int c_layout, int grid, unsigned int *counter, hipStream_t stream);
 hipError_t f8_launch(const Problem &p, const F8Config &cfg, bool mx, const void *A, const void *B, void *C,
                      const void *a_scale, const void *b_scale, hipStream_t stream);
 

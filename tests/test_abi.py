@@ -157,18 +157,27 @@ def test_group_argument_checks():
     buf = ctypes.create_string_buffer(1024)
     addr = (ctypes.addressof(buf) + 15) & ~15
     p = ctypes.c_void_p(addr)
-    good = tcbf.GroupProblem(addr, addr, addr, 1, 8, 8, 8, 0, 0)
+    good = tcbf.GroupProblem(addr, addr, addr, 1, 8, 8, 8, 0, 0, None, None)
     one = (tcbf.GroupProblem * 1)(good)
     assert L.tcbf_group_execute(0, tcbf.F16, 0, None, 1, p, None) == 1                 # no problems
     assert L.tcbf_group_execute(0, tcbf.F16, 0, one, 0, p, None) == 1                  # count 0
     assert L.tcbf_group_execute(0, tcbf.F16, 0, one, tcbf.GROUP_MAX + 1, p, None) == 1
-    assert L.tcbf_group_execute(0, tcbf.INT1, 0, one, 1, p, None) == 1                 # fp16 only
+    assert L.tcbf_group_execute(0, tcbf.INT1, 0, one, 1, p, None) == 1                 # fp16 / FP8 only
     assert L.tcbf_group_execute(0, tcbf.F16, 0, one, 1, ctypes.c_void_p(addr + 4), None) == 1
-    for bad in (dict(K=12), dict(N=4), dict(batch=0), dict(reserved=1), dict(A=addr + 2)):
+    for bad in (dict(K=12), dict(N=4), dict(batch=0), dict(reserved=1), dict(A=addr + 2), dict(a_scale=addr)):
         d = dict(A=addr, B=addr, C=addr, batch=1, M=8, N=8, K=8, a_shared=0, reserved=0)
         d.update(bad)
         arr = (tcbf.GroupProblem * 1)(tcbf.GroupProblem(**d))
         assert L.tcbf_group_execute(0, tcbf.F16, 0, arr, 1, p, None) == 1, bad
+    # FP8: scales required and aligned, N a multiple of 4, the plan's size limits
+    for dt in (tcbf.F8_E4M3, tcbf.MXF8_E4M3):
+        for bad, want in ((dict(), 1), (dict(a_scale=addr), 1), (dict(a_scale=addr, b_scale=addr + 4), 1),
+                          (dict(a_scale=addr, b_scale=addr, N=6), 1),
+                          (dict(a_scale=addr, b_scale=addr, M=1 << 14, K=1 << 16), 2)):
+            d = dict(A=addr, B=addr, C=addr, batch=1, M=8, N=8, K=40, a_shared=0, reserved=0)
+            d.update(bad)
+            arr = (tcbf.GroupProblem * 1)(tcbf.GroupProblem(**d))
+            assert L.tcbf_group_execute(0, dt, 0, arr, 1, p, None) == want, (dt, bad)
 
 
 def test_valid_descriptor_without_gpu_reports_device():

@@ -130,3 +130,86 @@ def test_group_rejects_bad_problems():
     W2, X2, Wd2, Xd2, C2 = make(98, 1, 64, 60, 64)       # N not a multiple of 8
     with pytest.raises(tcbf.TcbfError):
         tcbf.group_execute([(Wd2, Xd2, C2)])
+
+
+# FP8: (batch, M, N, K, shared W) -- ragged K (K % 64 == 32 for the per-block
+# tail), N a multiple of 4 but not of 8, one shared-W problem
+F8_MIX = [(1, 300, 264, 576), (2, 128, 132, 96), (1, 1000, 40, 8), (3, 200, 392, 200), (1, 64, 1024, 2048),
+          (2, 513, 136, 160), (1, 130, 8, 1032)]
+
+
+def make_f8(seed, batch, M, N, K, dtype, shared=False, layout=tcbf.PLANAR):
+    W, X = wl.random_f16_case(seed, batch, M, N, K, shared_w=shared)
+    block = 0 if dtype == tcbf.F8_E4M3 else 32
+    Wq, Ws = tcbf.quantize_e4m3(to_dev(W), k_major=True, block=block)
+    Xq, Xs = tcbf.quantize_e4m3(to_dev(X), k_major=False, block=block)
+    Cshape = (batch, 2, M, N) if layout == tcbf.PLANAR else (batch, M, N, 2)
+    return Wq, Ws, Xq, Xs, torch.full(Cshape, float("nan"), device="cuda:0")
+
+
+def single_f8(Wq, Ws, Xq, Xs, batch, M, N, K, dtype, shared=False, layout=tcbf.PLANAR):
+    plan = tcbf.Plan(batch, M, N, K, dtype, c_layout=layout, a_shared=shared)
+    C = plan.empty_output()
+    plan.execute(Wq, Xq, C, Ws, Xs)
+    return C
+
+
+@pytest.mark.parametrize("layout", [tcbf.PLANAR, tcbf.INTERLEAVED])
+@pytest.mark.parametrize("dtype", [tcbf.F8_E4M3, tcbf.MXF8_E4M3])
+def test_group_f8_equals_single_plans(dtype, layout):
+    cases = []
+    for i, (b, M, N, K) in enumerate(F8_MIX):
+        shared = i == 3
+        cases.append(((b, M, N, K, shared), make_f8(140 + i, b, M, N, K, dtype, shared, layout)))
+    log("fp8 group dtype %d layout %d" % (dtype, layout))
+    tcbf.group_execute([(Wq, Xq, C, Ws, Xs, sh) for (_, _, _, _, sh), (Wq, Ws, Xq, Xs, C) in cases],
+                       c_layout=layout, dtype=dtype)
+    torch.cuda.synchronize()
+    for (b, M, N, K, sh), (Wq, Ws, Xq, Xs, C) in cases:
+        ref = single_f8(Wq, Ws, Xq, Xs, b, M, N, K, dtype, sh, layout)
+        torch.cuda.synchronize()
+        got = C.cpu().numpy()
+        assert not np.isnan(got).any(), (b, M, N, K)
+        assert np.array_equal(got, ref.cpu().numpy()), (dtype, b, M, N, K)
+
+
+def test_group_f8_graph_replays_match_eager():
+    """A captured grouped FP8 launch (per-block scales) replayed with new
+    inputs quantised eagerly between replays equals single plans each time."""
+    dtype = tcbf.MXF8_E4M3
+    shapes = [(2, 200, 264, 576), (1, 96, 128, 96), (3, 128, 136, 200)]
+    cases = [make_f8(160 + i, *s, dtype) for i, s in enumerate(shapes)]
+    ws = torch.empty(tcbf.GROUP_WORKSPACE_BYTES, dtype=torch.uint8, device="cuda:0")
+    probs = [(Wq, Xq, C, Ws, Xs) for (Wq, Ws, Xq, Xs, C) in cases]
+    tcbf.group_execute(probs, workspace=ws, dtype=dtype)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            tcbf.group_execute(probs, workspace=ws, dtype=dtype)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(7)
+    for rep in range(3):
+        for (Wq, Ws, Xq, Xs, C), (b, M, N, K) in zip(cases, shapes):
+            X = torch.randint(-127, 128, (b, 2, K, N), device="cuda:0", generator=gen).half()
+            tcbf.quantize_e4m3(X, k_major=False, block=32, out=Xq, scales=Xs)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for (Wq, Ws, Xq, Xs, C), (b, M, N, K) in zip(cases, shapes):
+            ref = single_f8(Wq, Ws, Xq, Xs, b, M, N, K, dtype)
+            torch.cuda.synchronize()
+            assert np.array_equal(C.cpu().numpy(), ref.cpu().numpy()), "replay %d" % rep
+
+
+def test_group_f8_rejects_mismatched_scales():
+    Wq, Ws, Xq, Xs, C = make_f8(170, 1, 64, 64, 64, tcbf.F8_E4M3)
+    with pytest.raises(ValueError):
+        tcbf.group_execute([(Wq, Xq, C, Ws[:, :32], Xs)], dtype=tcbf.F8_E4M3)
+    with pytest.raises(ValueError):
+        tcbf.group_execute([(Wq, Xq, C, Ws, Xs)], dtype=tcbf.MXF8_E4M3)
+
