@@ -361,6 +361,31 @@ def bench_secondary(steps, serving=True, copy_gbs=None):
                     "roofline": {"bound": "mfma", "achieved": round(tops, 1), "peak": PEAK_F16_TFLOPS,
                                  "unit": "TFLOP/s", "frac": round(tops / PEAK_F16_TFLOPS, 4)}})
         del probs, plans
+    # the same small-job mix in FP8 (per-row scales), codes made on the GPU
+    shapes = wl.mixed_shapes(0, 32, m_range=(128, 512), n_range=(256, 1024), k_range=(64, 512))
+    probs, plans = [], []
+    for (M, N, K) in shapes:
+        Wg = torch.randn((1, 2, M, K), device="cuda:0", generator=g).half()
+        Xg = torch.randint(-127, 128, (1, 2, K, N), device="cuda:0", generator=g).half()
+        Wq, Ws = tcbf.quantize_e4m3(Wg, k_major=True, block=0)
+        Xq, Xs = tcbf.quantize_e4m3(Xg, k_major=False, block=0)
+        probs.append((Wq, Xq, torch.empty((1, 2, M, N), device="cuda:0"), Ws, Xs))
+        plans.append(tcbf.Plan(1, M, N, K, tcbf.F8_E4M3))
+    ops = sum(8.0 * M * N * K for (M, N, K) in shapes)
+    ms_g = time_launches(lambda: tcbf.group_execute(probs, workspace=ws, dtype=tcbf.F8_E4M3), st, 1)
+
+    def each8():
+        for pl, (Wq, Xq, Cg, Ws, Xs) in zip(plans, probs):
+            pl.execute(Wq, Xq, Cg, Ws, Xs)
+    ms_s = time_launches(each8, st, 1)
+    tops = ops / (ms_g * 1e-3) / 1e12
+    out.append({"workload": "grouped fp8 per-row: 32 small jobs, M~U[128,512] N~U[256,1024] K~U[64,512]",
+                "kernel": "cgemm_f8_group_kernel", "value": round(tops, 1), "unit": "TeraOps/s",
+                "ms_per_launch": round(ms_g, 4), "separate_launches_tops": round(ops / (ms_s * 1e-3) / 1e12, 1),
+                "separate_launches_ms": round(ms_s, 4), "dtype": "e4m3",
+                "roofline": {"bound": "mfma", "achieved": round(tops, 1), "peak": PEAK_F8_TFLOPS,
+                             "unit": "TFLOP/s", "frac": round(tops / PEAK_F8_TFLOPS, 4)}})
+    del probs, plans
     torch.cuda.empty_cache()
     if serving:
         out.append(bench_serving())
@@ -384,7 +409,7 @@ def bench_serving(warmup=1000, measured=10000):
     rnd = lambda d: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()}  # noqa: E731
     return {"workload": "served mixed stream: fp16/fp8/1-bit jobs, 16 resident weight sets per dtype, "
                         "M~U[128,4096] K~U[64,2048] N~U[256,8192], Poisson arrivals at 80% of capacity",
-            "kernel": "cgemm_f16_group_kernel + cgemm_f8_kernel + cgemm_1bit_mfma_kernel",
+            "kernel": "cgemm_f16_group_kernel + cgemm_f8_group_kernel + cgemm_1bit_mfma_kernel",
             "value": round(r["tops"], 1), "unit": "TeraOps/s", "p50_ms": round(r["p50_ms"], 3),
             "p99_ms": round(r["p99_ms"], 3), "capacity_jobs_per_s": round(cap, 1),
             "closed_loop": rnd(closed), "load_0.8": rnd(runs[0.8]), "load_0.5": rnd(runs[0.5]),
