@@ -409,7 +409,7 @@ def bench_serving(warmup=1000, measured=10000):
     rnd = lambda d: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()}  # noqa: E731
     return {"workload": "served mixed stream: fp16/fp8/1-bit jobs, 16 resident weight sets per dtype, "
                         "M~U[128,4096] K~U[64,2048] N~U[256,8192], Poisson arrivals at 80% of capacity",
-            "kernel": "cgemm_f16_group_kernel + cgemm_f8_group_kernel + cgemm_1bit_mfma_kernel",
+            "kernel": "cgemm_f16_group_kernel + cgemm_f8_group_kernel + cgemm_1bit_group_kernel",
             "value": round(r["tops"], 1), "unit": "TeraOps/s", "p50_ms": round(r["p50_ms"], 3),
             "p99_ms": round(r["p99_ms"], 3), "capacity_jobs_per_s": round(cap, 1),
             "closed_loop": rnd(closed), "load_0.8": rnd(runs[0.8]), "load_0.5": rnd(runs[0.5]),

@@ -235,10 +235,11 @@ tcbf_status tcbf_steering_weights(const double *positions, const double *directi
                                   int64_t M, int64_t K, int32_t out_type, void *W, void *stream);
 
 /*
- * Grouped persistent launch (TCBF_F16, TCBF_F8_E4M3, TCBF_MXF8_E4M3): up to
- * TCBF_GROUP_MAX independent problems of different shapes -- channels, frames
- * or jobs, each B = W . X in the layouts of `dtype` (planar W and X for fp16;
- * the e4m3 codes and scales of that FP8 mode) -- run in ONE launch.  The
+ * Grouped persistent launch (TCBF_F16, TCBF_F8_E4M3, TCBF_MXF8_E4M3,
+ * TCBF_INT1): up to TCBF_GROUP_MAX independent problems of different shapes
+ * -- channels, frames or jobs, each B = W . X in the layouts of `dtype`
+ * (planar W and X for fp16; the e4m3 codes and scales of that FP8 mode; the
+ * packed sign words for 1-bit, int8-MFMA variant) -- run in ONE launch.  The
  * problems' output tiles form one work list, longest receiver count first
  * (the paper's Sec. IV-C size sweep shows per-shape padding and tail effects;
  * one shared list keeps every CU busy across shape boundaries); persistent
@@ -249,7 +250,8 @@ tcbf_status tcbf_steering_weights(const double *positions, const double *directi
  *     each needs batch, M, N, K >= 1, 16-byte aligned device pointers and
  *     the size limits of a plan of its dtype; fp16: K and N multiples of 8,
  *     per-channel W and X below 2 GiB, a_scale = b_scale = NULL; FP8: N a
- *     multiple of 4, a_scale and b_scale as for tcbf_execute.  Every
+ *     multiple of 4, a_scale and b_scale as for tcbf_execute; 1-bit: K at
+ *     most 2^26, a_scale = b_scale = NULL, int32 output.  Every
  *     problem's output equals its own plan's (default variant) bit for bit.
  *   workspace: device memory of TCBF_GROUP_WORKSPACE_BYTES, 16-byte aligned,
  *     used for the tile counter; calls that overlap in time (on different
@@ -263,7 +265,7 @@ tcbf_status tcbf_steering_weights(const double *positions, const double *directi
 typedef struct tcbf_group_problem {
     const void *A;       /* W in the dtype's layout (shared: one batch entry) */
     const void *B;       /* X in the dtype's layout                           */
-    void *C;             /* output fp32, layout c_layout                      */
+    void *C;             /* output (fp32; int32 for 1-bit), layout c_layout   */
     int64_t batch, M, N, K;
     int32_t a_shared;    /* nonzero: one W for all batch entries              */
     int32_t reserved;    /* must be 0                                         */

@@ -420,7 +420,10 @@ def group_execute(problems, c_layout=PLANAR, workspace=None, device=0, stream=No
     (W, X, C, a_scale, b_scale, a_shared) with e4m3 codes W uint8
     [batch|1, 2, M, Kp], X uint8 [batch, 2, N, Kp] and the scales of that
     mode (see Plan.shape_a_scale / shape_b_scale).
-    C: float32 [batch, 2, M, N] (planar) or [batch, M, N, 2] (interleaved).
+    dtype INT1: (W, X, C, K) or (W, X, C, K, a_shared) with packed sign words
+    W int32 [batch|1, 2, M, kw], X int32 [batch, 2, N, kw] and the true K.
+    C: float32 (int32 for INT1) [batch, 2, M, N] (planar) or [batch, M, N, 2]
+    (interleaved).
     workspace: uint8 device tensor of GROUP_WORKSPACE_BYTES (allocated here
     if None; pass one to stay allocation-free).
     """
@@ -428,26 +431,34 @@ def group_execute(problems, c_layout=PLANAR, workspace=None, device=0, stream=No
     if not 1 <= len(problems) <= GROUP_MAX:
         raise ValueError("1..%d problems per launch" % GROUP_MAX)
     f8 = _is_f8(dtype)
-    if dtype != F16 and not f8:
-        raise ValueError("grouped launches take F16, F8_E4M3 or MXF8_E4M3")
+    if dtype not in (F16, INT1) and not f8:
+        raise ValueError("grouped launches take F16, F8_E4M3, MXF8_E4M3 or INT1")
     arr = (GroupProblem * len(problems))()
     for i, pr in enumerate(problems):
         W, X, C = pr[0], pr[1], pr[2]
-        nfix = 5 if f8 else 3
+        nfix = 5 if f8 else 4 if dtype == INT1 else 3   # fields before the optional a_shared
         shared = bool(pr[nfix]) if len(pr) > nfix else False
-        elem = torch.uint8 if f8 else torch.float16
-        if W.dtype != elem or X.dtype != elem or C.dtype != torch.float32:
-            raise ValueError("problem %d: W, X %s and C float32 expected" % (i, elem))
+        elem = torch.uint8 if f8 else torch.int32 if dtype == INT1 else torch.float16
+        cdt = torch.int32 if dtype == INT1 else torch.float32
+        if W.dtype != elem or X.dtype != elem or C.dtype != cdt:
+            raise ValueError("problem %d: W, X %s and C %s expected" % (i, elem, cdt))
         if W.dim() != 4 or X.dim() != 4 or W.shape[1] != 2 or X.shape[1] != 2:
             raise ValueError("problem %d: planar W [b, 2, M, K] and X [b, 2, ., .] expected" % i)
-        if f8:
+        if dtype == INT1:
+            if len(pr) < 4:
+                raise ValueError("problem %d: 1-bit problems are (W, X, C, K[, a_shared])" % i)
+            batch, N, kw = X.shape[0], X.shape[2], X.shape[3]
+            K = int(pr[3])
+            if not 0 < K <= 32 * kw or (K + 31) // 32 != kw:
+                raise ValueError("problem %d: K does not match the word count" % i)
+        elif f8:
             batch, N, K = X.shape[0], X.shape[2], X.shape[3]
             if K % 32:
                 raise ValueError("problem %d: FP8 rows must be Kp = 32 * ceil(K / 32) bytes" % i)
         else:
             batch, K, N = X.shape[0], X.shape[2], X.shape[3]
         M = W.shape[2]
-        if W.shape[3] != K or W.shape[0] != (1 if shared else batch):
+        if W.shape[3] != X.shape[3 if dtype != F16 else 2] or W.shape[0] != (1 if shared else batch):
             raise ValueError("problem %d: W does not match X" % i)
         want = (batch, 2, M, N) if c_layout == PLANAR else (batch, M, N, 2)
         if tuple(C.shape) != want:

@@ -27,6 +27,8 @@
 //     Re = 2 (Kp - (popc(Ar ^ Br) + popc(Ai ^ ~Bi)))
 //     Im = 2 (Kp - Kpad - (popc(Ar ^ Bi) + popc(Ai ^ Br)))
 // with Kp the number of bit positions processed and Kpad = Kp - K.
+#include <cstring>
+
 #include "tcbf_internal.h"
 
 namespace tcbf {
@@ -87,21 +89,14 @@ __device__ __forceinline__ i32x4 expand(uint32_t x) {
     return v;
 }
 
+// One 128 x 128 output tile of channel c; lds holds the two stages,
+// popA / popB the row bit counts of the tile's operands.
 template <int CIL>
-__global__ __launch_bounds__(U_NT, 2) void cgemm_1bit_mfma_kernel(
-    const uint32_t *__restrict__ A, const uint32_t *__restrict__ B, int32_t *__restrict__ C,
-    int64_t M, int64_t N, int64_t K, int64_t kw, int a_shared, int tiles_m, int tiles_n,
-    int64_t nblocks, int vec) {
-    __shared__ __attribute__((aligned(16))) uint32_t lds[2 * U_STAGE];
-    __shared__ int popA[2][U_BM], popB[2][U_BN];
-
+__device__ __forceinline__ void int1_tile(const uint32_t *__restrict__ A, const uint32_t *__restrict__ B,
+                                          int32_t *__restrict__ C, int64_t M, int64_t N, int64_t K, int64_t kw,
+                                          int a_shared, int64_t c, int tm, int tn, int vec, uint32_t *lds,
+                                          int (*popA)[U_BM], int (*popB)[U_BN]) {
     const int tid = threadIdx.x;
-    const int64_t t = xcd_remap(blockIdx.x, nblocks);
-    const int64_t per_c = (int64_t)tiles_m * tiles_n;
-    const int64_t c = t / per_c;
-    const int rem = (int)(t - c * per_c);
-    int tm, tn;
-    tile_coords(rem, tiles_m, tiles_n, tm, tn);
     const int64_t m0 = (int64_t)tm * U_BM, n0 = (int64_t)tn * U_BN;
 
     // loader: thread -> (plane, row) of both tiles; 4 words per stage each
@@ -221,6 +216,72 @@ __global__ __launch_bounds__(U_NT, 2) void cgemm_1bit_mfma_kernel(
             }
         }
 }
+
+template <int CIL>
+__global__ __launch_bounds__(U_NT, 2) void cgemm_1bit_mfma_kernel(
+    const uint32_t *__restrict__ A, const uint32_t *__restrict__ B, int32_t *__restrict__ C,
+    int64_t M, int64_t N, int64_t K, int64_t kw, int a_shared, int tiles_m, int tiles_n,
+    int64_t nblocks, int vec) {
+    __shared__ __attribute__((aligned(16))) uint32_t lds[2 * U_STAGE];
+    __shared__ int popA[2][U_BM], popB[2][U_BN];
+    const int64_t t = xcd_remap(blockIdx.x, nblocks);
+    const int64_t per_c = (int64_t)tiles_m * tiles_n;
+    const int64_t c = t / per_c;
+    const int rem = (int)(t - c * per_c);
+    int tm, tn;
+    tile_coords(rem, tiles_m, tiles_n, tm, tn);
+    int1_tile<CIL>(A, B, C, M, N, K, kw, a_shared, c, tm, tn, vec, lds, popA, popB);
+}
+
+// Grouped persistent launch of the int8-MFMA variant: problems of different
+// shapes in one launch, tiles taken from a device counter, each problem's
+// output equal to its own plan's.  The table travels in the kernel arguments.
+struct Int1GroupProblem {
+    const uint32_t *A;
+    const uint32_t *B;
+    int32_t *C;
+    int M, N, K, kw;  // 2 M N < 2^31 and K <= 2^26 (the plan limits)
+    int a_shared, vec;
+    int tiles_m, tiles_n;  // per channel
+    int first_tile;        // index of this problem's first tile in the list
+    int pad;
+};
+struct Int1GroupArgs {
+    Int1GroupProblem p[TCBF_GROUP_MAX];
+    int count, total_tiles;
+};
+
+template <int CIL>
+__global__ __launch_bounds__(U_NT, 2) void cgemm_1bit_group_kernel(const Int1GroupArgs args,
+                                                                    unsigned int *__restrict__ counter) {
+    __shared__ __attribute__((aligned(16))) uint32_t lds[2 * U_STAGE];
+    __shared__ int popA[2][U_BM], popB[2][U_BN];
+    __shared__ int next_tile;
+    for (;;) {
+        if (threadIdx.x == 0) next_tile = (int)atomicAdd(counter, 1u);
+        // the index is visible, and every wave has finished the previous
+        // tile (its epilogue reads the bit counts) before the next one
+        // overwrites the stages and counts
+        __syncthreads();
+        const int t = __builtin_amdgcn_readfirstlane(next_tile);
+        if (t >= args.total_tiles) break;
+        int pi = 0;
+        for (int i = 1; i < args.count; ++i)
+            if (t >= args.p[i].first_tile) pi = i;
+        const Int1GroupProblem &q = args.p[pi];
+        const int local = t - q.first_tile;
+        const int per_c = q.tiles_m * q.tiles_n;
+        const int c = local / per_c;
+        const int rem = local - c * per_c;
+        int tm, tn;
+        tile_coords(rem, q.tiles_m, q.tiles_n, tm, tn);
+        int1_tile<CIL>(q.A, q.B, q.C, q.M, q.N, q.K, q.kw, q.a_shared, c, tm, tn, q.vec, lds, popA, popB);
+        // next_tile is rewritten only after the tile's own barriers, which
+        // every wave passes after reading it
+    }
+}
+
+__global__ void int1_group_reset_kernel(unsigned int *counter) { *counter = 0u; }
 
 // ---------------------------------------------------------------------------
 // Variant 2: VALU xor/popcount.  256 threads, 64 x 64 complex outputs, each
@@ -358,6 +419,44 @@ hipError_t int1_launch(const Problem &p, const Int1Config &cfg, const uint32_t *
         hipLaunchKernelGGL(fn, dim3((uint32_t)nblocks), dim3(V_NT), 0, stream, A, B, C, p.M, p.N, p.K,
                            kw, p.a_shared, tiles_m, tiles_n, nblocks, vec);
     }
+    return hipGetLastError();
+}
+
+int64_t int1_group_tiles(const Problem &p) {
+    return p.batch * ((p.M + U_BM - 1) / U_BM) * ((p.N + U_BN - 1) / U_BN);
+}
+
+hipError_t int1_group_launch(const Problem *probs, const void *const *A, const void *const *B, void *const *C,
+                             const int *order, int count, int c_layout, int grid, unsigned int *counter,
+                             hipStream_t stream) {
+    Int1GroupArgs args;
+    memset(&args, 0, sizeof(args));
+    int64_t first = 0;
+    for (int j = 0; j < count; ++j) {
+        const int i = order[j];
+        const Problem &p = probs[i];
+        Int1GroupProblem &q = args.p[j];
+        q.A = (const uint32_t *)A[i];
+        q.B = (const uint32_t *)B[i];
+        q.C = (int32_t *)C[i];
+        q.M = (int)p.M;
+        q.N = (int)p.N;
+        q.K = (int)p.K;
+        q.kw = (int)((p.K + 31) / 32);
+        q.a_shared = p.a_shared;
+        q.vec = (q.kw % 4) == 0;
+        q.tiles_m = (int)((p.M + U_BM - 1) / U_BM);
+        q.tiles_n = (int)((p.N + U_BN - 1) / U_BN);
+        q.first_tile = (int)first;
+        first += int1_group_tiles(p);
+    }
+    args.count = count;
+    args.total_tiles = (int)first;
+    hipLaunchKernelGGL(int1_group_reset_kernel, dim3(1), dim3(1), 0, stream, counter);
+    if (c_layout == TCBF_INTERLEAVED)
+        hipLaunchKernelGGL(cgemm_1bit_group_kernel<1>, dim3((uint32_t)grid), dim3(U_NT), 0, stream, args, counter);
+    else
+        hipLaunchKernelGGL(cgemm_1bit_group_kernel<0>, dim3((uint32_t)grid), dim3(U_NT), 0, stream, args, counter);
     return hipGetLastError();
 }
 

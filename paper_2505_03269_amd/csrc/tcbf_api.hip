@@ -276,7 +276,8 @@ tcbf_status tcbf_peak_probe(int32_t kind, int64_t blocks, int64_t iterations, ui
 tcbf_status tcbf_group_execute(int32_t device, int32_t dtype, int32_t c_layout, const tcbf_group_problem *problems,
                                int32_t count, void *workspace, void *stream) {
     if (problems == nullptr || workspace == nullptr) return TCBF_ERROR_INVALID_VALUE;
-    if ((dtype != TCBF_F16 && !is_f8(dtype)) || !is_layout(c_layout)) return TCBF_ERROR_INVALID_VALUE;
+    if ((dtype != TCBF_F16 && dtype != TCBF_INT1 && !is_f8(dtype)) || !is_layout(c_layout))
+        return TCBF_ERROR_INVALID_VALUE;
     if (count < 1 || count > TCBF_GROUP_MAX) return TCBF_ERROR_INVALID_VALUE;
     if (!aligned16(workspace)) return TCBF_ERROR_INVALID_VALUE;
     tcbf::Problem probs[TCBF_GROUP_MAX];
@@ -298,6 +299,11 @@ tcbf_status tcbf_group_execute(int32_t device, int32_t dtype, int32_t c_layout, 
             if (g.a_scale != nullptr || g.b_scale != nullptr) return TCBF_ERROR_INVALID_VALUE;
             if (!tcbf::f16_group_problem_ok(probs[i])) return TCBF_ERROR_NOT_SUPPORTED;
             total += tcbf::f16_group_tiles(probs[i]);
+        } else if (dtype == TCBF_INT1) {
+            if (g.a_scale != nullptr || g.b_scale != nullptr) return TCBF_ERROR_INVALID_VALUE;
+            // the plan limits: int32 accumulators, 32-bit output indices
+            if (g.K > ((int64_t)1 << 26) || 2 * g.M * g.N >= kMaxIndex) return TCBF_ERROR_NOT_SUPPORTED;
+            total += tcbf::int1_group_tiles(probs[i]);
         } else {
             if (g.N % 4 != 0) return TCBF_ERROR_INVALID_VALUE;
             if (g.a_scale == nullptr || g.b_scale == nullptr) return TCBF_ERROR_INVALID_VALUE;
@@ -324,11 +330,15 @@ tcbf_status tcbf_group_execute(int32_t device, int32_t dtype, int32_t c_layout, 
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1)
         return TCBF_ERROR_DEVICE;
     const int grid = (int)std::min<int64_t>(total, 2 * (int64_t)cus);
-    hipError_t e = dtype == TCBF_F16
-                       ? tcbf::f16_group_launch(probs, A, B, C, order, count, c_layout, grid,
-                                                (unsigned int *)workspace, (hipStream_t)stream)
-                       : tcbf::f8_group_launch(probs, A, B, C, SA, SB, order, count, dtype == TCBF_MXF8_E4M3, c_layout,
-                                               grid, (unsigned int *)workspace, (hipStream_t)stream);
+    unsigned int *counter = (unsigned int *)workspace;
+    hipError_t e;
+    if (dtype == TCBF_F16)
+        e = tcbf::f16_group_launch(probs, A, B, C, order, count, c_layout, grid, counter, (hipStream_t)stream);
+    else if (dtype == TCBF_INT1)
+        e = tcbf::int1_group_launch(probs, A, B, C, order, count, c_layout, grid, counter, (hipStream_t)stream);
+    else
+        e = tcbf::f8_group_launch(probs, A, B, C, SA, SB, order, count, dtype == TCBF_MXF8_E4M3, c_layout, grid,
+                                  counter, (hipStream_t)stream);
     return e == hipSuccess ? TCBF_SUCCESS : TCBF_ERROR_DEVICE;
 }
 

@@ -78,6 +78,11 @@ struct Int1Config {
 bool int1_select(const Problem &p, int forced_variant, Int1Config *cfg);
 int64_t int1_workgroups(const Problem &p, const Int1Config &cfg);
 const char *int1_kernel_name(const Int1Config &cfg);
+// Grouped launch of the int8-MFMA 1-bit variant.
+int64_t int1_group_tiles(const Problem &p);
+hipError_t int1_group_launch(const Problem *probs, const void *const *A, const void *const *B, void *const *C,
+                             const int *order, int count, int c_layout, int grid, unsigned int *counter,
+                             hipStream_t stream);
 hipError_t int1_launch(const Problem &p, const Int1Config &cfg, const uint32_t *A,
                        const uint32_t *B, int32_t *C, hipStream_t stream);
 

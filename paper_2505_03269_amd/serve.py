@@ -8,10 +8,9 @@ A job asks for B = W . X with one of the resident weight sets (fp16, FP8 or
     built once at start-up;
   * admits arrived jobs in arrival order while the device-memory budget and
     the slot count allow (a job's budget is its input and output buffers);
-  * launches the admitted jobs as soon as a stream is free: the fp16 jobs of
-    a batch go into one grouped persistent launch (tcbf_group_execute), the
-    FP8 jobs into another, 1-bit jobs into their own plan launches on the same
-    stream;
+  * launches the admitted jobs as soon as a stream is free: the jobs of a
+    batch go into one grouped persistent launch per dtype
+    (tcbf_group_execute), on that stream;
   * runs several streams, so a batch formed while others are still on the
     GPU overlaps with them, and frees a job's memory and slot when the host
     sees its batch complete (an event query, no blocking wait);
@@ -204,10 +203,10 @@ class Server:
 
 
 class GpuExecutor:
-    """Runs batches through the library on the server's streams: the fp16
-    jobs of a batch in one grouped launch, the FP8 jobs (their data quantised
-    one by one) in another, 1-bit jobs as plan launches.  A batch's handle is
-    an event recorded after its launches."""
+    """Runs batches through the library on the server's streams: per dtype,
+    the jobs of a batch in one grouped launch (their data quantised or
+    sign-packed one by one first).  A batch's handle is an event recorded
+    after its launches."""
 
     def __init__(self, server):
         self.srv = server
@@ -217,7 +216,7 @@ class GpuExecutor:
         srv = self.srv
         s = srv.streams[si]
         with torch.cuda.stream(s):
-            f16, f8 = [], []
+            f16, f8, i1 = [], [], []
             for job in batch:
                 ws = srv.pool[(job.dtype, job.wid)]
                 X = job_input(job, srv.device, srv.gen)
@@ -230,10 +229,10 @@ class GpuExecutor:
                     f8.append((ws.A, job.X, job.out, ws.scale, job.xs))
                 else:
                     job.X = pack1bit(X, k_major=False)
-                    srv._plan(INT1, job.M, job.N, job.K).execute(ws.A, job.X, job.out)
-            # one workspace per stream: the two grouped launches of a batch
-            # run one after the other on it
-            for dt, probs in ((F16, f16), (F8_E4M3, f8)):
+                    i1.append((ws.A, job.X, job.out, job.K))
+            # one workspace per stream: the grouped launches of a batch run
+            # one after the other on it
+            for dt, probs in ((F16, f16), (F8_E4M3, f8), (INT1, i1)):
                 for i in range(0, len(probs), GROUP_MAX):
                     group_execute(probs[i:i + GROUP_MAX], workspace=srv.workspaces[si], device=srv.dev_index,
                                   dtype=dt)

@@ -162,7 +162,13 @@ def test_group_argument_checks():
     assert L.tcbf_group_execute(0, tcbf.F16, 0, None, 1, p, None) == 1                 # no problems
     assert L.tcbf_group_execute(0, tcbf.F16, 0, one, 0, p, None) == 1                  # count 0
     assert L.tcbf_group_execute(0, tcbf.F16, 0, one, tcbf.GROUP_MAX + 1, p, None) == 1
-    assert L.tcbf_group_execute(0, tcbf.INT1, 0, one, 1, p, None) == 1                 # fp16 / FP8 only
+    assert L.tcbf_group_execute(0, 9, 0, one, 1, p, None) == 1                         # unknown dtype
+    int1 = dict(A=addr, B=addr, C=addr, batch=1, M=8, N=8, K=8, a_shared=0, reserved=0)
+    for bad, want in ((dict(a_scale=addr), 1), (dict(K=(1 << 26) + 1), 2), (dict(M=1 << 16, N=1 << 15), 2)):
+        d = dict(int1)
+        d.update(bad)
+        arr = (tcbf.GroupProblem * 1)(tcbf.GroupProblem(**d))
+        assert L.tcbf_group_execute(0, tcbf.INT1, 0, arr, 1, p, None) == want, bad
     assert L.tcbf_group_execute(0, tcbf.F16, 0, one, 1, ctypes.c_void_p(addr + 4), None) == 1
     for bad in (dict(K=12), dict(N=4), dict(batch=0), dict(reserved=1), dict(A=addr + 2), dict(a_scale=addr)):
         d = dict(A=addr, B=addr, C=addr, batch=1, M=8, N=8, K=8, a_shared=0, reserved=0)

@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 import workloads as wl
-from gpu_util import check_fp_full, log, to_dev
+from gpu_util import check_fp_full, log, to_dev, words_to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -212,4 +212,37 @@ def test_group_f8_rejects_mismatched_scales():
         tcbf.group_execute([(Wq, Xq, C, Ws[:, :32], Xs)], dtype=tcbf.F8_E4M3)
     with pytest.raises(ValueError):
         tcbf.group_execute([(Wq, Xq, C, Ws, Xs)], dtype=tcbf.MXF8_E4M3)
+
+
+# 1-bit: ragged K (partial last word, word counts not a multiple of 4), one
+# shared-W problem, tiles cut by M and N
+INT1_MIX = [(1, 300, 264, 576), (2, 128, 130, 95), (1, 1000, 40, 8), (3, 200, 392, 200), (1, 64, 1024, 2049),
+            (2, 513, 136, 160), (1, 130, 8, 1032)]
+
+
+@pytest.mark.parametrize("layout", [tcbf.PLANAR, tcbf.INTERLEAVED])
+def test_group_int1_equals_single_plans_and_oracle(layout):
+    cases = []
+    for i, (b, M, N, K) in enumerate(INT1_MIX):
+        shared = i == 3
+        Wp, Xp = wl.random_bits_case(180 + i, b, M, N, K, shared_w=shared)
+        Cshape = (b, 2, M, N) if layout == tcbf.PLANAR else (b, M, N, 2)
+        C = torch.full(Cshape, -7, dtype=torch.int32, device="cuda:0")
+        cases.append(((b, M, N, K, shared), Wp, Xp, words_to_dev(Wp), words_to_dev(Xp), C))
+    log("1-bit group layout %d" % layout)
+    tcbf.group_execute([(Wd, Xd, C, K, sh) for (_, _, _, K, sh), _, _, Wd, Xd, C in cases], c_layout=layout,
+                       dtype=tcbf.INT1)
+    torch.cuda.synchronize()
+    for (b, M, N, K, sh), Wp, Xp, Wd, Xd, C in cases:
+        plan = tcbf.Plan(b, M, N, K, tcbf.INT1, c_layout=layout, a_shared=sh, variant=1)
+        ref = plan.empty_output()
+        plan.execute(Wd, Xd, ref)
+        torch.cuda.synchronize()
+        got = C.cpu().numpy()
+        assert np.array_equal(got, ref.cpu().numpy()), (b, M, N, K)
+        Wr, Wi = (Wp[0, 0], Wp[0, 1]) if sh else (Wp[:, 0], Wp[:, 1])
+        rr, ri = oracle.cgemm_1bit_popc(Wr, Wi, Xp[:, 0], Xp[:, 1], K)
+        g64 = got.astype(np.int64)
+        gr, gi = (g64[:, 0], g64[:, 1]) if layout == tcbf.PLANAR else (g64[..., 0], g64[..., 1])
+        assert np.array_equal(gr, rr) and np.array_equal(gi, ri), (b, M, N, K)
 
