@@ -27,6 +27,8 @@ template <> struct Bits<uint16_t> { static __device__ uint32_t pos(uint16_t v) {
 template <> struct Bits<uint32_t> { static __device__ uint32_t pos(uint32_t v) { return (v >> 31) ^ 1u; } };
 
 constexpr int NT = 256;
+constexpr int VW = 4;            // waves per workgroup of the vectorised N-major kernel
+constexpr int VNT = 64 * VW;
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
@@ -134,25 +136,25 @@ template <> struct RawRows<0> {
 };
 
 template <typename T, int IL>
-__global__ __launch_bounds__(NT) void pack_nmajor_vec_kernel(const T *__restrict__ src, uint32_t *__restrict__ dst,
+__global__ __launch_bounds__(VNT) void pack_nmajor_vec_kernel(const T *__restrict__ src, uint32_t *__restrict__ dst,
                                                              int64_t batch, int64_t rows, int64_t K, int64_t kw) {
     constexpr int R = 8 / (int)sizeof(T);      // rows per thread
     constexpr int E = 2 * R;                   // elements in the 16 bytes of one receiver
     constexpr int W = 8 * (int)sizeof(T);      // element width in bits
     constexpr int EPD = 4 / (int)sizeof(T);    // elements per dword
     constexpr uint32_t LOW = sizeof(T) == 1 ? 0x01010101u : sizeof(T) == 2 ? 0x00010001u : 1u;
-    // Workgroup -> (c, 4 word groups, 64 row groups): wave w takes word group
-    // 4 gb + w of the workgroup's rows, so the four waves write the four
-    // 16-byte pieces of each row's 64 output bytes together (whole lines
-    // instead of scattered quarter lines); consecutive workgroups take the
-    // next rows, so the reads in flight spread along each receiver's row of
+    // Workgroup -> (c, VW word groups, 64 row groups): wave w takes word group
+    // VW gb + w of the workgroup's rows, so the VW waves write the VW 16-byte
+    // pieces of each row's 16 VW output bytes together (whole 64-byte runs
+    // instead of scattered pieces); consecutive workgroups take the next
+    // rows, so the reads in flight spread along each receiver's row of
     // samples.
     const int64_t ngroups = (kw + 3) / 4;
     const int64_t rgroups = rows / R;
-    const int64_t gblocks = (ngroups + 3) / 4, rblocks = (rgroups + 63) / 64;
+    const int64_t gblocks = (ngroups + VW - 1) / VW, rblocks = (rgroups + 63) / 64;
     const int64_t bid = blockIdx.x;
     const int64_t rb = bid % rblocks, gb = (bid / rblocks) % gblocks, c = bid / (gblocks * rblocks);
-    const int64_t g = gb * 4 + (threadIdx.x >> 6);
+    const int64_t g = gb * VW + (threadIdx.x >> 6);
     const int64_t rg = rb * 64 + (threadIdx.x & 63);
     if (c >= batch || g >= ngroups || rg >= rgroups) return;
     const int64_t r0 = rg * R;
@@ -226,7 +228,7 @@ __global__ __launch_bounds__(NT) void pack_nmajor_vec_kernel(const T *__restrict
 int64_t pack_workgroups(int64_t elem_bytes, int64_t batch, int64_t rows, int64_t K, int kmajor) {
     const int64_t kw = (K + 31) / 32, ngroups = (kw + 3) / 4, R = 8 / elem_bytes;
     if (kmajor) return (batch * rows * kw + NT - 1) / NT;
-    if (rows % R == 0) return batch * ((ngroups + 3) / 4) * ((rows / R + 63) / 64);
+    if (rows % R == 0) return batch * ((ngroups + VW - 1) / VW) * ((rows / R + 63) / 64);
     return (batch * ngroups * rows + NT - 1) / NT;
 }
 
@@ -240,8 +242,8 @@ hipError_t launch_typed(const void *src, int il, int64_t batch, int64_t rows, in
         if (il) hipLaunchKernelGGL((pack_kmajor_kernel<T, 1>), grid, dim3(NT), 0, stream, s, dst, batch, rows, K, kw);
         else    hipLaunchKernelGGL((pack_kmajor_kernel<T, 0>), grid, dim3(NT), 0, stream, s, dst, batch, rows, K, kw);
     } else if (rows % (8 / (int64_t)sizeof(T)) == 0) {
-        if (il) hipLaunchKernelGGL((pack_nmajor_vec_kernel<T, 1>), grid, dim3(NT), 0, stream, s, dst, batch, rows, K, kw);
-        else    hipLaunchKernelGGL((pack_nmajor_vec_kernel<T, 0>), grid, dim3(NT), 0, stream, s, dst, batch, rows, K, kw);
+        if (il) hipLaunchKernelGGL((pack_nmajor_vec_kernel<T, 1>), grid, dim3(VNT), 0, stream, s, dst, batch, rows, K, kw);
+        else    hipLaunchKernelGGL((pack_nmajor_vec_kernel<T, 0>), grid, dim3(VNT), 0, stream, s, dst, batch, rows, K, kw);
     } else {
         const int vec = (kw % 4) == 0;
         if (il) hipLaunchKernelGGL((pack_nmajor_kernel<T, 1>), grid, dim3(NT), 0, stream, s, dst, batch, rows, K, kw, vec);
