@@ -235,6 +235,42 @@ def bench_c2(steps, warmup):
     return W, X, info, ms, tops, spread
 
 
+def bench_c1_latency(launches=200):
+    """The small plain-fp16 case (4 x 128 x 64 x 512): one launch is far too
+    short to fill the GPU, so what counts is latency.  Per launch: eager
+    launches back to back (host enqueue included), and the same launches
+    captured once in a HIP graph and replayed (one graph launch per
+    `launches` products)."""
+    import torch
+    import paper_2505_03269_amd as tcbf
+    import workloads as wl
+    cfg = wl.CONFIGS[1]
+    chans = [wl.c1_channel(c) for c in range(cfg["batch"])]
+    W = np.stack([w for w, _ in chans])
+    X = np.stack([x for _, x in chans])
+    plan = tcbf.Plan(cfg["batch"], cfg["M"], cfg["N"], cfg["K"], tcbf.F16)
+    A, B = torch.from_numpy(W).to("cuda:0"), torch.from_numpy(X).to("cuda:0")
+    C = plan.empty_output()
+    eager = time_launches(lambda: plan.execute(A, B, C), launches, 10)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        plan.execute(A, B, C)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=s):
+            for _ in range(launches):
+                plan.execute(A, B, C)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = time_launches(g.replay, 5, 2) / launches
+    ops = plan.info()["useful_ops"]
+    return {"workload": "plain-fp16 latency: batch=4 M=128 K=64 N=512", "kernel": plan.info()["kernel_name"],
+            "value": round(graph * 1e3, 2), "unit": "us per product (graph replay)", "higher_is_better": False,
+            "eager_us_per_launch": round(eager * 1e3, 2), "graph_us_per_product": round(graph * 1e3, 2),
+            "tops_graph": round(ops / (graph * 1e-3) / 1e12, 2), "launches_per_graph": launches}
+
+
 def bench_secondary(steps, serving=True, copy_gbs=None):
     """1-bit config (both variants), ultrasound-shaped fp16, sign packing."""
     import torch
@@ -242,6 +278,7 @@ def bench_secondary(steps, serving=True, copy_gbs=None):
     import workloads as wl
     out = []
     st = max(3, steps // 4)
+    out.append(bench_c1_latency())
     # 1-bit: 64 x 2048 x 8192 x 8192 from random words
     cfg = wl.CONFIGS[3]
     Wp, Xp = wl.generate_c3()
