@@ -58,10 +58,15 @@ typedef enum tcbf_dtype {
 
 /* Complex storage.  PLANAR keeps a real plane then an imaginary plane for each
  * batch entry; INTERLEAVED stores (re, im) pairs (the "usual interleaved
- * format" of Sec. VI). */
+ * format" of Sec. VI).  BLOCKED is a planar weight layout tiled along the
+ * receivers (Sec. III: the product kernel takes its inputs tiled in device
+ * memory, prepared by a separate transpose kernel; Sec. V-A: for the model
+ * matrix this is done once, before the data stream); see TCBF_F16 below and
+ * tcbf_block_weights. */
 typedef enum tcbf_layout {
     TCBF_PLANAR = 0,
-    TCBF_INTERLEAVED = 1
+    TCBF_INTERLEAVED = 1,
+    TCBF_BLOCKED = 2
 } tcbf_layout;
 
 /* Element type of a source array for tcbf_pack1bit. */
@@ -77,6 +82,14 @@ typedef enum tcbf_src_type {
  * TCBF_F16 buffer layouts (fp16 = IEEE binary16, fp32 = IEEE binary32):
  *   A = W   planar      [batch][2][M][K]   K contiguous
  *           interleaved [batch][M][K][2]
+ *           blocked     [batch][2][Kb][M][32], Kb = ceil(K/32): receiver k of
+ *                       beam m in block k/32, position k%32 (each block holds
+ *                       all M beams x 32 receivers, 64 bytes per beam);
+ *                       entries at k >= K must be zero (tcbf_block_weights
+ *                       writes them so).  A layout only; needs b_layout
+ *                       TCBF_PLANAR and N a multiple of 8 (any K); variants
+ *                       0 (default), 2, 5, 6.  Results are bitwise identical
+ *                       to the planar layout's.
  *   B = X   planar      [batch][2][K][N]   N contiguous
  *           interleaved [batch][K][N][2]
  *   C = out planar      [batch][2][M][N]   fp32
@@ -164,6 +177,23 @@ tcbf_status tcbf_plan(const tcbf_plan_desc *desc, tcbf_plan_t *plan);
  */
 tcbf_status tcbf_execute(tcbf_plan_t plan, const void *A, const void *B, void *C,
                          const void *a_scale, const void *b_scale, void *stream);
+
+/*
+ * tcbf_block_weights -- repack fp16 weights into the TCBF_BLOCKED layout
+ * (Sec. III: the library's transpose kernel tiles the inputs in device memory;
+ * here, the receiver axis of W in blocks of 32).
+ *   src (device): fp16 W, planar [batch][2][M][K] (src_layout TCBF_PLANAR) or
+ *                 interleaved [batch][M][K][2] (TCBF_INTERLEAVED).
+ *   dst (device): fp16 [batch][2][ceil(K/32)][M][32]; receivers k >= K are
+ *                 written as +0.  Values are copied bit for bit.
+ * src and dst must be 16-byte aligned device pointers that do not overlap.
+ * Asynchronous on `stream`, allocation-free.  TCBF_ERROR_INVALID_VALUE for
+ * NULL or misaligned pointers, sizes below 1 or a src_layout other than
+ * TCBF_PLANAR / TCBF_INTERLEAVED; TCBF_ERROR_NOT_SUPPORTED for sizes whose
+ * launch would exceed 2^31 - 1 workgroups.
+ */
+tcbf_status tcbf_block_weights(const void *src, int32_t src_layout, int64_t batch, int64_t M,
+                               int64_t K, void *dst, void *stream);
 
 /*
  * tcbf_pack1bit -- sign-pack complex data for TCBF_INT1 (Sec. III kernels

@@ -12,8 +12,8 @@ import ctypes
 import os
 
 __all__ = [
-    "F16", "INT1", "F8_E4M3", "MXF8_E4M3", "PLANAR", "INTERLEAVED", "SRC_I8", "SRC_F16", "SRC_F32",
-    "TcbfError", "Plan", "pack1bit", "quantize_e4m3", "steering_weights", "group_execute", "peak_probe", "f8_kp", "mx_scale_pitch", "mx_scales_to_rows",
+    "F16", "INT1", "F8_E4M3", "MXF8_E4M3", "PLANAR", "INTERLEAVED", "BLOCKED", "SRC_I8", "SRC_F16", "SRC_F32",
+    "TcbfError", "Plan", "block_weights", "blocked_shape", "pack1bit", "quantize_e4m3", "steering_weights", "group_execute", "peak_probe", "f8_kp", "mx_scale_pitch", "mx_scales_to_rows",
     "mx_scales_from_rows", "lib",
     "status_string", "EXPORTS", "GROUP_MAX", "GROUP_WORKSPACE_BYTES",
 ]
@@ -22,11 +22,11 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtcbf.so")
 
 F16, INT1, F8_E4M3, MXF8_E4M3 = 0, 1, 2, 3
-PLANAR, INTERLEAVED = 0, 1
+PLANAR, INTERLEAVED, BLOCKED = 0, 1, 2
 SRC_I8, SRC_F16, SRC_F32 = 0, 1, 2
 
 # every symbol include/tcbf.h declares
-EXPORTS = ("tcbf_plan", "tcbf_execute", "tcbf_pack1bit", "tcbf_quantize_e4m3", "tcbf_steering_weights",
+EXPORTS = ("tcbf_plan", "tcbf_execute", "tcbf_block_weights", "tcbf_pack1bit", "tcbf_quantize_e4m3", "tcbf_steering_weights",
            "tcbf_peak_probe", "tcbf_group_execute", "tcbf_plan_query", "tcbf_plan_destroy", "tcbf_status_string",
            "tcbf_version")
 GROUP_MAX = 32
@@ -85,6 +85,8 @@ def lib():
     L.tcbf_plan.restype = i32
     L.tcbf_execute.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.tcbf_execute.restype = i32
+    L.tcbf_block_weights.argtypes = [vp, i32, i64, i64, i64, vp, vp]
+    L.tcbf_block_weights.restype = i32
     L.tcbf_pack1bit.argtypes = [vp, i32, i32, i64, i64, i64, i32, vp, vp]
     L.tcbf_pack1bit.restype = i32
     L.tcbf_quantize_e4m3.argtypes = [vp, i32, i32, i64, i64, i64, i32, i32, vp, vp, vp]
@@ -215,6 +217,8 @@ class Plan:
             return (nb, 2, self.M, (self.K + 31) // 32)
         if _is_f8(self.dtype):
             return (nb, 2, self.M, f8_kp(self.K))
+        if self.a_layout == BLOCKED:
+            return blocked_shape(nb, self.M, self.K)
         return (nb, 2, self.M, self.K) if self.a_layout == PLANAR else (nb, self.M, self.K, 2)
 
     def shape_b(self):
@@ -272,6 +276,38 @@ class Plan:
         psb = _dev_ptr(b_scale, "b_scale") if b_scale is not None else None
         _check(lib().tcbf_execute(self._h, pa, pb, pc, psa, psb, _stream_handle(stream)), "tcbf_execute")
         return C
+
+
+def blocked_shape(batch, M, K):
+    """Shape of fp16 weights in the receiver-blocked layout: [batch, 2, ceil(K/32), M, 32]."""
+    return (int(batch), 2, (int(K) + 31) // 32, int(M), 32)
+
+
+def block_weights(W, layout=PLANAR, out=None, stream=None):
+    """Repack fp16 weights (planar [batch, 2, M, K] or interleaved
+    [batch, M, K, 2]) into the receiver-blocked layout (tcbf_block_weights);
+    returns (or fills) float16 [batch, 2, ceil(K/32), M, 32], zero past K."""
+    import torch
+    if W.dtype != torch.float16 or W.dim() != 4:
+        raise ValueError("W must be a 4-d float16 tensor")
+    if layout == PLANAR:
+        if W.shape[1] != 2:
+            raise ValueError("planar W needs a plane axis of 2")
+        batch, M, K = W.shape[0], W.shape[2], W.shape[3]
+    elif layout == INTERLEAVED:
+        if W.shape[3] != 2:
+            raise ValueError("interleaved W needs a trailing axis of 2")
+        batch, M, K = W.shape[0], W.shape[1], W.shape[2]
+    else:
+        raise ValueError("source layout must be PLANAR or INTERLEAVED")
+    shape = blocked_shape(batch, M, K)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float16, device=W.device)
+    if tuple(out.shape) != shape or out.dtype != torch.float16:
+        raise ValueError("out must be float16 %s" % (shape,))
+    _check(lib().tcbf_block_weights(_dev_ptr(W, "W"), int(layout), int(batch), int(M), int(K),
+                                    _dev_ptr(out, "out"), _stream_handle(stream)), "tcbf_block_weights")
+    return out
 
 
 def pack1bit(src, K=None, k_major=True, layout=PLANAR, out=None, stream=None):

@@ -19,7 +19,8 @@
 // Two kernels share the exact same MFMA sequence (same 16-receiver steps in
 // increasing order, same k assignment per lane, same operand order and
 // accumulation order), so they produce bitwise-identical results:
-//  * cgemm_f16_fast_kernel: planar W and X, K and N multiples of 8.  Global
+//  * cgemm_f16_fast_kernel: planar (or receiver-blocked) W, planar X, K and N
+//    multiples of 8 (any K with blocked W).  Global
 //    tiles go straight into LDS with buffer_load ... lds (no registers, no
 //    ALU work per stage) through a ring of NS stage buffers; out-of-range rows,
 //    columns and the K tail read as zero through the buffer descriptor's range
@@ -446,7 +447,11 @@ template <int WM, int BK, int NS> struct FastLds {
 // One output tile (64*WM beams x 128 samples of channel c at tile (tm, tn)):
 // the whole K loop and the epilogue.  Entered and left with the stage buffers
 // idle; the caller separates two tiles of one workgroup with a barrier.
-template <int WM, int BK, int NS, int CIL>
+// AB: W in the receiver-blocked layout (TCBF_BLOCKED: per plane, blocks of
+// 32 receivers, each block all M beams x 32 receivers), so a stage's W tile
+// is one contiguous run per plane and every load instruction reads whole
+// cache lines; with planar W each beam row contributes a 64-byte piece.
+template <int WM, int BK, int NS, int CIL, int AB>
 __device__ __forceinline__ void fast_tile(const uint16_t *__restrict__ A, const uint16_t *__restrict__ B,
                                           float *__restrict__ C, int M, int N, int K, int a_shared, int c, int tm,
                                           int tn, char *lds0, char *lds1, char *lds2, char *lds3, char *lds4,
@@ -465,9 +470,11 @@ __device__ __forceinline__ void fast_tile(const uint16_t *__restrict__ A, const 
     const int wm = wave >> 1, wn = wave & 1;
     const int hl = lane >> 5, l32 = lane & 31;
 
-    const uint16_t *Wc = A + (a_shared ? (int64_t)0 : (int64_t)c * 2 * M * K);
+    static_assert(!AB || BK == 32, "blocked W holds 32-receiver blocks");
+    const int KW = AB ? (K + 31) / 32 * 32 : K;  // receivers per W row as stored (blocked: padded)
+    const uint16_t *Wc = A + (a_shared ? (int64_t)0 : (int64_t)c * 2 * M * KW);
     const uint16_t *Xc = B + (int64_t)c * 2 * K * N;
-    const __amdgpu_buffer_rsrc_t rw = __builtin_amdgcn_make_buffer_rsrc((void *)Wc, 0, 4 * M * K, RSRC_FLAGS);
+    const __amdgpu_buffer_rsrc_t rw = __builtin_amdgcn_make_buffer_rsrc((void *)Wc, 0, 4 * M * KW, RSRC_FLAGS);
     const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc((void *)Xc, 0, 4 * K * N, RSRC_FLAGS);
 
     // The 16-byte chunks this lane moves into LDS per stage.  A wave load
@@ -486,7 +493,8 @@ __device__ __forceinline__ void fast_tile(const uint16_t *__restrict__ A, const 
         const int ch = (s % G::WCH) ^ G::swzW(m);
         ka = ch * 8;
         am = m;
-        va = (uint32_t)(((p * M + m0 + m) * K + ch * 8) * 2);
+        va = AB ? (uint32_t)(((p * (KW / 32)) * M + m0 + m) * 64 + ch * 16)
+                : (uint32_t)(((p * M + m0 + m) * K + ch * 8) * 2);
     }
     {
         const int s = wave * XPW * 64 + lane;
@@ -526,8 +534,10 @@ __device__ __forceinline__ void fast_tile(const uint16_t *__restrict__ A, const 
             uint32_t off = va;
             if (!rows_full && m0 + am + q * WROWS >= M) off = OOB;  // beams past M
             if (tail && k0 + ka >= K) off = OOB;                    // receivers past K
+            // uniform part: the stage's receiver block and this piece's rows
+            const int so = AB ? (k0 / 32) * M * 64 + q * WROWS * 64 : k0 * 2 + q * WROWS * K * 2;
             __builtin_amdgcn_raw_ptr_buffer_load_lds(rw, (LDS_AS void *)(base + (wave * WPW + q) * 1024), 16,
-                                                     off, k0 * 2 + q * WROWS * K * 2, 0, 0);
+                                                     off, so, 0, 0);
         }
 #pragma unroll
         for (int q = 0; q < XPW; ++q) {
@@ -613,7 +623,7 @@ __device__ __forceinline__ void fast_tile(const uint16_t *__restrict__ A, const 
     store_tile_staged<WM, CIL>(acc, row_ptr, C + (int64_t)c * 2 * M * N, M, N, m0, n0, wave, lane);
 }
 
-template <int WM, int BK, int NS, int CIL>
+template <int WM, int BK, int NS, int CIL, int AB>
 __global__ __launch_bounds__(128 * WM, WM == 2 ? 2 : 1) void cgemm_f16_fast_kernel(
     const uint16_t *__restrict__ A, const uint16_t *__restrict__ B, float *__restrict__ C,
     int M, int N, int K, int a_shared, int tiles_m, int tiles_n, int nblocks) {
@@ -624,7 +634,7 @@ __global__ __launch_bounds__(128 * WM, WM == 2 ? 2 : 1) void cgemm_f16_fast_kern
     const int rem = t - c * per_c;
     int tm, tn;
     tile_coords(rem, tiles_m, tiles_n, tm, tn);
-    fast_tile<WM, BK, NS, CIL>(A, B, C, M, N, K, a_shared, c, tm, tn, lds0, lds1, lds2, lds3, lds4, lds5);
+    fast_tile<WM, BK, NS, CIL, AB>(A, B, C, M, N, K, a_shared, c, tm, tn, lds0, lds1, lds2, lds3, lds4, lds5);
 }
 
 // ===========================================================================
@@ -673,7 +683,7 @@ __global__ __launch_bounds__(256, 2) void cgemm_f16_group_kernel(const GroupArgs
         const int rem = local - c * per_c;
         int tm, tn;
         tile_coords(rem, q.tiles_m, q.tiles_n, tm, tn);
-        fast_tile<2, 32, 2, CIL>(q.A, q.B, q.C, q.M, q.N, q.K, q.a_shared, c, tm, tn, lds0, lds1, lds2, lds3, lds4,
+        fast_tile<2, 32, 2, CIL, 0>(q.A, q.B, q.C, q.M, q.N, q.K, q.a_shared, c, tm, tn, lds0, lds1, lds2, lds3, lds4,
                                  lds5);
         // next_tile is rewritten only after the tile's own barriers, which
         // every wave passes after reading it
@@ -717,34 +727,50 @@ FastShape fast_shape(int v) {
     }
 }
 
-FastFn fast_fn(int v, bool cil) {
+template <int AB> FastFn fast_fn_of(int v, bool cil) {
     switch (v) {
-    case 2: return cil ? cgemm_f16_fast_kernel<2, 32, 2, 1> : cgemm_f16_fast_kernel<2, 32, 2, 0>;
-    case 3: return cil ? cgemm_f16_fast_kernel<2, 16, 4, 1> : cgemm_f16_fast_kernel<2, 16, 4, 0>;
-    case 4: return cil ? cgemm_f16_fast_kernel<2, 16, 5, 1> : cgemm_f16_fast_kernel<2, 16, 5, 0>;
-    case 5: return cil ? cgemm_f16_fast_kernel<2, 32, 3, 1> : cgemm_f16_fast_kernel<2, 32, 3, 0>;
-    case 6: return cil ? cgemm_f16_fast_kernel<4, 32, 3, 1> : cgemm_f16_fast_kernel<4, 32, 3, 0>;
-    default: return cil ? cgemm_f16_fast_kernel<4, 16, 6, 1> : cgemm_f16_fast_kernel<4, 16, 6, 0>;
+    case 2: return cil ? cgemm_f16_fast_kernel<2, 32, 2, 1, AB> : cgemm_f16_fast_kernel<2, 32, 2, 0, AB>;
+    case 5: return cil ? cgemm_f16_fast_kernel<2, 32, 3, 1, AB> : cgemm_f16_fast_kernel<2, 32, 3, 0, AB>;
+    case 6: return cil ? cgemm_f16_fast_kernel<4, 32, 3, 1, AB> : cgemm_f16_fast_kernel<4, 32, 3, 0, AB>;
     }
+    return nullptr;
+}
+
+FastFn fast_fn(int v, bool cil, bool ab) {
+    if (ab) return fast_fn_of<1>(v, cil);
+    switch (v) {
+    case 3: return cil ? cgemm_f16_fast_kernel<2, 16, 4, 1, 0> : cgemm_f16_fast_kernel<2, 16, 4, 0, 0>;
+    case 4: return cil ? cgemm_f16_fast_kernel<2, 16, 5, 1, 0> : cgemm_f16_fast_kernel<2, 16, 5, 0, 0>;
+    case 7: return cil ? cgemm_f16_fast_kernel<4, 16, 6, 1, 0> : cgemm_f16_fast_kernel<4, 16, 6, 0, 0>;
+    }
+    return fast_fn_of<0>(v, cil);
 }
 
 }  // namespace
 
-// Variant 1: generic kernel.  Variants 2..: fast kernel (planar W and X, K and
-// N multiples of 8, every per-channel operand and output below 2 GiB so 32-bit
-// buffer offsets reach it).
+// Variant 1: generic kernel.  Variants 2..: fast kernel (planar X, N a
+// multiple of 8; planar W with K a multiple of 8, or blocked W with any K;
+// every per-channel operand and output below 2 GiB so 32-bit buffer offsets
+// reach it).  Blocked W: only the fast kernel, variants with 32 receivers per
+// stage (2, 5, 6).
 static bool fast_ok(const Problem &p) {
     const int64_t lim = (int64_t)1 << 31;
-    return p.a_layout == TCBF_PLANAR && p.b_layout == TCBF_PLANAR && p.K % 8 == 0 && p.N % 8 == 0 &&
-           4 * p.M * p.K < lim && 4 * p.K * p.N < lim && 8 * p.M * p.N < lim && p.M < lim && p.N < lim &&
+    const bool ab = p.a_layout == TCBF_BLOCKED;
+    const int64_t kw = ab ? (p.K + 31) / 32 * 32 : p.K;
+    return (ab || (p.a_layout == TCBF_PLANAR && p.K % 8 == 0)) && p.b_layout == TCBF_PLANAR && p.N % 8 == 0 &&
+           4 * p.M * kw < lim && 4 * p.K * p.N < lim && 8 * p.M * p.N < lim && p.M < lim && p.N < lim &&
            p.batch * ((p.M + BM - 1) / BM) * ((p.N + BN - 1) / BN) < lim;
 }
 
+static bool reads_blocked(int v) { return v == 2 || v == 5 || v == 6; }
+
 bool f16_select(const Problem &p, int forced_variant, F16Config *cfg) {
+    const bool ab = p.a_layout == TCBF_BLOCKED;
     int v = forced_variant;
     if (v == 0) v = fast_ok(p) ? kDefaultFast : 1;
     if (v < 1 || v >= kFirstFast + kNumFast) return false;
     if (v >= kFirstFast && !fast_ok(p)) return false;
+    if (ab && !reads_blocked(v)) return false;
     cfg->variant = v;
     cfg->tile_m = v >= kFirstFast ? 64 * fast_shape(v).wm : BM;
     cfg->tile_n = BN;
@@ -773,7 +799,7 @@ hipError_t f16_launch(const Problem &p, const F16Config &cfg, const void *A, con
     int tiles_n = (int)((p.N + BN - 1) / BN);
     int64_t nblocks = p.batch * tiles_m * tiles_n;
     if (cfg.variant >= kFirstFast) {
-        FastFn fn = fast_fn(cfg.variant, p.c_layout == TCBF_INTERLEAVED);
+        FastFn fn = fast_fn(cfg.variant, p.c_layout == TCBF_INTERLEAVED, p.a_layout == TCBF_BLOCKED);
         hipLaunchKernelGGL(fn, dim3((uint32_t)nblocks), dim3(cfg.threads), 0, stream, (const uint16_t *)A,
                            (const uint16_t *)B, (float *)C, (int)p.M, (int)p.N, (int)p.K, p.a_shared,
                            tiles_m, tiles_n, (int)nblocks);
@@ -787,7 +813,7 @@ hipError_t f16_launch(const Problem &p, const F16Config &cfg, const void *A, con
     return hipGetLastError();
 }
 
-bool f16_group_problem_ok(const Problem &p) { return fast_ok(p); }
+bool f16_group_problem_ok(const Problem &p) { return p.a_layout == TCBF_PLANAR && fast_ok(p); }
 
 int64_t f16_group_tiles(const Problem &p) { return p.batch * ((p.M + BM - 1) / BM) * ((p.N + BN - 1) / BN); }
 

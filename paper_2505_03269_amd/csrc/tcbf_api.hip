@@ -57,12 +57,14 @@ tcbf_status current_device_is(int device) {
 tcbf_status validate_desc(const tcbf_plan_desc *d) {
     if (d->struct_size < kDescV1) return TCBF_ERROR_INVALID_VALUE;
     if (d->batch < 1 || d->M < 1 || d->N < 1 || d->K < 1) return TCBF_ERROR_INVALID_VALUE;
-    if (!is_layout(d->a_layout) || !is_layout(d->b_layout) || !is_layout(d->c_layout))
-        return TCBF_ERROR_INVALID_VALUE;
+    // the receiver-blocked layout is a weight (A) layout of the fp16 mode only
+    const bool a_ok = is_layout(d->a_layout) || (d->a_layout == TCBF_BLOCKED && d->dtype == TCBF_F16);
+    if (!a_ok || !is_layout(d->b_layout) || !is_layout(d->c_layout)) return TCBF_ERROR_INVALID_VALUE;
     if (d->variant < 0) return TCBF_ERROR_INVALID_VALUE;
     if (d->dtype == TCBF_F16) {
         // every per-channel plane must be indexable with 32-bit element counts
-        if (2 * d->M * d->K >= kMaxIndex || 2 * d->K * d->N >= kMaxIndex || 2 * d->M * d->N >= kMaxIndex)
+        const int64_t kw = d->a_layout == TCBF_BLOCKED ? (d->K + 31) / 32 * 32 : d->K;
+        if (2 * d->M * kw >= kMaxIndex || 2 * d->K * d->N >= kMaxIndex || 2 * d->M * d->N >= kMaxIndex)
             return TCBF_ERROR_NOT_SUPPORTED;
     } else if (d->dtype == TCBF_INT1) {
         if (d->a_layout != TCBF_PLANAR || d->b_layout != TCBF_PLANAR) return TCBF_ERROR_INVALID_VALUE;
@@ -209,6 +211,18 @@ tcbf_status tcbf_execute(tcbf_plan_t plan, const void *A, const void *B, void *C
         e = tcbf::int1_launch(plan->prob, plan->int1, (const uint32_t *)A, (const uint32_t *)B, (int32_t *)C,
                               (hipStream_t)stream);
     }
+    return e == hipSuccess ? TCBF_SUCCESS : TCBF_ERROR_DEVICE;
+}
+
+tcbf_status tcbf_block_weights(const void *src, int32_t src_layout, int64_t batch, int64_t M, int64_t K, void *dst,
+                               void *stream) {
+    if (src == nullptr || dst == nullptr) return TCBF_ERROR_INVALID_VALUE;
+    if (!is_layout(src_layout)) return TCBF_ERROR_INVALID_VALUE;
+    if (batch < 1 || M < 1 || K < 1) return TCBF_ERROR_INVALID_VALUE;
+    if (!aligned16(src) || !aligned16(dst)) return TCBF_ERROR_INVALID_VALUE;
+    if ((double)batch * (double)M * (double)(K + 31) >= 0x1p62) return TCBF_ERROR_NOT_SUPPORTED;
+    if (tcbf::block_weights_workgroups(batch, M, K) >= kMaxIndex) return TCBF_ERROR_NOT_SUPPORTED;
+    hipError_t e = tcbf::block_weights_launch(src, src_layout, batch, M, K, dst, (hipStream_t)stream);
     return e == hipSuccess ? TCBF_SUCCESS : TCBF_ERROR_DEVICE;
 }
 

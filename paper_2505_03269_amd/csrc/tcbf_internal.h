@@ -86,6 +86,11 @@ hipError_t int1_group_launch(const Problem *probs, const void *const *A, const v
 hipError_t int1_launch(const Problem &p, const Int1Config &cfg, const uint32_t *A,
                        const uint32_t *B, int32_t *C, hipStream_t stream);
 
+// Weight repack into the receiver-blocked layout (TCBF_BLOCKED).
+int64_t block_weights_workgroups(int64_t batch, int64_t M, int64_t K);
+hipError_t block_weights_launch(const void *src, int src_layout, int64_t batch, int64_t M, int64_t K, void *dst,
+                                hipStream_t stream);
+
 // Sign packing.
 // Workgroups the packing launch uses (what the argument checks bound).
 int64_t pack1bit_workgroups(int src_type, int64_t batch, int64_t rows, int64_t K, int src_k_major);

@@ -62,7 +62,13 @@ def _plan_status(**kw):
 
 @pytest.mark.parametrize("bad", [
     dict(struct_size=4), dict(batch=0), dict(M=0), dict(N=-1), dict(K=0), dict(dtype=7),
-    dict(a_layout=2), dict(b_layout=-1), dict(c_layout=5), dict(variant=-1), dict(variant=9),
+    dict(a_layout=3), dict(b_layout=-1), dict(c_layout=5), dict(variant=-1), dict(variant=9),
+    # the receiver-blocked layout: fp16 weights only, fast kernel with 32 receivers per stage
+    dict(b_layout=tcbf.BLOCKED), dict(c_layout=tcbf.BLOCKED), dict(dtype=tcbf.INT1, a_layout=tcbf.BLOCKED),
+    dict(dtype=tcbf.F8_E4M3, a_layout=tcbf.BLOCKED), dict(dtype=tcbf.MXF8_E4M3, a_layout=tcbf.BLOCKED),
+    dict(a_layout=tcbf.BLOCKED, b_layout=tcbf.INTERLEAVED), dict(a_layout=tcbf.BLOCKED, N=12),
+    dict(a_layout=tcbf.BLOCKED, variant=1), dict(a_layout=tcbf.BLOCKED, variant=3),
+    dict(a_layout=tcbf.BLOCKED, variant=4), dict(a_layout=tcbf.BLOCKED, variant=7),
     dict(dtype=tcbf.INT1, a_layout=tcbf.INTERLEAVED), dict(dtype=tcbf.INT1, b_layout=tcbf.INTERLEAVED),
     dict(dtype=tcbf.INT1, variant=7),
     dict(dtype=tcbf.F8_E4M3, a_layout=tcbf.INTERLEAVED), dict(dtype=tcbf.MXF8_E4M3, b_layout=tcbf.INTERLEAVED),
@@ -75,6 +81,8 @@ def test_bad_descriptors_rejected_without_device(bad):
 
 def test_oversized_rejected():
     assert _plan_status(M=1 << 20, K=1 << 12) == 2
+    # blocked weights are padded to whole 32-receiver blocks: 2*M*32*ceil(K/32) elements
+    assert _plan_status(a_layout=tcbf.BLOCKED, M=1 << 15, K=(1 << 15) - 31) == 2
     assert _plan_status(dtype=tcbf.INT1, K=(1 << 26) + 1) == 2
     assert _plan_status(dtype=tcbf.F8_E4M3, M=1 << 14, K=1 << 16) == 2   # 2*M*Kp bytes
     assert _plan_status(dtype=tcbf.MXF8_E4M3, M=1 << 14, N=1 << 14) == 2  # 8*M*N bytes
@@ -89,6 +97,28 @@ def test_null_arguments():
     assert L.tcbf_plan_destroy(None) == 0
     assert L.tcbf_pack1bit(None, 0, 0, 1, 1, 1, 1, None, None) == 1
     assert L.tcbf_quantize_e4m3(None, 0, 0, 1, 1, 1, 1, 0, None, None, None) == 1
+    assert L.tcbf_block_weights(None, 0, 1, 1, 1, None, None) == 1
+
+
+def test_block_weights_argument_checks():
+    L = tcbf.lib()
+    buf = ctypes.create_string_buffer(256)
+    addr = (ctypes.addressof(buf) + 15) & ~15
+    p = ctypes.c_void_p(addr)
+    assert L.tcbf_block_weights(p, tcbf.BLOCKED, 1, 1, 1, p, None) == 1   # blocked source
+    assert L.tcbf_block_weights(p, -1, 1, 1, 1, p, None) == 1            # bad layout
+    assert L.tcbf_block_weights(p, 0, 0, 1, 1, p, None) == 1             # batch 0
+    assert L.tcbf_block_weights(p, 0, 1, 0, 1, p, None) == 1             # M 0
+    assert L.tcbf_block_weights(p, 0, 1, 1, 0, p, None) == 1             # K 0
+    q = ctypes.c_void_p(addr + 8)
+    assert L.tcbf_block_weights(p, 0, 1, 1, 1, q, None) == 1             # misaligned dst
+    assert L.tcbf_block_weights(p, 0, 1 << 40, 1 << 20, 1 << 10, p, None) == 2   # too large
+
+
+def test_blocked_shape():
+    assert tcbf.blocked_shape(3, 100, 1) == (3, 2, 1, 100, 32)
+    assert tcbf.blocked_shape(1, 8, 64) == (1, 2, 2, 8, 32)
+    assert tcbf.blocked_shape(2, 8, 65) == (2, 2, 3, 8, 32)
 
 
 def test_pack_argument_checks():
