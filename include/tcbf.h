@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define TCBF_VERSION 1
+#define TCBF_VERSION 2
 
 typedef enum tcbf_status {
     TCBF_SUCCESS = 0,
@@ -104,10 +104,16 @@ typedef enum tcbf_src_type {
  *
  * TCBF_F8_E4M3 / TCBF_MXF8_E4M3 layouts (as tcbf_quantize_e4m3 writes them;
  * codes are OCP FP8 E4M3 bytes; Kp = 32 * ceil(K / 32)):
- *   A = W   [batch][2][M][Kp]  receivers contiguous, bytes past K zero
- *   B = X   [batch][2][N][Kp]  packed along K for each sample n
+ *   A = W   planar  [batch][2][M][Kp]  receivers contiguous, bytes past K zero
+ *           blocked [batch][2][Kb][M][64], Kb = ceil(Kp / 64): receiver k of
+ *                   row m in block k/64, position k%64 (each block all M rows
+ *                   x 64 receivers); bytes past Kp are never read
+ *   B = X   planar  [batch][2][N][Kp]  packed along K for each sample n
+ *           blocked [batch][2][Kb][N][64]
  *   C = out planar [batch][2][M][N] or interleaved [batch][M][N][2], fp32
- *   a_layout and b_layout must be TCBF_PLANAR; N must be a multiple of 4.
+ *   a_layout and b_layout both TCBF_PLANAR or both TCBF_BLOCKED (results
+ *   bitwise identical; blocked reads whole cache lines per stage); N must be
+ *   a multiple of 4.
  *   Scales (tcbf_execute's a_scale, b_scale):
  *     TCBF_F8_E4M3:   fp32 a_scale [batch][M] (or [M] when a_shared), fp32
  *                     b_scale [batch][N]; out = a_scale[m] * b_scale[n] *
@@ -224,8 +230,10 @@ tcbf_status tcbf_pack1bit(const void *src, int32_t src_type, int32_t src_layout,
  *                amax <= 448 * 2^e over the block (clamped to [-127, 127],
  *                0 for an all-zero block)
  *   src (device), src_type, src_layout and src_k_major as for tcbf_pack1bit.
- *   dst (device): [batch][2][rows][Kp] bytes, Kp = 32 * ceil(K / 32), zero
- *   past K.  scales (device): block 0: fp32 [batch][rows]; block 32: uint8
+ *   dst (device), dst_layout TCBF_PLANAR: [batch][2][rows][Kp] bytes,
+ *   Kp = 32 * ceil(K / 32), zero past K; TCBF_BLOCKED: [batch][2][Kb][rows][64],
+ *   Kb = ceil(Kp / 64), receiver k of row r at [k / 64][r][k % 64], zero past
+ *   K (the whole last block written).  scales (device): block 0: fp32 [batch][rows]; block 32: uint8
  *   [batch][Ks / 16][rows][16], Ks = 16 * ceil(Kp / 512), block j of row r
  *   at [j / 16][r][j % 16] (the padding codes j >= Kp / 32 are not written).
  * src, dst and scales must be 16-byte aligned device buffers that do not
@@ -233,7 +241,8 @@ tcbf_status tcbf_pack1bit(const void *src, int32_t src_type, int32_t src_layout,
  */
 tcbf_status tcbf_quantize_e4m3(const void *src, int32_t src_type, int32_t src_layout,
                                int64_t batch, int64_t rows, int64_t K, int32_t src_k_major,
-                               int32_t block, uint8_t *dst, void *scales, void *stream);
+                               int32_t block, int32_t dst_layout, uint8_t *dst, void *scales,
+                               void *stream);
 
 /*
  * tcbf_steering_weights -- the weights W of Eq. 3 from array geometry, with

@@ -13,7 +13,7 @@ import os
 
 __all__ = [
     "F16", "INT1", "F8_E4M3", "MXF8_E4M3", "PLANAR", "INTERLEAVED", "BLOCKED", "SRC_I8", "SRC_F16", "SRC_F32",
-    "TcbfError", "Plan", "block_weights", "blocked_shape", "pack1bit", "quantize_e4m3", "steering_weights", "group_execute", "peak_probe", "f8_kp", "mx_scale_pitch", "mx_scales_to_rows",
+    "TcbfError", "Plan", "block_weights", "blocked_shape", "f8_codes_shape", "pack1bit", "quantize_e4m3", "steering_weights", "group_execute", "peak_probe", "f8_kp", "mx_scale_pitch", "mx_scales_to_rows",
     "mx_scales_from_rows", "lib",
     "status_string", "EXPORTS", "GROUP_MAX", "GROUP_WORKSPACE_BYTES",
 ]
@@ -89,7 +89,7 @@ def lib():
     L.tcbf_block_weights.restype = i32
     L.tcbf_pack1bit.argtypes = [vp, i32, i32, i64, i64, i64, i32, vp, vp]
     L.tcbf_pack1bit.restype = i32
-    L.tcbf_quantize_e4m3.argtypes = [vp, i32, i32, i64, i64, i64, i32, i32, vp, vp, vp]
+    L.tcbf_quantize_e4m3.argtypes = [vp, i32, i32, i64, i64, i64, i32, i32, i32, vp, vp, vp]
     L.tcbf_quantize_e4m3.restype = i32
     L.tcbf_steering_weights.argtypes = [vp, vp, vp, ctypes.c_double, i64, i64, i64, i32, vp, vp]
     L.tcbf_steering_weights.restype = i32
@@ -216,7 +216,7 @@ class Plan:
         if self.dtype == INT1:
             return (nb, 2, self.M, (self.K + 31) // 32)
         if _is_f8(self.dtype):
-            return (nb, 2, self.M, f8_kp(self.K))
+            return f8_codes_shape(nb, self.M, self.K, self.a_layout)
         if self.a_layout == BLOCKED:
             return blocked_shape(nb, self.M, self.K)
         return (nb, 2, self.M, self.K) if self.a_layout == PLANAR else (nb, self.M, self.K, 2)
@@ -225,7 +225,7 @@ class Plan:
         if self.dtype == INT1:
             return (self.batch, 2, self.N, (self.K + 31) // 32)
         if _is_f8(self.dtype):
-            return (self.batch, 2, self.N, f8_kp(self.K))
+            return f8_codes_shape(self.batch, self.N, self.K, self.b_layout)
         return (self.batch, 2, self.K, self.N) if self.b_layout == PLANAR else (self.batch, self.K, self.N, 2)
 
     def shape_a_scale(self):
@@ -360,11 +360,23 @@ def _source_geometry(src, k_major, layout):
     return src.shape[0], rows, kk
 
 
-def quantize_e4m3(src, k_major=True, layout=PLANAR, block=0, out=None, scales=None, stream=None):
+def f8_codes_shape(batch, rows, K, out_layout=PLANAR):
+    """Shape of e4m3 codes: planar [batch, 2, rows, Kp] or receiver-blocked
+    [batch, 2, ceil(Kp/64), rows, 64], Kp = 32 * ceil(K/32)."""
+    kp = f8_kp(K)
+    if out_layout == BLOCKED:
+        return (int(batch), 2, (kp + 63) // 64, int(rows), 64)
+    return (int(batch), 2, int(rows), kp)
+
+
+def quantize_e4m3(src, k_major=True, layout=PLANAR, block=0, out=None, scales=None, stream=None,
+                  out_layout=PLANAR):
     """Quantise a device tensor (int8 / float16 / float32) to the FP8 operand form.
 
     Source orientation as for pack1bit.  Returns (codes, scales): uint8 codes
-    [batch, 2, rows, Kp] and fp32 scales [batch, rows] (block=0) or uint8 E8M0
+    (f8_codes_shape: [batch, 2, rows, Kp], or receiver-blocked
+    [batch, 2, ceil(Kp/64), rows, 64] with out_layout=BLOCKED) and fp32 scales
+    [batch, rows] (block=0) or uint8 E8M0
     codes in groups of 16 blocks [batch, Ks/16, rows, 16] (block=32; Ks =
     mx_scale_pitch(K); block j of row r at [j // 16, r, j % 16]; codes past
     Kp/32 not written).  mx_scales_to_rows turns them into [batch, rows, Kp/32].
@@ -374,22 +386,24 @@ def quantize_e4m3(src, k_major=True, layout=PLANAR, block=0, out=None, scales=No
     if src.dtype not in types:
         raise ValueError("unsupported source dtype %s" % src.dtype)
     batch, rows, kk = _source_geometry(src, k_major, layout)
-    kp = f8_kp(kk)
+    if out_layout not in (PLANAR, BLOCKED):
+        raise ValueError("out_layout must be PLANAR or BLOCKED")
+    cshape = f8_codes_shape(batch, rows, kk, out_layout)
     if out is None:
-        out = torch.empty((batch, 2, rows, kp), dtype=torch.uint8, device=src.device)
+        out = torch.empty(cshape, dtype=torch.uint8, device=src.device)
     if scales is None:
         if block == 0:
             scales = torch.empty((batch, rows), dtype=torch.float32, device=src.device)
         else:
             scales = torch.empty((batch, mx_scale_pitch(kk) // 16, rows, 16), dtype=torch.uint8, device=src.device)
-    if tuple(out.shape) != (batch, 2, rows, kp) or out.dtype != torch.uint8:
-        raise ValueError("out must be uint8 [batch, 2, rows, Kp]")
+    if tuple(out.shape) != cshape or out.dtype != torch.uint8:
+        raise ValueError("out must be uint8 %s" % (cshape,))
     want = (((batch, rows), torch.float32) if block == 0
             else ((batch, mx_scale_pitch(kk) // 16, rows, 16), torch.uint8))
     if tuple(scales.shape) != want[0] or scales.dtype != want[1]:
         raise ValueError("scales must be %s %s" % (want[1], want[0]))
     _check(lib().tcbf_quantize_e4m3(_dev_ptr(src, "src"), types[src.dtype], int(layout), int(batch), int(rows),
-                                    int(kk), int(bool(k_major)), int(block), _dev_ptr(out, "out"),
+                                    int(kk), int(bool(k_major)), int(block), int(out_layout), _dev_ptr(out, "out"),
                                     _dev_ptr(scales, "scales"), _stream_handle(stream)),
            "tcbf_quantize_e4m3")
     return out, scales

@@ -3,7 +3,8 @@
 // The 8-bit path is the library's extension of Sec. III-B (the paper names
 // 8-bit floats as future work in Sec. VI).  Inputs are e4m3 codes as the
 // quantiser writes them: W [batch][2][M][Kp] and X [batch][2][N][Kp], both
-// receiver-contiguous with Kp = 32 * ceil(K / 32) and zero padding.  The sum
+// receiver-contiguous with Kp = 32 * ceil(K / 32) and zero padding, or both
+// receiver-blocked, [batch][2][ceil(Kp / 64)][rows][64].  The sum
 // over receivers is exact-product, fp32-accumulated:
 //   per-row scales (TCBF_F8_E4M3): C[m][n] = a_scale[m] * b_scale[n] * sum_k W8 X8
 //     -- the scales factor out of the sum, so they are applied in the epilogue;
@@ -85,8 +86,12 @@ __device__ __forceinline__ f32x16 mma(const i32x8 &x, const i32x8 &w, const f32x
     __shared__ __attribute__((aligned((NS) > 3 ? 1024 : 4))) char lds3[(NS) > 3 ? STAGE : 4];   \
     __shared__ __attribute__((aligned((MX) ? 1024 : 4))) char slabs[(MX) ? 2 * SLAB : 4];
 
-// One 128 x 128 output tile of channel c.
-template <int NS, int CIL, int MX>
+// One 128 x 128 output tile of channel c.  BL: both operands in the
+// receiver-blocked layout (TCBF_BLOCKED: per plane, blocks of 64 receivers,
+// each block all rows x 64 bytes), so a stage's tile of each operand is one
+// contiguous run per plane and every load instruction reads whole cache
+// lines; receiver-contiguous rows give 64-byte pieces instead.
+template <int NS, int CIL, int MX, int BL>
 __device__ __forceinline__ void f8_tile(const uint8_t *__restrict__ A, const uint8_t *__restrict__ B,
                                         float *__restrict__ C, const void *__restrict__ a_scale,
                                         const void *__restrict__ b_scale, int M, int N, int Kp, int a_shared,
@@ -103,10 +108,13 @@ __device__ __forceinline__ void f8_tile(const uint8_t *__restrict__ A, const uin
     const int hl = lane >> 5, l32 = lane & 31;
 
     const int cw = a_shared ? 0 : c;
-    const uint8_t *Wc = A + (int64_t)cw * 2 * M * Kp;
-    const uint8_t *Xc = B + (int64_t)c * 2 * N * Kp;
-    const __amdgpu_buffer_rsrc_t rw = __builtin_amdgcn_make_buffer_rsrc((void *)Wc, 0, 2 * M * Kp, RSRC_FLAGS);
-    const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc((void *)Xc, 0, 2 * N * Kp, RSRC_FLAGS);
+    const int KS = BL ? (Kp + BK - 1) / BK * BK : Kp;  // bytes per row as stored (blocked: whole blocks)
+    const uint8_t *Wc = A + (int64_t)cw * 2 * M * KS;
+    const uint8_t *Xc = B + (int64_t)c * 2 * N * KS;
+    const __amdgpu_buffer_rsrc_t rw = __builtin_amdgcn_make_buffer_rsrc((void *)Wc, 0, 2 * M * KS, RSRC_FLAGS);
+    const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc((void *)Xc, 0, 2 * N * KS, RSRC_FLAGS);
+    // row pitch inside a plane, and the uniform step from one stage to the next
+    const int pitch_w = BL ? BK : Kp, pitch_x = BL ? BK : Kp;
 
     // This lane's 16-byte chunk in each of the wave's loads.  Slot s of an
     // operand region (16 B each, lane order within a 1 KiB wave load) holds
@@ -119,8 +127,8 @@ __device__ __forceinline__ void f8_tile(const uint8_t *__restrict__ A, const uin
         const int p = s / (BM * 4);
         row0 = (s / 4) % BM;
         kc = ((s & 3) ^ swz(row0)) * 16;
-        plane_off_w = (uint32_t)(p * M) * Kp;
-        plane_off_x = (uint32_t)(p * N) * Kp;
+        plane_off_w = (uint32_t)(p * M) * KS;
+        plane_off_x = (uint32_t)(p * N) * KS;
     }
 
     // Fragment offsets within a stage (plane 0 of W; X adds REG, the
@@ -161,16 +169,17 @@ __device__ __forceinline__ void f8_tile(const uint8_t *__restrict__ A, const uin
 #pragma unroll
         for (int q = 0; q < PIECES_PER_WAVE; ++q) {
             const int r = row0 + q * PIECE_ROWS;
-            const uint32_t off = (kin && m0 + r < M) ? plane_off_w + (uint32_t)(m0 + r) * Kp + kc : OOB;
+            const uint32_t off = (kin && m0 + r < M) ? plane_off_w + (uint32_t)(m0 + r) * pitch_w + kc : OOB;
             __builtin_amdgcn_raw_ptr_buffer_load_lds(rw, (TCBF_LDS_AS void *)(base + (wave * PIECES_PER_WAVE + q) * 1024),
-                                                     16, off, k0, 0, 0);
+                                                     16, off, BL ? kt * M * BK : k0, 0, 0);
         }
 #pragma unroll
         for (int q = 0; q < PIECES_PER_WAVE; ++q) {
             const int r = row0 + q * PIECE_ROWS;
-            const uint32_t off = (kin && n0 + r < N) ? plane_off_x + (uint32_t)(n0 + r) * Kp + kc : OOB;
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(
-                rx, (TCBF_LDS_AS void *)(base + REG + (wave * PIECES_PER_WAVE + q) * 1024), 16, off, k0, 0, 0);
+            const uint32_t off = (kin && n0 + r < N) ? plane_off_x + (uint32_t)(n0 + r) * pitch_x + kc : OOB;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rx,
+                                                     (TCBF_LDS_AS void *)(base + REG + (wave * PIECES_PER_WAVE + q) * 1024),
+                                                     16, off, BL ? kt * N * BK : k0, 0, 0);
         }
         if (MX && kt % SLAB_STAGES == 0)
             __builtin_amdgcn_raw_ptr_buffer_load_lds(
@@ -292,7 +301,7 @@ __device__ __forceinline__ void f8_tile(const uint8_t *__restrict__ A, const uin
     store_tile_staged<2, CIL>(acc, row_ptr, C + (int64_t)c * 2 * M * N, M, N, m0, n0, wave, lane);
 }
 
-template <int NS, int CIL, int MX>
+template <int NS, int CIL, int MX, int BL>
 __global__ __launch_bounds__(NT, 2) void cgemm_f8_kernel(
     const uint8_t *__restrict__ A, const uint8_t *__restrict__ B, float *__restrict__ C,
     const void *__restrict__ a_scale, const void *__restrict__ b_scale, int M, int N, int Kp, int a_shared,
@@ -304,7 +313,8 @@ __global__ __launch_bounds__(NT, 2) void cgemm_f8_kernel(
     const int rem = t - c * per_c;
     int tm, tn;
     tile_coords(rem, tiles_m, tiles_n, tm, tn);
-    f8_tile<NS, CIL, MX>(A, B, C, a_scale, b_scale, M, N, Kp, a_shared, c, tm, tn, lds0, lds1, lds2, lds3, slabs);
+    f8_tile<NS, CIL, MX, BL>(A, B, C, a_scale, b_scale, M, N, Kp, a_shared, c, tm, tn, lds0, lds1, lds2, lds3,
+                             slabs);
 }
 
 // Grouped persistent launch: problems of different shapes (and their own
@@ -351,7 +361,7 @@ __global__ __launch_bounds__(NT, 2) void cgemm_f8_group_kernel(const F8GroupArgs
         const int rem = local - c * per_c;
         int tm, tn;
         tile_coords(rem, q.tiles_m, q.tiles_n, tm, tn);
-        f8_tile<2, CIL, MX>(q.A, q.B, q.C, q.a_scale, q.b_scale, q.M, q.N, q.Kp, q.a_shared, c, tm, tn, lds0, lds1,
+        f8_tile<2, CIL, MX, 0>(q.A, q.B, q.C, q.a_scale, q.b_scale, q.M, q.N, q.Kp, q.a_shared, c, tm, tn, lds0, lds1,
                             lds2, lds3, slabs);
         // next_tile is rewritten only after the tile's own barriers, which
         // every wave passes after reading it
@@ -363,14 +373,16 @@ __global__ void f8_group_reset_kernel(unsigned int *counter) { *counter = 0u; }
 typedef void (*F8Fn)(const uint8_t *, const uint8_t *, float *, const void *, const void *, int, int, int, int, int,
                      int, int);
 
-F8Fn f8_fn(int v, bool cil, bool mx) {
+template <int BL> F8Fn f8_fn_of(int v, bool cil, bool mx) {
     if (mx) {
-        if (v == 2) return cil ? cgemm_f8_kernel<3, 1, 1> : cgemm_f8_kernel<3, 0, 1>;
-        return cil ? cgemm_f8_kernel<2, 1, 1> : cgemm_f8_kernel<2, 0, 1>;
+        if (v == 2) return cil ? cgemm_f8_kernel<3, 1, 1, BL> : cgemm_f8_kernel<3, 0, 1, BL>;
+        return cil ? cgemm_f8_kernel<2, 1, 1, BL> : cgemm_f8_kernel<2, 0, 1, BL>;
     }
-    if (v == 2) return cil ? cgemm_f8_kernel<3, 1, 0> : cgemm_f8_kernel<3, 0, 0>;
-    return cil ? cgemm_f8_kernel<2, 1, 0> : cgemm_f8_kernel<2, 0, 0>;
+    if (v == 2) return cil ? cgemm_f8_kernel<3, 1, 0, BL> : cgemm_f8_kernel<3, 0, 0, BL>;
+    return cil ? cgemm_f8_kernel<2, 1, 0, BL> : cgemm_f8_kernel<2, 0, 0, BL>;
 }
+
+F8Fn f8_fn(int v, bool cil, bool mx, bool bl) { return bl ? f8_fn_of<1>(v, cil, mx) : f8_fn_of<0>(v, cil, mx); }
 
 constexpr int kNumVariants = 2;  // 1: two-stage ring (default), 2: three-stage ring
 
@@ -382,6 +394,8 @@ bool f8_select(const Problem &p, int forced_variant, F8Config *cfg) {
     int v = forced_variant == 0 ? 1 : forced_variant;
     if (v < 1 || v > kNumVariants) return false;
     if (p.N % 4 != 0) return false;
+    // both operands planar, or both receiver-blocked
+    if (p.a_layout != p.b_layout || (p.a_layout != TCBF_PLANAR && p.a_layout != TCBF_BLOCKED)) return false;
     cfg->variant = v;
     cfg->tile_m = BM;
     cfg->tile_n = BN;
@@ -401,7 +415,7 @@ hipError_t f8_launch(const Problem &p, const F8Config &cfg, bool mx, const void 
     const int tiles_m = (int)((p.M + BM - 1) / BM);
     const int tiles_n = (int)((p.N + BN - 1) / BN);
     const int64_t nblocks = p.batch * tiles_m * tiles_n;
-    F8Fn fn = f8_fn(cfg.variant, p.c_layout == TCBF_INTERLEAVED, mx);
+    F8Fn fn = f8_fn(cfg.variant, p.c_layout == TCBF_INTERLEAVED, mx, p.a_layout == TCBF_BLOCKED);
     hipLaunchKernelGGL(fn, dim3((uint32_t)nblocks), dim3(NT), 0, stream, (const uint8_t *)A, (const uint8_t *)B,
                        (float *)C, a_scale, b_scale, (int)p.M, (int)p.N, (int)f8_kp(p.K), p.a_shared, tiles_m,
                        tiles_n, (int)nblocks);

@@ -164,7 +164,10 @@ __global__ __launch_bounds__(NT) void row_scale_kernel(float *scales, int64_t n)
 
 // Quantise one tile.  MX == 0: row scales from the finished amax pass;
 // MX == 1: block exponents computed here (a tile holds two whole blocks).
-template <typename T, int IL, int KMAJ, int MX>
+// BL: codes written in the receiver-blocked layout [b][2][ceil(kp/64)][rows][64]
+// (one tile is one 64-receiver block of 64 rows: 4 KiB contiguous per plane);
+// bytes past kp in the last block are written as zero codes too.
+template <typename T, int IL, int KMAJ, int MX, int BL>
 __global__ __launch_bounds__(NT) void quantize_kernel(const T *__restrict__ src, uint8_t *__restrict__ dst,
                                                       void *__restrict__ scales, int64_t rows, int64_t K,
                                                       int64_t kp) {
@@ -237,21 +240,29 @@ __global__ __launch_bounds__(NT) void quantize_kernel(const T *__restrict__ src,
         const int c = t + h * NT;
         const int p = c >> 8, r = (c >> 2) & 63, piece = c & 3;
         const int64_t row = ti.r0 + r, k = ti.k0 + 16 * piece;
-        if (row < rows && k < kp) {
+        if (BL) {
+            static_assert(TK == 64, "one tile per 64-receiver block");
+            const int64_t nblk = (kp + 63) / 64;
+            if (row < rows) {
+                const uint4 v = *reinterpret_cast<const uint4 *>(&q[p][r][16 * piece]);
+                *reinterpret_cast<uint4 *>(dst + (((ti.b * 2 + p) * nblk + ti.k0 / 64) * rows + row) * 64 +
+                                           16 * piece) = v;
+            }
+        } else if (row < rows && k < kp) {
             const uint4 v = *reinterpret_cast<const uint4 *>(&q[p][r][16 * piece]);
             *reinterpret_cast<uint4 *>(dst + ((ti.b * 2 + p) * rows + row) * kp + k) = v;
         }
     }
 }
 
-template <typename T, int IL, int KMAJ>
+template <typename T, int IL, int KMAJ, int BL>
 hipError_t quantize_typed(const void *src, int64_t batch, int64_t rows, int64_t K, int block, uint8_t *dst,
                           void *scales, hipStream_t stream) {
     const int64_t kp = (K + 31) / 32 * 32;
     const int64_t tiles = batch * ((rows + TR - 1) / TR) * ((kp + TK - 1) / TK);
     const T *s = (const T *)src;
     if (block == 32) {
-        hipLaunchKernelGGL((quantize_kernel<T, IL, KMAJ, 1>), dim3((uint32_t)tiles), dim3(NT), 0, stream, s, dst,
+        hipLaunchKernelGGL((quantize_kernel<T, IL, KMAJ, 1, BL>), dim3((uint32_t)tiles), dim3(NT), 0, stream, s, dst,
                            scales, rows, K, kp);
         return hipGetLastError();
     }
@@ -260,19 +271,30 @@ hipError_t quantize_typed(const void *src, int64_t batch, int64_t rows, int64_t 
     hipLaunchKernelGGL(fill_zero_kernel, dim3(nb), dim3(NT), 0, stream, (uint32_t *)scales, n);
     hipLaunchKernelGGL((row_amax_kernel<T, IL, KMAJ>), dim3((uint32_t)tiles), dim3(NT), 0, stream, s,
                        (uint32_t *)scales, rows, K, kp);
-    hipLaunchKernelGGL((quantize_kernel<T, IL, KMAJ, 0>), dim3((uint32_t)tiles), dim3(NT), 0, stream, s, dst,
+    hipLaunchKernelGGL((quantize_kernel<T, IL, KMAJ, 0, BL>), dim3((uint32_t)tiles), dim3(NT), 0, stream, s, dst,
                        scales, rows, K, kp);
     hipLaunchKernelGGL(row_scale_kernel, dim3(nb), dim3(NT), 0, stream, (float *)scales, n);
     return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, int BL>
 hipError_t quantize_layout(const void *src, int il, int kmaj, int64_t batch, int64_t rows, int64_t K, int block,
                            uint8_t *dst, void *scales, hipStream_t stream) {
-    if (il) return kmaj ? quantize_typed<T, 1, 1>(src, batch, rows, K, block, dst, scales, stream)
-                        : quantize_typed<T, 1, 0>(src, batch, rows, K, block, dst, scales, stream);
-    return kmaj ? quantize_typed<T, 0, 1>(src, batch, rows, K, block, dst, scales, stream)
-                : quantize_typed<T, 0, 0>(src, batch, rows, K, block, dst, scales, stream);
+    if (il) return kmaj ? quantize_typed<T, 1, 1, BL>(src, batch, rows, K, block, dst, scales, stream)
+                        : quantize_typed<T, 1, 0, BL>(src, batch, rows, K, block, dst, scales, stream);
+    return kmaj ? quantize_typed<T, 0, 1, BL>(src, batch, rows, K, block, dst, scales, stream)
+                : quantize_typed<T, 0, 0, BL>(src, batch, rows, K, block, dst, scales, stream);
+}
+
+template <int BL>
+hipError_t quantize_any(const void *src, int src_type, int il, int kmaj, int64_t batch, int64_t rows, int64_t K,
+                        int block, uint8_t *dst, void *scales, hipStream_t stream) {
+    switch (src_type) {
+    case TCBF_SRC_I8: return quantize_layout<int8_t, BL>(src, il, kmaj, batch, rows, K, block, dst, scales, stream);
+    case TCBF_SRC_F16:
+        return quantize_layout<_Float16, BL>(src, il, kmaj, batch, rows, K, block, dst, scales, stream);
+    default: return quantize_layout<float, BL>(src, il, kmaj, batch, rows, K, block, dst, scales, stream);
+    }
 }
 
 }  // namespace
@@ -283,15 +305,12 @@ int64_t quantize_e4m3_tiles(int64_t batch, int64_t rows, int64_t K) {
 }
 
 hipError_t quantize_e4m3_launch(const void *src, int src_type, int src_layout, int64_t batch, int64_t rows,
-                                int64_t K, int src_k_major, int block, uint8_t *dst, void *scales,
+                                int64_t K, int src_k_major, int block, int dst_layout, uint8_t *dst, void *scales,
                                 hipStream_t stream) {
     const int il = src_layout == TCBF_INTERLEAVED;
-    switch (src_type) {
-    case TCBF_SRC_I8: return quantize_layout<int8_t>(src, il, src_k_major, batch, rows, K, block, dst, scales, stream);
-    case TCBF_SRC_F16:
-        return quantize_layout<_Float16>(src, il, src_k_major, batch, rows, K, block, dst, scales, stream);
-    default: return quantize_layout<float>(src, il, src_k_major, batch, rows, K, block, dst, scales, stream);
-    }
+    if (dst_layout == TCBF_BLOCKED)
+        return quantize_any<1>(src, src_type, il, src_k_major, batch, rows, K, block, dst, scales, stream);
+    return quantize_any<0>(src, src_type, il, src_k_major, batch, rows, K, block, dst, scales, stream);
 }
 
 }  // namespace tcbf

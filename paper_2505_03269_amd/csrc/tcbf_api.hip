@@ -57,9 +57,10 @@ tcbf_status current_device_is(int device) {
 tcbf_status validate_desc(const tcbf_plan_desc *d) {
     if (d->struct_size < kDescV1) return TCBF_ERROR_INVALID_VALUE;
     if (d->batch < 1 || d->M < 1 || d->N < 1 || d->K < 1) return TCBF_ERROR_INVALID_VALUE;
-    // the receiver-blocked layout is a weight (A) layout of the fp16 mode only
-    const bool a_ok = is_layout(d->a_layout) || (d->a_layout == TCBF_BLOCKED && d->dtype == TCBF_F16);
-    if (!a_ok || !is_layout(d->b_layout) || !is_layout(d->c_layout)) return TCBF_ERROR_INVALID_VALUE;
+    // the receiver-blocked layout: fp16 weights (A), or both FP8 operands
+    const bool a_ok = is_layout(d->a_layout) || (d->a_layout == TCBF_BLOCKED && (d->dtype == TCBF_F16 || is_f8(d->dtype)));
+    const bool b_ok = is_layout(d->b_layout) || (d->b_layout == TCBF_BLOCKED && is_f8(d->dtype));
+    if (!a_ok || !b_ok || !is_layout(d->c_layout)) return TCBF_ERROR_INVALID_VALUE;
     if (d->variant < 0) return TCBF_ERROR_INVALID_VALUE;
     if (d->dtype == TCBF_F16) {
         // every per-channel plane must be indexable with 32-bit element counts
@@ -72,10 +73,13 @@ tcbf_status validate_desc(const tcbf_plan_desc *d) {
         if (d->K > ((int64_t)1 << 26)) return TCBF_ERROR_NOT_SUPPORTED;
         if (2 * d->M * d->N >= kMaxIndex) return TCBF_ERROR_NOT_SUPPORTED;
     } else if (is_f8(d->dtype)) {
-        if (d->a_layout != TCBF_PLANAR || d->b_layout != TCBF_PLANAR) return TCBF_ERROR_INVALID_VALUE;
+        const bool planar = d->a_layout == TCBF_PLANAR && d->b_layout == TCBF_PLANAR;
+        const bool blocked = d->a_layout == TCBF_BLOCKED && d->b_layout == TCBF_BLOCKED;
+        if (!planar && !blocked) return TCBF_ERROR_INVALID_VALUE;
         if (d->N % 4 != 0) return TCBF_ERROR_INVALID_VALUE;
         // byte offsets of every per-channel operand and output fit 31 bits
-        const int64_t kp = tcbf::f8_kp(d->K);
+        // (blocked operands hold whole 64-receiver blocks)
+        const int64_t kp = blocked ? (tcbf::f8_kp(d->K) + 63) / 64 * 64 : tcbf::f8_kp(d->K);
         if (2 * d->M * kp >= kMaxIndex || 2 * d->N * kp >= kMaxIndex || 8 * d->M * d->N >= kMaxIndex)
             return TCBF_ERROR_NOT_SUPPORTED;
     } else {
@@ -243,17 +247,18 @@ tcbf_status tcbf_pack1bit(const void *src, int32_t src_type, int32_t src_layout,
 }
 
 tcbf_status tcbf_quantize_e4m3(const void *src, int32_t src_type, int32_t src_layout, int64_t batch, int64_t rows,
-                               int64_t K, int32_t src_k_major, int32_t block, uint8_t *dst, void *scales,
-                               void *stream) {
+                               int64_t K, int32_t src_k_major, int32_t block, int32_t dst_layout, uint8_t *dst,
+                               void *scales, void *stream) {
     if (src == nullptr || dst == nullptr || scales == nullptr) return TCBF_ERROR_INVALID_VALUE;
     if (!is_src_type(src_type) || !is_layout(src_layout)) return TCBF_ERROR_INVALID_VALUE;
+    if (dst_layout != TCBF_PLANAR && dst_layout != TCBF_BLOCKED) return TCBF_ERROR_INVALID_VALUE;
     if (block != 0 && block != 32) return TCBF_ERROR_INVALID_VALUE;
     if (batch < 1 || rows < 1 || K < 1) return TCBF_ERROR_INVALID_VALUE;
     if (!aligned16(src) || !aligned16(dst) || !aligned16(scales)) return TCBF_ERROR_INVALID_VALUE;
     if (tcbf::quantize_e4m3_tiles(batch, rows, K) >= kMaxIndex || batch * rows / 256 + 1 >= kMaxIndex)
         return TCBF_ERROR_NOT_SUPPORTED;
     hipError_t e = tcbf::quantize_e4m3_launch(src, src_type, src_layout, batch, rows, K, src_k_major != 0, block,
-                                              dst, scales, (hipStream_t)stream);
+                                              dst_layout, dst, scales, (hipStream_t)stream);
     return e == hipSuccess ? TCBF_SUCCESS : TCBF_ERROR_DEVICE;
 }
 

@@ -62,7 +62,7 @@ hipError_t f8_launch(const Problem &p, const F8Config &cfg, bool mx, const void 
 // e4m3 quantisation (block 0: per-row fp32 scales, 32: per-block E8M0).
 int64_t quantize_e4m3_tiles(int64_t batch, int64_t rows, int64_t K);
 hipError_t quantize_e4m3_launch(const void *src, int src_type, int src_layout, int64_t batch, int64_t rows,
-                                int64_t K, int src_k_major, int block, uint8_t *dst, void *scales,
+                                int64_t K, int src_k_major, int block, int dst_layout, uint8_t *dst, void *scales,
                                 hipStream_t stream);
 
 // Steering weights from geometry (FP64 phases; fp16 or fp32 planar out).

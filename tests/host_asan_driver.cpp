@@ -100,8 +100,9 @@ int main() {
     expect("pack null", tcbf_pack1bit(nullptr, 0, 0, 1, 1, 1, 1, nullptr, nullptr), INV);
     expect("pack src type", tcbf_pack1bit(p, 9, 0, 1, 1, 1, 1, static_cast<uint32_t *>(p), nullptr), INV);
     expect("pack misaligned", tcbf_pack1bit(q, 0, 0, 1, 1, 1, 1, static_cast<uint32_t *>(p), nullptr), INV);
-    expect("quant block", tcbf_quantize_e4m3(p, 1, 0, 1, 1, 1, 1, 16, a16, p, nullptr), INV);
-    expect("quant no scales", tcbf_quantize_e4m3(p, 1, 0, 1, 1, 1, 1, 0, a16, nullptr, nullptr), INV);
+    expect("quant block", tcbf_quantize_e4m3(p, 1, 0, 1, 1, 1, 1, 16, 0, a16, p, nullptr), INV);
+    expect("quant out layout", tcbf_quantize_e4m3(p, 1, 0, 1, 1, 1, 1, 0, 1, a16, p, nullptr), INV);
+    expect("quant no scales", tcbf_quantize_e4m3(p, 1, 0, 1, 1, 1, 1, 0, 0, a16, nullptr, nullptr), INV);
     const double *dp = reinterpret_cast<const double *>(p);
     expect("steer speed", tcbf_steering_weights(dp, dp, dp, 0.0, 1, 1, 1, TCBF_SRC_F16, p, nullptr), INV);
     expect("steer out type", tcbf_steering_weights(dp, dp, dp, 3e8, 1, 1, 1, TCBF_SRC_I8, p, nullptr), INV);

@@ -43,7 +43,7 @@ def test_status_strings_and_version():
     assert tcbf.status_string(1) == "TCBF_ERROR_INVALID_VALUE"
     assert tcbf.status_string(4) == "TCBF_ERROR_DEVICE"
     assert tcbf.status_string(99) == "TCBF_UNKNOWN_STATUS"
-    assert tcbf.lib().tcbf_version() == 1
+    assert tcbf.lib().tcbf_version() == 2
 
 
 def _plan_status(**kw):
@@ -66,6 +66,8 @@ def _plan_status(**kw):
     # the receiver-blocked layout: fp16 weights only, fast kernel with 32 receivers per stage
     dict(b_layout=tcbf.BLOCKED), dict(c_layout=tcbf.BLOCKED), dict(dtype=tcbf.INT1, a_layout=tcbf.BLOCKED),
     dict(dtype=tcbf.F8_E4M3, a_layout=tcbf.BLOCKED), dict(dtype=tcbf.MXF8_E4M3, a_layout=tcbf.BLOCKED),
+    dict(dtype=tcbf.F8_E4M3, b_layout=tcbf.BLOCKED), dict(dtype=tcbf.INT1, b_layout=tcbf.BLOCKED),
+    dict(dtype=tcbf.F8_E4M3, a_layout=tcbf.BLOCKED, b_layout=tcbf.BLOCKED, N=6),
     dict(a_layout=tcbf.BLOCKED, b_layout=tcbf.INTERLEAVED), dict(a_layout=tcbf.BLOCKED, N=12),
     dict(a_layout=tcbf.BLOCKED, variant=1), dict(a_layout=tcbf.BLOCKED, variant=3),
     dict(a_layout=tcbf.BLOCKED, variant=4), dict(a_layout=tcbf.BLOCKED, variant=7),
@@ -96,7 +98,7 @@ def test_null_arguments():
     assert L.tcbf_plan_query(None, None) == 1
     assert L.tcbf_plan_destroy(None) == 0
     assert L.tcbf_pack1bit(None, 0, 0, 1, 1, 1, 1, None, None) == 1
-    assert L.tcbf_quantize_e4m3(None, 0, 0, 1, 1, 1, 1, 0, None, None, None) == 1
+    assert L.tcbf_quantize_e4m3(None, 0, 0, 1, 1, 1, 1, 0, 0, None, None, None) == 1
     assert L.tcbf_block_weights(None, 0, 1, 1, 1, None, None) == 1
 
 
@@ -113,6 +115,13 @@ def test_block_weights_argument_checks():
     q = ctypes.c_void_p(addr + 8)
     assert L.tcbf_block_weights(p, 0, 1, 1, 1, q, None) == 1             # misaligned dst
     assert L.tcbf_block_weights(p, 0, 1 << 40, 1 << 20, 1 << 10, p, None) == 2   # too large
+
+
+def test_f8_codes_shape():
+    assert tcbf.f8_codes_shape(2, 10, 100) == (2, 2, 10, 128)
+    assert tcbf.f8_codes_shape(2, 10, 100, tcbf.BLOCKED) == (2, 2, 2, 10, 64)
+    assert tcbf.f8_codes_shape(1, 3, 8192, tcbf.BLOCKED) == (1, 2, 128, 3, 64)
+    assert tcbf.f8_codes_shape(1, 3, 33, tcbf.BLOCKED) == (1, 2, 1, 3, 64)
 
 
 def test_blocked_shape():
@@ -141,13 +150,15 @@ def test_quantize_argument_checks():
     buf = ctypes.create_string_buffer(256)
     addr = (ctypes.addressof(buf) + 15) & ~15
     p = ctypes.c_void_p(addr)
-    assert L.tcbf_quantize_e4m3(p, 9, 0, 1, 1, 1, 1, 0, p, p, None) == 1     # bad source type
-    assert L.tcbf_quantize_e4m3(p, 1, 2, 1, 1, 1, 1, 0, p, p, None) == 1     # bad layout
-    assert L.tcbf_quantize_e4m3(p, 1, 0, 1, 1, 1, 1, 16, p, p, None) == 1    # bad block
-    assert L.tcbf_quantize_e4m3(p, 1, 0, 1, 0, 1, 1, 0, p, p, None) == 1     # rows 0
-    assert L.tcbf_quantize_e4m3(p, 1, 0, 1, 1, 1, 1, 0, p, None, None) == 1  # no scales
+    assert L.tcbf_quantize_e4m3(p, 9, 0, 1, 1, 1, 1, 0, 0, p, p, None) == 1     # bad source type
+    assert L.tcbf_quantize_e4m3(p, 1, 2, 1, 1, 1, 1, 0, 0, p, p, None) == 1     # bad layout
+    assert L.tcbf_quantize_e4m3(p, 1, 0, 1, 1, 1, 1, 0, 1, p, p, None) == 1     # interleaved output
+    assert L.tcbf_quantize_e4m3(p, 1, 0, 1, 1, 1, 1, 0, 5, p, p, None) == 1     # bad output layout
+    assert L.tcbf_quantize_e4m3(p, 1, 0, 1, 1, 1, 1, 16, 0, p, p, None) == 1    # bad block
+    assert L.tcbf_quantize_e4m3(p, 1, 0, 1, 0, 1, 1, 0, 0, p, p, None) == 1     # rows 0
+    assert L.tcbf_quantize_e4m3(p, 1, 0, 1, 1, 1, 1, 0, 0, p, None, None) == 1  # no scales
     q = ctypes.c_void_p(addr + 4)
-    assert L.tcbf_quantize_e4m3(p, 1, 0, 1, 1, 1, 1, 32, p, q, None) == 1    # misaligned scales
+    assert L.tcbf_quantize_e4m3(p, 1, 0, 1, 1, 1, 1, 32, 2, p, q, None) == 1    # misaligned scales
 
 
 def test_steering_argument_checks():
