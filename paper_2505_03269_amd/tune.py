@@ -17,6 +17,13 @@ import os
 
 from . import F16, F8_E4M3, INT1, MXF8_E4M3, PLANAR, Plan, TcbfError
 
+
+def _layouts(dtype, operand_layout):
+    """(a_layout, b_layout) of a plan: the operand layout applies to W (and,
+    for FP8, to X as well; a blocked fp16 plan keeps X planar)."""
+    fp8 = dtype in (F8_E4M3, MXF8_E4M3)
+    return operand_layout, (operand_layout if fp8 else PLANAR)
+
 # candidate variants per dtype, seed first
 CANDIDATES = {
     F16: [2, 6, 3, 4, 5, 7, 1],      # 2: Table 3's MI300X point (128 x 128 tile, 2 x 2 waves of 64 x 64)
@@ -26,8 +33,9 @@ CANDIDATES = {
 }
 
 
-def cache_key(arch, dtype, batch, M, N, K, c_layout=PLANAR, a_shared=False):
-    return "%s|dtype%d|%dx%dx%dx%d|c%d|s%d" % (arch, int(dtype), batch, M, N, K, int(c_layout), int(bool(a_shared)))
+def cache_key(arch, dtype, batch, M, N, K, c_layout=PLANAR, a_shared=False, operand_layout=PLANAR):
+    key = "%s|dtype%d|%dx%dx%dx%d|c%d|s%d" % (arch, int(dtype), batch, M, N, K, int(c_layout), int(bool(a_shared)))
+    return key if operand_layout == PLANAR else key + "|op%d" % int(operand_layout)
 
 
 def load_cache(path):
@@ -46,12 +54,14 @@ def save_cache(path, cache):
     os.replace(tmp, path)
 
 
-def valid_candidates(batch, M, N, K, dtype, c_layout=PLANAR, a_shared=False, device=0):
+def valid_candidates(batch, M, N, K, dtype, c_layout=PLANAR, a_shared=False, device=0, operand_layout=PLANAR):
     """Variants the library accepts for this problem (plan creation succeeds)."""
     out = []
+    al, bl = _layouts(dtype, operand_layout)
     for v in CANDIDATES[dtype]:
         try:
-            Plan(batch, M, N, K, dtype, c_layout=c_layout, a_shared=a_shared, variant=v, device=device)
+            Plan(batch, M, N, K, dtype, a_layout=al, b_layout=bl, c_layout=c_layout, a_shared=a_shared, variant=v,
+                 device=device)
         except TcbfError:
             continue
         out.append(v)
@@ -108,23 +118,26 @@ def measure(plan, reps=10, warmup=2, inputs=None):
 
 
 def tune(batch, M, N, K, dtype=F16, c_layout=PLANAR, a_shared=False, cache_path=None, reps=10, warmup=2,
-         device=0, arch=None, measure_fn=None, force=False):
+         device=0, arch=None, measure_fn=None, force=False, operand_layout=PLANAR):
     """Time every valid variant (seed first) and return
-    {"variant": best, "ms": {variant: ms}}; cached under cache_path."""
+    {"variant": best, "ms": {variant: ms}}; cached under cache_path.
+    operand_layout=BLOCKED tunes the receiver-blocked operand form."""
     if arch is None:
         import torch
         arch = torch.cuda.get_device_properties(device).gcnArchName.split(":")[0]
-    key = cache_key(arch, dtype, batch, M, N, K, c_layout, a_shared)
+    key = cache_key(arch, dtype, batch, M, N, K, c_layout, a_shared, operand_layout)
     cache = load_cache(cache_path)
     if key in cache and not force:
         return cache[key]
-    cands = valid_candidates(batch, M, N, K, dtype, c_layout, a_shared, device)
+    cands = valid_candidates(batch, M, N, K, dtype, c_layout, a_shared, device, operand_layout)
+    al, bl = _layouts(dtype, operand_layout)
     if not cands:
         raise TcbfError(2, "no kernel variant accepts this problem")
     timings = {}
     inputs = None
     for v in cands:
-        plan = Plan(batch, M, N, K, dtype, c_layout=c_layout, a_shared=a_shared, variant=v, device=device)
+        plan = Plan(batch, M, N, K, dtype, a_layout=al, b_layout=bl, c_layout=c_layout, a_shared=a_shared,
+                    variant=v, device=device)
         if measure_fn is not None:
             ms = measure_fn(plan)
         else:
@@ -140,7 +153,11 @@ def tune(batch, M, N, K, dtype=F16, c_layout=PLANAR, a_shared=False, cache_path=
     return entry
 
 
-def tuned_plan(batch, M, N, K, dtype=F16, c_layout=PLANAR, a_shared=False, cache_path=None, device=0, **kw):
+def tuned_plan(batch, M, N, K, dtype=F16, c_layout=PLANAR, a_shared=False, cache_path=None, device=0,
+               operand_layout=PLANAR, **kw):
     """A Plan with the cached (or freshly tuned) variant for this shape."""
-    entry = tune(batch, M, N, K, dtype, c_layout, a_shared, cache_path=cache_path, device=device, **kw)
-    return Plan(batch, M, N, K, dtype, c_layout=c_layout, a_shared=a_shared, variant=entry["variant"], device=device)
+    entry = tune(batch, M, N, K, dtype, c_layout, a_shared, cache_path=cache_path, device=device,
+                 operand_layout=operand_layout, **kw)
+    al, bl = _layouts(dtype, operand_layout)
+    return Plan(batch, M, N, K, dtype, a_layout=al, b_layout=bl, c_layout=c_layout, a_shared=a_shared,
+                variant=entry["variant"], device=device)

@@ -43,3 +43,16 @@ def test_tune_picks_a_measured_variant_and_caches(tmp_path):
 def test_tune_other_dtypes(tmp_path, dtype):
     e = tune.tune(1, 256, 256, 512, dtype, cache_path=str(tmp_path / "t.json"), reps=2, warmup=1)
     assert set(e["ms"]) == {"1", "2"}
+
+
+@pytest.mark.parametrize("dtype", [tcbf.F16, tcbf.F8_E4M3])
+def test_tune_blocked_operands(tmp_path, dtype):
+    """Blocked operands: only the variants that read them are timed, under
+    their own cache key, and the tuned plan takes blocked tensors."""
+    path = str(tmp_path / "tb.json")
+    e = tune.tune(2, 256, 256, 192, dtype, cache_path=path, reps=2, warmup=1, operand_layout=tcbf.BLOCKED)
+    want = {"2", "5", "6"} if dtype == tcbf.F16 else {"1", "2"}
+    assert set(e["ms"]) == want
+    plan = tune.tuned_plan(2, 256, 256, 192, dtype, cache_path=path, operand_layout=tcbf.BLOCKED)
+    assert plan.a_layout == tcbf.BLOCKED and plan.info()["variant"] == e["variant"]
+    assert len(tune.load_cache(path)) == 1

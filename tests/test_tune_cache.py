@@ -2,7 +2,7 @@
 the seed of the fp16 sweep is the variant matching Table 3's MI300X point."""
 import json
 
-from paper_2505_03269_amd import F16, INTERLEAVED, tune
+from paper_2505_03269_amd import BLOCKED, F16, INTERLEAVED, tune
 
 
 def test_cache_key_distinguishes_every_field():
@@ -11,7 +11,8 @@ def test_cache_key_distinguishes_every_field():
     others = [tune.cache_key("gfx942", F16, 256, 1024, 4096, 576), tune.cache_key("gfx950", 2, 256, 1024, 4096, 576),
               tune.cache_key("gfx950", F16, 255, 1024, 4096, 576), tune.cache_key("gfx950", F16, 256, 1024, 4096, 577),
               tune.cache_key("gfx950", F16, 256, 1024, 4096, 576, INTERLEAVED),
-              tune.cache_key("gfx950", F16, 256, 1024, 4096, 576, a_shared=True)]
+              tune.cache_key("gfx950", F16, 256, 1024, 4096, 576, a_shared=True),
+              tune.cache_key("gfx950", F16, 256, 1024, 4096, 576, operand_layout=BLOCKED)]
     assert len(set(others + [base])) == len(others) + 1
 
 
