@@ -354,8 +354,10 @@ def bench_secondary(steps, serving=True, copy_gbs=None):
     B = torch.from_numpy(X[None]).to("cuda:0")
     Ab = tcbf.block_weights(A)
     C = plan.empty_output()
-    ms = time_launches(lambda: plan.execute(Ab, B, C), st, 3)
-    ms_p = time_launches(lambda: plan_p.execute(A, B, C), st, 3)
+    # sub-millisecond launches: time enough of them to average out clock swings
+    st4 = max(st, 20)
+    ms = time_launches(lambda: plan.execute(Ab, B, C), st4, 3)
+    ms_p = time_launches(lambda: plan_p.execute(A, B, C), st4, 3)
     del Ab
     tops = info["useful_ops"] / (ms * 1e-3) / 1e12
     out.append({"workload": "ultrasound-fp16: batch=1 M=32768 K=8192 N=256", "kernel": info["kernel_name"],
@@ -377,13 +379,13 @@ def bench_secondary(steps, serving=True, copy_gbs=None):
         plan = tcbf.Plan(1, cfg["M"], cfg["N"], cfg["K"], dt, a_layout=BL, b_layout=BL)
         info = plan.info()
         C = plan.empty_output()
-        ms = time_launches(lambda: plan.execute(Wq, Xq, C, Ws, Xs), st, 3)
+        ms = time_launches(lambda: plan.execute(Wq, Xq, C, Ws, Xs), st4, 3)
         ms_q = time_launches(lambda: tcbf.quantize_e4m3(B, k_major=False, layout=tcbf.PLANAR, block=block,
-                                                        out=Xq, scales=Xs, out_layout=BL), st, 1)
+                                                        out=Xq, scales=Xs, out_layout=BL), st4, 1)
         Wp, Wps = tcbf.quantize_e4m3(A, k_major=True, layout=tcbf.PLANAR, block=block)
         Xp, Xps = tcbf.quantize_e4m3(B, k_major=False, layout=tcbf.PLANAR, block=block)
         plan_p = tcbf.Plan(1, cfg["M"], cfg["N"], cfg["K"], dt)
-        ms_p = time_launches(lambda: plan_p.execute(Wp, Xp, C, Wps, Xps), st, 3)
+        ms_p = time_launches(lambda: plan_p.execute(Wp, Xp, C, Wps, Xps), st4, 3)
         del Wp, Wps, Xp, Xps
         tops = info["useful_ops"] / (ms * 1e-3) / 1e12
         out.append({"workload": "ultrasound-%s: batch=1 M=32768 K=8192 N=256" % name, "kernel": info["kernel_name"],
