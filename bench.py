@@ -100,6 +100,16 @@ def time_launches(fn, steps, warmup):
     return start.elapsed_time(stop) / steps  # ms per launch
 
 
+def time_interleaved(fns, steps, warmup, rounds=3):
+    """Median ms per launch of each callable, timed in alternating rounds (so a
+    clock swing during the measurement does not favour whichever goes first)."""
+    res = [[] for _ in fns]
+    for _ in range(rounds):
+        for i, fn in enumerate(fns):
+            res[i].append(time_launches(fn, steps, warmup))
+    return [float(np.median(v)) for v in res]
+
+
 def measure_peak(kind, random=False, target_ms=40.0, blocks=2048):
     """Measured ceiling of one instruction kind (tcbf_peak_probe): a short
     launch sizes the run to about target_ms, then the median of three timed
@@ -356,8 +366,7 @@ def bench_secondary(steps, serving=True, copy_gbs=None):
     C = plan.empty_output()
     # sub-millisecond launches: time enough of them to average out clock swings
     st4 = max(st, 20)
-    ms = time_launches(lambda: plan.execute(Ab, B, C), st4, 3)
-    ms_p = time_launches(lambda: plan_p.execute(A, B, C), st4, 3)
+    ms, ms_p = time_interleaved([lambda: plan.execute(Ab, B, C), lambda: plan_p.execute(A, B, C)], st4, 3)
     del Ab
     tops = info["useful_ops"] / (ms * 1e-3) / 1e12
     out.append({"workload": "ultrasound-fp16: batch=1 M=32768 K=8192 N=256", "kernel": info["kernel_name"],
@@ -379,13 +388,13 @@ def bench_secondary(steps, serving=True, copy_gbs=None):
         plan = tcbf.Plan(1, cfg["M"], cfg["N"], cfg["K"], dt, a_layout=BL, b_layout=BL)
         info = plan.info()
         C = plan.empty_output()
-        ms = time_launches(lambda: plan.execute(Wq, Xq, C, Ws, Xs), st4, 3)
         ms_q = time_launches(lambda: tcbf.quantize_e4m3(B, k_major=False, layout=tcbf.PLANAR, block=block,
                                                         out=Xq, scales=Xs, out_layout=BL), st4, 1)
         Wp, Wps = tcbf.quantize_e4m3(A, k_major=True, layout=tcbf.PLANAR, block=block)
         Xp, Xps = tcbf.quantize_e4m3(B, k_major=False, layout=tcbf.PLANAR, block=block)
         plan_p = tcbf.Plan(1, cfg["M"], cfg["N"], cfg["K"], dt)
-        ms_p = time_launches(lambda: plan_p.execute(Wp, Xp, C, Wps, Xps), st4, 3)
+        ms, ms_p = time_interleaved([lambda: plan.execute(Wq, Xq, C, Ws, Xs),
+                                     lambda: plan_p.execute(Wp, Xp, C, Wps, Xps)], st4, 3)
         del Wp, Wps, Xp, Xps
         tops = info["useful_ops"] / (ms * 1e-3) / 1e12
         out.append({"workload": "ultrasound-%s: batch=1 M=32768 K=8192 N=256" % name, "kernel": info["kernel_name"],
