@@ -638,6 +638,204 @@ __global__ __launch_bounds__(128 * WM, WM == 2 ? 2 : 1) void cgemm_f16_fast_kern
 }
 
 // ===========================================================================
+// Split-ring variant: separate rings for the two operands.
+// ===========================================================================
+//
+// Same tile, waves, fragments and MFMA sequence as the fast kernel with 32
+// receivers per stage, but W and X stage through rings of their own: W two
+// stages deep, X three, in five 16 KiB buffers (80 KiB: still two workgroups
+// per CU).  X, the operand that comes from HBM on a batched radio-astronomy
+// shape (W is re-read from L2 by every sample tile of its channel), is issued
+// two stages ahead, W one.  At stage kt the wave issues W(kt+1) and then
+// X(kt+2); loads retire in order, so waiting until only the newest X stage is
+// in flight means W(kt) and X(kt) have landed while X(kt+1) may still come.
+#define TCBF_SPLIT_LDS                                                             \
+    __shared__ __attribute__((aligned(1024))) char wb0[FastGeo<2, 32>::WREG];      \
+    __shared__ __attribute__((aligned(1024))) char wb1[FastGeo<2, 32>::WREG];      \
+    __shared__ __attribute__((aligned(1024))) char xb0[FastGeo<2, 32>::XREG];      \
+    __shared__ __attribute__((aligned(1024))) char xb1[FastGeo<2, 32>::XREG];      \
+    __shared__ __attribute__((aligned(1024))) char xb2[FastGeo<2, 32>::XREG];
+
+template <int CIL, int AB>
+__device__ __forceinline__ void split_tile(const uint16_t *__restrict__ A, const uint16_t *__restrict__ B,
+                                           float *__restrict__ C, int M, int N, int K, int a_shared, int c, int tm,
+                                           int tn, char *wb0, char *wb1, char *xb0, char *xb1, char *xb2) {
+    constexpr int WM = 2, BK = 32;
+    typedef FastGeo<WM, BK> G;
+    constexpr int TM = G::TM, NW = G::NW;
+    static_assert(G::WREG == G::XREG, "equal operand regions");
+    char *const wbs[2] = {wb0, wb1};
+    char *const xbs[3] = {xb0, xb1, xb2};
+
+    const int tid = threadIdx.x;
+    const int m0 = tm * TM, n0 = tn * BN;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int hl = lane >> 5, l32 = lane & 31;
+
+    const int KW = AB ? (K + 31) / 32 * 32 : K;
+    const uint16_t *Wc = A + (a_shared ? (int64_t)0 : (int64_t)c * 2 * M * KW);
+    const uint16_t *Xc = B + (int64_t)c * 2 * K * N;
+    const __amdgpu_buffer_rsrc_t rw = __builtin_amdgcn_make_buffer_rsrc((void *)Wc, 0, 4 * M * KW, RSRC_FLAGS);
+    const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc((void *)Xc, 0, 4 * K * N, RSRC_FLAGS);
+
+    // per-lane chunks, as in the fast kernel (X slots counted from the X
+    // region's own start)
+    constexpr int WPIECES = G::WREG / 1024, XPIECES = G::XREG / 1024;
+    constexpr int WPW = WPIECES / NW, XPW = XPIECES / NW;
+    constexpr int WROWS = 64 / G::WCH, XROWS = 64 / 16;
+    uint32_t va, vb;
+    int ka, kb, am;
+    {
+        const int s = wave * WPW * 64 + lane;
+        const int p = s / (TM * G::WCH), m = (s / G::WCH) % TM;
+        const int ch = (s % G::WCH) ^ G::swzW(m);
+        ka = ch * 8;
+        am = m;
+        va = AB ? (uint32_t)(((p * (KW / 32)) * M + m0 + m) * 64 + ch * 16)
+                : (uint32_t)(((p * M + m0 + m) * K + ch * 8) * 2);
+    }
+    {
+        const int s = wave * XPW * 64 + lane;
+        const int p = s / (BK * 16), k = (s / 16) % BK, ch = (s & 15) ^ G::swzX(k);
+        kb = k;
+        vb = (n0 + ch * 8 < N) ? (uint32_t)(((p * K + k) * N + n0 + ch * 8) * 2) : OOB;
+    }
+    const bool rows_full = m0 + TM <= M;
+
+    constexpr int KS = BK / 16;
+    int ow[KS], ox[2];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+        const int m = wm * 64 + l32;
+        ow[s] = m * (BK * 2) + (((2 * s + hl) ^ G::swzW(m)) * 16);
+    }
+    {
+        const int g = lane >> 4, j16 = lane & 15;
+        const int krow = 8 * (g >> 1) + (j16 >> 2);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int ns = wn * 64 + 32 * j + 16 * (g & 1) + 4 * (j16 & 3);
+            ox[j] = krow * 256 + (((ns >> 3) ^ G::swzX(krow)) * 16) + (ns & 7) * 2;
+        }
+    }
+
+    const int nk = (K + BK - 1) / BK;
+    // Stages past the last one are issued all the same with every offset out
+    // of range (the loads write zeros into a buffer no stage reads again), so
+    // the sequence of loads, and with it every wait count, is the same on
+    // every path; the compiler then needs no conservative full waits.
+    auto issue_w = [&](char *base, int kt) {
+        const int k0 = kt * BK;
+        const bool tail = k0 + BK > K;
+#pragma unroll
+        for (int q = 0; q < WPW; ++q) {
+            uint32_t off = va;
+            if (!rows_full && m0 + am + q * WROWS >= M) off = OOB;
+            if (tail && k0 + ka >= K) off = OOB;   // also every lane of a stage past the last
+            const int so = kt >= nk ? 0
+                           : AB   ? (k0 / 32) * M * 64 + q * WROWS * 64
+                                  : k0 * 2 + q * WROWS * K * 2;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rw, (LDS_AS void *)(base + (wave * WPW + q) * 1024), 16, off,
+                                                     so, 0, 0);
+        }
+    };
+    auto issue_x = [&](char *base, int kt) {
+        const int k0 = kt * BK;
+        const bool tail = k0 + BK > K;
+#pragma unroll
+        for (int q = 0; q < XPW; ++q) {
+            uint32_t off = vb;
+            if (tail && k0 + kb + q * XROWS >= K) off = OOB;   // also every lane of a stage past the last
+            // (a stage past the last: no uniform offset, so OOB + offset cannot wrap into range)
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rx, (LDS_AS void *)(base + (wave * XPW + q) * 1024), 16, off,
+                                                     kt < nk ? (k0 + q * XROWS) * N * 2 : 0, 0, 0);
+        }
+    };
+
+    Acc acc;
+    acc.zero();
+    auto compute = [&](const char *wst, const char *xst) {
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            half8 wr[2], wi[2], xr[2], xi[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                wr[i] = *reinterpret_cast<const half8 *>(wst + ow[s] + i * 32 * BK * 2);
+                wi[i] = *reinterpret_cast<const half8 *>(wst + ow[s] + i * 32 * BK * 2 + TM * BK * 2);
+            }
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int o = ox[j] + s * 16 * 256;
+                xr[j] = tr_frag(xst, o, o + 4 * 256);
+                xi[j] = tr_frag(xst, o + BK * BN * 2, o + BK * BN * 2 + 4 * 256);
+            }
+            mma_step(acc, wr, wi, xr, xi);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    };
+
+    static_assert(XPW < 64, "vmcnt range");
+    constexpr int kWaitNewestX = vmcnt_imm(XPW), kWaitAll = vmcnt_imm(0);
+    // stage kt: W in wbs[kt % 2], X in xbs[kt % 3]
+    auto stage_step = [&](int kt, int uw, int ux) {
+        // W(kt) and X(kt) landed; X(kt+1), issued last, may be in flight
+        __builtin_amdgcn_s_waitcnt(kWaitNewestX);
+        // every wave's loads landed and stage kt-1 fully read (bare barrier:
+        // the release fence of __syncthreads would wait for X(kt+1) too)
+        asm volatile("s_barrier" ::: "memory");
+        issue_w(wbs[(uw + 1) % 2], kt + 1);
+        issue_x(xbs[(ux + 2) % 3], kt + 2);
+        compute(wbs[uw], xbs[ux]);
+    };
+    // prologue, in the order of the steady state: X(0), then W(0), X(1)
+    issue_x(xbs[0], 0);
+    issue_w(wbs[0], 0);
+    issue_x(xbs[1], 1);
+    // groups of 6 stages keep both rings' buffer choices compile-time
+    int kt0 = 0;
+    for (; kt0 + 6 <= nk; kt0 += 6) {
+#pragma unroll
+        for (int u = 0; u < 6; ++u) stage_step(kt0 + u, u % 2, u % 3);
+    }
+#pragma unroll
+    for (int u = 0; u < 5; ++u)
+        if (kt0 + u < nk) stage_step(kt0 + u, u % 2, u % 3);
+
+    // epilogue through the idle buffers (four of the five: 64 KiB), once the
+    // zero-filling loads past the last stage have landed
+    __builtin_amdgcn_s_waitcnt(kWaitAll);
+    constexpr int ROWS_PER_BUF = G::WREG / staging_pitch<CIL>();
+    static_assert(ROWS_PER_BUF * 4 >= staging_rows<WM, CIL>(), "four buffers hold a staging round");
+    auto row_ptr = [&](int row) -> char * {
+        const int b = row / ROWS_PER_BUF;
+        char *base = wb0;
+        if (b == 1) base = wb1;
+        if (b == 2) base = xb0;
+        if (b == 3) base = xb1;
+        return base + (row % ROWS_PER_BUF) * staging_pitch<CIL>();
+    };
+    store_tile_staged<WM, CIL>(acc, row_ptr, C + (int64_t)c * 2 * M * N, M, N, m0, n0, wave, lane);
+}
+
+template <int CIL, int AB>
+__global__ __launch_bounds__(256, 2) void cgemm_f16_split_kernel(const uint16_t *__restrict__ A,
+                                                                 const uint16_t *__restrict__ B,
+                                                                 float *__restrict__ C, int M, int N, int K,
+                                                                 int a_shared, int tiles_m, int tiles_n,
+                                                                 int nblocks) {
+    TCBF_SPLIT_LDS
+    const int t = (int)xcd_remap(blockIdx.x, nblocks);
+    const int per_c = tiles_m * tiles_n;
+    const int c = t / per_c;
+    const int rem = t - c * per_c;
+    int tm, tn;
+    tile_coords(rem, tiles_m, tiles_n, tm, tn);
+    split_tile<CIL, AB>(A, B, C, M, N, K, a_shared, c, tm, tn, wb0, wb1, xb0, xb1, xb2);
+}
+
+// ===========================================================================
 // Grouped persistent kernel: many problems of different shapes in one launch.
 // ===========================================================================
 //
@@ -707,11 +905,11 @@ KernFn pick(int ail, int bil, int cil) {
 
 // Fast-kernel configurations (variant: beam waves WM, receivers per stage,
 // ring depth):  2: 2, 32, 2   3: 2, 16, 4   4: 2, 16, 5   5: 2, 32, 3
-//               6: 4, 32, 3   7: 4, 16, 6
+//               6: 4, 32, 3   7: 4, 16, 6   8: 2, 32, split (W 2, X 3)
 // WM = 2 runs two 256-thread workgroups per CU; WM = 4 one 512-thread
 // workgroup with a 256 x 128 tile.
 constexpr int kFirstFast = 2;
-constexpr int kNumFast = 6;
+constexpr int kNumFast = 7;
 constexpr int kDefaultFast = 2;
 
 struct FastShape {
@@ -723,6 +921,7 @@ FastShape fast_shape(int v) {
     case 3: case 4: return {2, 16};
     case 5: return {2, 32};
     case 6: return {4, 32};
+    case 8: return {2, 32};
     default: return {4, 16};
     }
 }
@@ -732,6 +931,7 @@ template <int AB> FastFn fast_fn_of(int v, bool cil) {
     case 2: return cil ? cgemm_f16_fast_kernel<2, 32, 2, 1, AB> : cgemm_f16_fast_kernel<2, 32, 2, 0, AB>;
     case 5: return cil ? cgemm_f16_fast_kernel<2, 32, 3, 1, AB> : cgemm_f16_fast_kernel<2, 32, 3, 0, AB>;
     case 6: return cil ? cgemm_f16_fast_kernel<4, 32, 3, 1, AB> : cgemm_f16_fast_kernel<4, 32, 3, 0, AB>;
+    case 8: return cil ? cgemm_f16_split_kernel<1, AB> : cgemm_f16_split_kernel<0, AB>;
     }
     return nullptr;
 }
@@ -752,7 +952,7 @@ FastFn fast_fn(int v, bool cil, bool ab) {
 // multiple of 8; planar W with K a multiple of 8, or blocked W with any K;
 // every per-channel operand and output below 2 GiB so 32-bit buffer offsets
 // reach it).  Blocked W: only the fast kernel, variants with 32 receivers per
-// stage (2, 5, 6).
+// stage (2, 5, 6, 8).
 static bool fast_ok(const Problem &p) {
     const int64_t lim = (int64_t)1 << 31;
     const bool ab = p.a_layout == TCBF_BLOCKED;
@@ -762,7 +962,7 @@ static bool fast_ok(const Problem &p) {
            p.batch * ((p.M + BM - 1) / BM) * ((p.N + BN - 1) / BN) < lim;
 }
 
-static bool reads_blocked(int v) { return v == 2 || v == 5 || v == 6; }
+static bool reads_blocked(int v) { return v == 2 || v == 5 || v == 6 || v == 8; }
 
 bool f16_select(const Problem &p, int forced_variant, F16Config *cfg) {
     const bool ab = p.a_layout == TCBF_BLOCKED;
@@ -790,6 +990,7 @@ int64_t f16_workgroups(const Problem &p, const F16Config &cfg) {
 }
 
 const char *f16_kernel_name(const F16Config &cfg) {
+    if (cfg.variant == 8) return "cgemm_f16_split_kernel";
     return cfg.variant >= kFirstFast ? "cgemm_f16_fast_kernel" : "cgemm_f16_kernel";
 }
 

@@ -76,9 +76,9 @@ def test_blocked_products_match_planar(batch, M, N, K):
     check_fp_full(planar, oracle.cgemm(Wc, Xc), np.matmul(np.abs(Wc), np.abs(Xc)), K)
     Wb = tcbf.block_weights(to_dev(W))
     Xd = to_dev(X)
-    for v in (0, 2, 5, 6):
+    for v in (0, 2, 5, 6, 8):
         got, plan = _run(Wb, Xd, M, K, tcbf.BLOCKED, variant=v)
-        assert plan.info()["kernel_name"] == "cgemm_f16_fast_kernel"
+        assert plan.info()["kernel_name"] == ("cgemm_f16_split_kernel" if v == 8 else "cgemm_f16_fast_kernel")
         assert np.array_equal(got, planar), "blocked weights, variant %d, differ from planar" % v
     got_il, _ = _run(Wb, Xd, M, K, tcbf.BLOCKED, c_layout=tcbf.INTERLEAVED)
     assert np.array_equal(got_il, planar)
