@@ -329,8 +329,14 @@ def bench_secondary(steps, serving=True, copy_gbs=None):
     ms = time_launches(lambda: tcbf.steering_weights(pos, dirs, freqs, wl.C0, out=Wst), st, 1)
     nbytes = Wst.numel() * 2 + (pos.numel() + dirs.numel() + freqs.numel()) * 8
     gbs = nbytes / (ms * 1e-3) / 1e9
+    # the same weights written straight into the blocked layout the product reads
+    Wbl = torch.empty(tcbf.blocked_shape(256, 1024, 576), dtype=torch.float16, device="cuda:0")
+    ms_bl = time_launches(lambda: tcbf.steering_weights(pos, dirs, freqs, wl.C0, out=Wbl, out_layout=tcbf.BLOCKED),
+                          st, 1)
+    del Wbl
     out.append({"workload": "steering weights fp16: 256 ch x 1024 beams x 576 antennas (FP64 phase)",
                 "kernel": "steering_kernel", "value": round(gbs, 1), "unit": "GB/s", "ms_per_launch": round(ms, 4),
+                "blocked_output_ms_per_launch": round(ms_bl, 4),
                 "weights_per_s": round(Wst.numel() / 2 / (ms * 1e-3), 1),
                 "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                              "frac": round(gbs / PEAK_HBM_GBS, 4)}})

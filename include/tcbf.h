@@ -273,16 +273,21 @@ tcbf_status tcbf_quantize_e4m3(const void *src, int32_t src_type, int32_t src_la
  * boundaries).
  *   positions (device) [K][3] double, directions (device) [M][3] double,
  *   frequencies (device) [batch] double, all 8-byte aligned;
- *   W (device, 16-byte aligned): planar [batch][2][M][K], element type
- *   out_type = TCBF_SRC_F16 or TCBF_SRC_F32.  This is the TCBF_F16 operand layout of W; FP8
- *   weights follow with tcbf_quantize_e4m3.
+ *   W (device, 16-byte aligned), element type out_type = TCBF_SRC_F16 or
+ *   TCBF_SRC_F32, out_layout TCBF_PLANAR: [batch][2][M][K]; out_layout
+ *   TCBF_BLOCKED (fp16 only): the receiver-blocked [batch][2][ceil(K/32)][M][32]
+ *   with zeros past K, the same values as tcbf_block_weights of the planar
+ *   output.  These are the TCBF_F16 operand layouts of W; FP8 weights follow
+ *   with tcbf_quantize_e4m3.
  * Returns INVALID_VALUE for NULL or misaligned pointers, non-positive sizes,
- * a wave speed that is not positive and finite, or another out_type.
+ * a wave speed that is not positive and finite, another out_type, or another
+ * out_layout (blocked with fp32 included).
  * Asynchronous on `stream`; allocation-free.
  */
 tcbf_status tcbf_steering_weights(const double *positions, const double *directions,
                                   const double *frequencies, double wave_speed, int64_t batch,
-                                  int64_t M, int64_t K, int32_t out_type, void *W, void *stream);
+                                  int64_t M, int64_t K, int32_t out_type, int32_t out_layout,
+                                  void *W, void *stream);
 
 /*
  * Grouped persistent launch (TCBF_F16, TCBF_F8_E4M3, TCBF_MXF8_E4M3,

@@ -91,7 +91,7 @@ def lib():
     L.tcbf_pack1bit.restype = i32
     L.tcbf_quantize_e4m3.argtypes = [vp, i32, i32, i64, i64, i64, i32, i32, i32, vp, vp, vp]
     L.tcbf_quantize_e4m3.restype = i32
-    L.tcbf_steering_weights.argtypes = [vp, vp, vp, ctypes.c_double, i64, i64, i64, i32, vp, vp]
+    L.tcbf_steering_weights.argtypes = [vp, vp, vp, ctypes.c_double, i64, i64, i64, i32, i32, vp, vp]
     L.tcbf_steering_weights.restype = i32
     L.tcbf_peak_probe.argtypes = [i32, i64, i64, ctypes.c_uint32, i32, vp, i64, ctypes.POINTER(ctypes.c_double), vp]
     L.tcbf_peak_probe.restype = i32
@@ -409,10 +409,12 @@ def quantize_e4m3(src, k_major=True, layout=PLANAR, block=0, out=None, scales=No
     return out, scales
 
 
-def steering_weights(positions, directions, frequencies, wave_speed, dtype=None, out=None, stream=None):
+def steering_weights(positions, directions, frequencies, wave_speed, dtype=None, out=None, stream=None,
+                     out_layout=PLANAR):
     """Steering weights on the device: positions [K, 3], directions [M, 3],
     frequencies [batch] (float64 device tensors) -> planar [batch, 2, M, K]
-    float16 (default) or float32 weights, w = exp(+2 pi i frac(f s / c))."""
+    float16 (default) or float32 weights, w = exp(+2 pi i frac(f s / c));
+    out_layout=BLOCKED: float16 in the receiver-blocked layout (blocked_shape)."""
     import torch
     dtype = torch.float16 if dtype is None else dtype
     types = {torch.float16: SRC_F16, torch.float32: SRC_F32}
@@ -424,13 +426,17 @@ def steering_weights(positions, directions, frequencies, wave_speed, dtype=None,
     if positions.dim() != 2 or positions.shape[1] != 3 or directions.dim() != 2 or directions.shape[1] != 3:
         raise ValueError("positions [K, 3] and directions [M, 3]")
     K, M, batch = positions.shape[0], directions.shape[0], frequencies.numel()
+    if out_layout not in (PLANAR, BLOCKED) or (out_layout == BLOCKED and dtype != torch.float16):
+        raise ValueError("out_layout must be PLANAR, or BLOCKED with float16 weights")
+    shape = blocked_shape(batch, M, K) if out_layout == BLOCKED else (batch, 2, M, K)
     if out is None:
-        out = torch.empty((batch, 2, M, K), dtype=dtype, device=positions.device)
-    if tuple(out.shape) != (batch, 2, M, K) or out.dtype != dtype:
-        raise ValueError("out must be %s [batch, 2, M, K]" % dtype)
+        out = torch.empty(shape, dtype=dtype, device=positions.device)
+    if tuple(out.shape) != tuple(shape) or out.dtype != dtype:
+        raise ValueError("out must be %s %s" % (dtype, tuple(shape)))
     _check(lib().tcbf_steering_weights(_dev_ptr(positions, "positions"), _dev_ptr(directions, "directions"),
                                        _dev_ptr(frequencies, "frequencies"), float(wave_speed), int(batch), int(M),
-                                       int(K), types[dtype], _dev_ptr(out, "out"), _stream_handle(stream)),
+                                       int(K), types[dtype], int(out_layout), _dev_ptr(out, "out"),
+                                       _stream_handle(stream)),
            "tcbf_steering_weights")
     return out
 

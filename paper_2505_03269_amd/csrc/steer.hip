@@ -70,17 +70,30 @@ __device__ __forceinline__ void weight(double px, double py, double pz, double l
 // One thread per (channel, beam, 8 consecutive receivers): the 8 weights of
 // each plane go out as one 16-byte (fp16) or two 16-byte (fp32) stores when
 // K is a multiple of 8; consecutive threads take consecutive receiver groups
-// of a row, then the next row.
-template <int F16>
+// of a row, then the next row.  BL (fp16 only): the receiver-blocked layout
+// [c][2][Kb][M][32]; consecutive threads take the four 8-receiver groups of
+// a block row, then the next beam, so a wave writes 16 beams x 64 bytes in
+// one run; groups past K (up to the end of the last block) are written as
+// zeros.
+template <int F16, int BL>
 __global__ __launch_bounds__(NT) void steering_kernel(const double *__restrict__ pos, const double *__restrict__ dir,
                                                       const double *__restrict__ freq, double speed, int64_t batch,
                                                       int64_t M, int64_t K, void *__restrict__ out) {
-    const int64_t nkc = (K + 7) / 8;
+    static_assert(!BL || F16, "blocked output is fp16");
+    const int64_t nkc = BL ? (K + 31) / 32 * 4 : (K + 7) / 8;
     const int64_t gid = (int64_t)blockIdx.x * NT + threadIdx.x;
     const int64_t total = batch * M * nkc;
     if (gid >= total) return;
     int64_t kc, m, c;  // row = c M + m
-    if (total <= 0xffffffffll) {
+    if (BL) {
+        // gid = ((c Kb + kb) M + m) 4 + q, kc = 4 kb + q
+        const int64_t kb_count = nkc / 4;
+        const int64_t q = gid & 3, r = gid >> 2;
+        m = r % M;
+        const int64_t r2 = r / M;
+        c = r2 / kb_count;
+        kc = (r2 - c * kb_count) * 4 + q;
+    } else if (total <= 0xffffffffll) {
         // 32-bit divisions (a 64-bit division is a long software sequence)
         const uint32_t g = (uint32_t)gid, nk = (uint32_t)nkc, mm32 = (uint32_t)M;
         const uint32_t row = g / nk;
@@ -95,7 +108,7 @@ __global__ __launch_bounds__(NT) void steering_kernel(const double *__restrict__
     }
     const double l = dir[3 * m], mm = dir[3 * m + 1], n = dir[3 * m + 2], f = freq[c];
     const int64_t k0 = kc * 8;
-    const int cnt = K - k0 < 8 ? (int)(K - k0) : 8;
+    const int cnt = K - k0 < 8 ? (K - k0 > 0 ? (int)(K - k0) : 0) : 8;
     float cv[8], sv[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
@@ -105,10 +118,12 @@ __global__ __launch_bounds__(NT) void steering_kernel(const double *__restrict__
             weight<F16>(p[0], p[1], p[2], l, mm, n, f, speed, cv[i], sv[i]);
         }
     }
-    const int64_t re = ((c * 2 + 0) * M + m) * K + k0, im = ((c * 2 + 1) * M + m) * K + k0;
+    const int64_t kbn = (K + 31) / 32;
+    const int64_t re = BL ? (((c * 2 + 0) * kbn + k0 / 32) * M + m) * 32 + k0 % 32 : ((c * 2 + 0) * M + m) * K + k0;
+    const int64_t im = BL ? (((c * 2 + 1) * kbn + k0 / 32) * M + m) * 32 + k0 % 32 : ((c * 2 + 1) * M + m) * K + k0;
     if (F16) {
         _Float16 *o = (_Float16 *)out;
-        if (K % 8 == 0) {
+        if (BL || K % 8 == 0) {
             typedef _Float16 h8 __attribute__((ext_vector_type(8)));
             h8 a, b;
 #pragma unroll
@@ -143,17 +158,19 @@ __global__ __launch_bounds__(NT) void steering_kernel(const double *__restrict__
 
 }  // namespace
 
-int64_t steering_blocks(int64_t batch, int64_t M, int64_t K) { return (batch * M * ((K + 7) / 8) + NT - 1) / NT; }
+int64_t steering_blocks(int64_t batch, int64_t M, int64_t K, int blocked) {
+    const int64_t groups = blocked ? (K + 31) / 32 * 4 : (K + 7) / 8;
+    return (batch * M * groups + NT - 1) / NT;
+}
 
 hipError_t steering_launch(const double *pos, const double *dir, const double *freq, double speed, int64_t batch,
-                           int64_t M, int64_t K, int out_type, void *out, hipStream_t stream) {
-    const uint32_t blocks = (uint32_t)steering_blocks(batch, M, K);
-    if (out_type == TCBF_SRC_F16)
-        hipLaunchKernelGGL(steering_kernel<1>, dim3(blocks), dim3(NT), 0, stream, pos, dir, freq, speed, batch, M, K,
-                           out);
-    else
-        hipLaunchKernelGGL(steering_kernel<0>, dim3(blocks), dim3(NT), 0, stream, pos, dir, freq, speed, batch, M, K,
-                           out);
+                           int64_t M, int64_t K, int out_type, int out_layout, void *out, hipStream_t stream) {
+    const bool bl = out_layout == TCBF_BLOCKED;
+    const uint32_t blocks = (uint32_t)steering_blocks(batch, M, K, bl);
+    typedef void (*Fn)(const double *, const double *, const double *, double, int64_t, int64_t, int64_t, void *);
+    const Fn fn = out_type == TCBF_SRC_F16 ? (bl ? steering_kernel<1, 1> : steering_kernel<1, 0>)
+                                           : steering_kernel<0, 0>;
+    hipLaunchKernelGGL(fn, dim3(blocks), dim3(NT), 0, stream, pos, dir, freq, speed, batch, M, K, out);
     return hipGetLastError();
 }
 

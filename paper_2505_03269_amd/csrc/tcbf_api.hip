@@ -263,19 +263,22 @@ tcbf_status tcbf_quantize_e4m3(const void *src, int32_t src_type, int32_t src_la
 }
 
 tcbf_status tcbf_steering_weights(const double *positions, const double *directions, const double *frequencies,
-                                  double wave_speed, int64_t batch, int64_t M, int64_t K, int32_t out_type, void *W,
-                                  void *stream) {
+                                  double wave_speed, int64_t batch, int64_t M, int64_t K, int32_t out_type,
+                                  int32_t out_layout, void *W, void *stream) {
     if (positions == nullptr || directions == nullptr || frequencies == nullptr || W == nullptr)
         return TCBF_ERROR_INVALID_VALUE;
     if (out_type != TCBF_SRC_F16 && out_type != TCBF_SRC_F32) return TCBF_ERROR_INVALID_VALUE;
+    // blocked output: fp16 weights only (the layout the fp16 product reads)
+    if (out_layout != TCBF_PLANAR && !(out_layout == TCBF_BLOCKED && out_type == TCBF_SRC_F16))
+        return TCBF_ERROR_INVALID_VALUE;
     if (batch < 1 || M < 1 || K < 1) return TCBF_ERROR_INVALID_VALUE;
     if (!(wave_speed > 0.0) || wave_speed > 1e300) return TCBF_ERROR_INVALID_VALUE;
     if (!aligned8(positions) || !aligned8(directions) || !aligned8(frequencies) || !aligned16(W))
         return TCBF_ERROR_INVALID_VALUE;
-    if ((double)batch * (double)M * (double)K >= 0x1p62) return TCBF_ERROR_NOT_SUPPORTED;
-    if (tcbf::steering_blocks(batch, M, K) >= kMaxIndex) return TCBF_ERROR_NOT_SUPPORTED;
-    hipError_t e = tcbf::steering_launch(positions, directions, frequencies, wave_speed, batch, M, K, out_type, W,
-                                         (hipStream_t)stream);
+    if ((double)batch * (double)M * (double)(K + 31) >= 0x1p62) return TCBF_ERROR_NOT_SUPPORTED;
+    if (tcbf::steering_blocks(batch, M, K, out_layout == TCBF_BLOCKED) >= kMaxIndex) return TCBF_ERROR_NOT_SUPPORTED;
+    hipError_t e = tcbf::steering_launch(positions, directions, frequencies, wave_speed, batch, M, K, out_type,
+                                         out_layout, W, (hipStream_t)stream);
     return e == hipSuccess ? TCBF_SUCCESS : TCBF_ERROR_DEVICE;
 }
 

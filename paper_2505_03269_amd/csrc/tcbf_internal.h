@@ -65,10 +65,11 @@ hipError_t quantize_e4m3_launch(const void *src, int src_type, int src_layout, i
                                 int64_t K, int src_k_major, int block, int dst_layout, uint8_t *dst, void *scales,
                                 hipStream_t stream);
 
-// Steering weights from geometry (FP64 phases; fp16 or fp32 planar out).
-int64_t steering_blocks(int64_t batch, int64_t M, int64_t K);
+// Steering weights from geometry (FP64 phases; fp16 or fp32 planar out, or
+// fp16 receiver-blocked).
+int64_t steering_blocks(int64_t batch, int64_t M, int64_t K, int blocked);
 hipError_t steering_launch(const double *pos, const double *dir, const double *freq, double speed, int64_t batch,
-                           int64_t M, int64_t K, int out_type, void *out, hipStream_t stream);
+                           int64_t M, int64_t K, int out_type, int out_layout, void *out, hipStream_t stream);
 
 // 1-bit mode (packed sign bits in, int32 out).
 struct Int1Config {

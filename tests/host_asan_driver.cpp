@@ -104,8 +104,9 @@ int main() {
     expect("quant out layout", tcbf_quantize_e4m3(p, 1, 0, 1, 1, 1, 1, 0, 1, a16, p, nullptr), INV);
     expect("quant no scales", tcbf_quantize_e4m3(p, 1, 0, 1, 1, 1, 1, 0, 0, a16, nullptr, nullptr), INV);
     const double *dp = reinterpret_cast<const double *>(p);
-    expect("steer speed", tcbf_steering_weights(dp, dp, dp, 0.0, 1, 1, 1, TCBF_SRC_F16, p, nullptr), INV);
-    expect("steer out type", tcbf_steering_weights(dp, dp, dp, 3e8, 1, 1, 1, TCBF_SRC_I8, p, nullptr), INV);
+    expect("steer speed", tcbf_steering_weights(dp, dp, dp, 0.0, 1, 1, 1, TCBF_SRC_F16, TCBF_PLANAR, p, nullptr), INV);
+    expect("steer out type", tcbf_steering_weights(dp, dp, dp, 3e8, 1, 1, 1, TCBF_SRC_I8, TCBF_PLANAR, p, nullptr), INV);
+    expect("steer blocked fp32", tcbf_steering_weights(dp, dp, dp, 3e8, 1, 1, 1, TCBF_SRC_F32, TCBF_BLOCKED, p, nullptr), INV);
     expect("probe kind", tcbf_peak_probe(7, 1, 1, 0, 0, p, 4096, nullptr, nullptr), INV);
     expect("probe sink", tcbf_peak_probe(0, 4, 1, 0, 0, p, 100, nullptr, nullptr), INV);
 

@@ -167,13 +167,15 @@ def test_steering_argument_checks():
     addr = (ctypes.addressof(buf) + 15) & ~15
     p = ctypes.c_void_p(addr)
     q = ctypes.c_void_p(addr + 4)
-    assert L.tcbf_steering_weights(None, p, p, 3e8, 1, 1, 1, 1, p, None) == 1   # NULL positions
-    assert L.tcbf_steering_weights(p, p, p, 3e8, 1, 1, 1, 0, p, None) == 1      # int8 output
-    assert L.tcbf_steering_weights(p, p, p, 0.0, 1, 1, 1, 1, p, None) == 1      # wave speed 0
-    assert L.tcbf_steering_weights(p, p, p, float("nan"), 1, 1, 1, 1, p, None) == 1
-    assert L.tcbf_steering_weights(p, p, p, 3e8, 1, 0, 1, 1, p, None) == 1      # M 0
-    assert L.tcbf_steering_weights(q, p, p, 3e8, 1, 1, 1, 1, p, None) == 1      # misaligned positions
-    assert L.tcbf_steering_weights(p, p, p, 3e8, 1, 1, 1, 1, ctypes.c_void_p(addr + 8), None) == 1
+    assert L.tcbf_steering_weights(None, p, p, 3e8, 1, 1, 1, 1, 0, p, None) == 1   # NULL positions
+    assert L.tcbf_steering_weights(p, p, p, 3e8, 1, 1, 1, 0, 0, p, None) == 1      # int8 output
+    assert L.tcbf_steering_weights(p, p, p, 0.0, 1, 1, 1, 1, 0, p, None) == 1      # wave speed 0
+    assert L.tcbf_steering_weights(p, p, p, float("nan"), 1, 1, 1, 1, 0, p, None) == 1
+    assert L.tcbf_steering_weights(p, p, p, 3e8, 1, 0, 1, 1, 0, p, None) == 1      # M 0
+    assert L.tcbf_steering_weights(q, p, p, 3e8, 1, 1, 1, 1, 0, p, None) == 1      # misaligned positions
+    assert L.tcbf_steering_weights(p, p, p, 3e8, 1, 1, 1, 2, 2, p, None) == 1      # blocked fp32
+    assert L.tcbf_steering_weights(p, p, p, 3e8, 1, 1, 1, 1, 1, p, None) == 1      # interleaved out
+    assert L.tcbf_steering_weights(p, p, p, 3e8, 1, 1, 1, 1, 0, ctypes.c_void_p(addr + 8), None) == 1
 
 
 def test_peak_probe_argument_checks():

@@ -185,3 +185,22 @@ def test_rejects_bad_arguments():
         tcbf.steering_weights(pos, dirs, fr, -1.0)
     with pytest.raises(ValueError):
         tcbf.steering_weights(pos, dirs, fr, C0, dtype=torch.int8)
+
+
+@pytest.mark.parametrize("batch,M,K", [(2, 70, 576), (3, 33, 100), (1, 5, 7), (2, 130, 64), (1, 1, 1)])
+def test_blocked_output_equals_repacked_planar(batch, M, K):
+    """Weights written straight into the receiver-blocked layout are the planar
+    weights repacked by tcbf_block_weights, bit for bit (zeros past K); poison
+    in the output proves every element is written."""
+    g = np.random.default_rng([77, batch, M, K])
+    pos = np.column_stack([g.uniform(-900, 900, K), g.uniform(-900, 900, K), g.uniform(-5, 5, K)])
+    dirs = np.column_stack([g.uniform(-0.05, 0.05, M), g.uniform(-0.05, 0.05, M), np.ones(M)])
+    freqs = g.uniform(1.2e8, 1.8e8, batch)
+    P, D, F = to_dev(pos), to_dev(dirs), to_dev(freqs)
+    planar = tcbf.steering_weights(P, D, F, C0)
+    out = torch.full(tcbf.blocked_shape(batch, M, K), float("nan"), dtype=torch.float16, device="cuda:0")
+    blocked = tcbf.steering_weights(P, D, F, C0, out=out, out_layout=tcbf.BLOCKED)
+    torch.cuda.synchronize()
+    assert torch.equal(blocked.view(torch.int16), tcbf.block_weights(planar).view(torch.int16))
+    with pytest.raises(ValueError):
+        tcbf.steering_weights(P, D, F, C0, dtype=torch.float32, out_layout=tcbf.BLOCKED)
