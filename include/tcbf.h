@@ -293,8 +293,10 @@ tcbf_status tcbf_steering_weights(const double *positions, const double *directi
  * Grouped persistent launch (TCBF_F16, TCBF_F8_E4M3, TCBF_MXF8_E4M3,
  * TCBF_INT1): up to TCBF_GROUP_MAX independent problems of different shapes
  * -- channels, frames or jobs, each B = W . X in the layouts of `dtype`
- * (planar W and X for fp16; the e4m3 codes and scales of that FP8 mode; the
- * packed sign words for 1-bit, int8-MFMA variant) -- run in ONE launch.  The
+ * (planar or receiver-blocked W and planar X for fp16; the row-major or
+ * blocked e4m3 codes and the scales of that FP8 mode; the packed sign words
+ * for 1-bit, int8-MFMA variant; the `layout` field, one per launch) -- run in
+ * ONE launch.  The
  * problems' output tiles form one work list, longest receiver count first
  * (the paper's Sec. IV-C size sweep shows per-shape padding and tail effects;
  * one shared list keeps every CU busy across shape boundaries); persistent
@@ -303,8 +305,9 @@ tcbf_status tcbf_steering_weights(const double *positions, const double *directi
  * call can be captured in a HIP graph and replayed.
  *   problems: host array of `count` descriptors (1 <= count <= TCBF_GROUP_MAX);
  *     each needs batch, M, N, K >= 1, 16-byte aligned device pointers and
- *     the size limits of a plan of its dtype; fp16: K and N multiples of 8,
- *     per-channel W and X below 2 GiB, a_scale = b_scale = NULL; FP8: N a
+ *     the size limits of a plan of its dtype; fp16: N a multiple of 8 and
+ *     K too with planar W, per-channel W and X below 2 GiB, a_scale =
+ *     b_scale = NULL; every problem the same `layout`; FP8: N a
  *     multiple of 4, a_scale and b_scale as for tcbf_execute; 1-bit: K at
  *     most 2^26, a_scale = b_scale = NULL, int32 output.  Every
  *     problem's output equals its own plan's (default variant) bit for bit.
@@ -323,7 +326,10 @@ typedef struct tcbf_group_problem {
     void *C;             /* output (fp32; int32 for 1-bit), layout c_layout   */
     int64_t batch, M, N, K;
     int32_t a_shared;    /* nonzero: one W for all batch entries              */
-    int32_t reserved;    /* must be 0                                         */
+    int32_t layout;      /* TCBF_PLANAR (0) or TCBF_BLOCKED: fp16 W blocked
+                            (X planar), FP8 W and X codes blocked; 1-bit
+                            planar only.  The same for every problem of one
+                            launch.                                           */
     const void *a_scale; /* FP8 modes: W scales; fp16: NULL                   */
     const void *b_scale; /* FP8 modes: X scales; fp16: NULL                   */
 } tcbf_group_problem;

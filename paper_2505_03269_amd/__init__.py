@@ -57,7 +57,7 @@ class PlanDesc(ctypes.Structure):
 class GroupProblem(ctypes.Structure):
     _fields_ = [("A", ctypes.c_void_p), ("B", ctypes.c_void_p), ("C", ctypes.c_void_p),
                 ("batch", ctypes.c_int64), ("M", ctypes.c_int64), ("N", ctypes.c_int64), ("K", ctypes.c_int64),
-                ("a_shared", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("a_shared", ctypes.c_int32), ("layout", ctypes.c_int32),
                 ("a_scale", ctypes.c_void_p), ("b_scale", ctypes.c_void_p)]
 
 
@@ -467,15 +467,18 @@ def peak_probe(kind, blocks, iterations, operand_bits=None, random=False, sink=N
     return ops.value, values, marks
 
 
-def group_execute(problems, c_layout=PLANAR, workspace=None, device=0, stream=None, dtype=F16):
+def group_execute(problems, c_layout=PLANAR, workspace=None, device=0, stream=None, dtype=F16, layout=PLANAR):
     """One grouped persistent launch over up to GROUP_MAX problems of one dtype.
 
     dtype F16: problems are (W, X, C) or (W, X, C, a_shared) device tensors
-    with W float16 [batch|1, 2, M, K], X float16 [batch, 2, K, N].
+    with W float16 [batch|1, 2, M, K] (layout=BLOCKED: blocked_shape(batch|1,
+    M, K), from block_weights), X float16 [batch, 2, K, N].
     dtype F8_E4M3 / MXF8_E4M3: (W, X, C, a_scale, b_scale) or
     (W, X, C, a_scale, b_scale, a_shared) with e4m3 codes W uint8
     [batch|1, 2, M, Kp], X uint8 [batch, 2, N, Kp] and the scales of that
-    mode (see Plan.shape_a_scale / shape_b_scale).
+    mode (see Plan.shape_a_scale / shape_b_scale); layout=BLOCKED: blocked
+    codes (f8_codes_shape) and the true K after the scales,
+    (W, X, C, a_scale, b_scale, K[, a_shared]).
     dtype INT1: (W, X, C, K) or (W, X, C, K, a_shared) with packed sign words
     W int32 [batch|1, 2, M, kw], X int32 [batch, 2, N, kw] and the true K.
     C: float32 (int32 for INT1) [batch, 2, M, N] (planar) or [batch, M, N, 2]
@@ -489,17 +492,22 @@ def group_execute(problems, c_layout=PLANAR, workspace=None, device=0, stream=No
     f8 = _is_f8(dtype)
     if dtype not in (F16, INT1) and not f8:
         raise ValueError("grouped launches take F16, F8_E4M3, MXF8_E4M3 or INT1")
+    if layout not in (PLANAR, BLOCKED) or (layout == BLOCKED and dtype == INT1):
+        raise ValueError("layout must be PLANAR, or BLOCKED for fp16 and FP8")
+    blocked = layout == BLOCKED
     arr = (GroupProblem * len(problems))()
     for i, pr in enumerate(problems):
         W, X, C = pr[0], pr[1], pr[2]
-        nfix = 5 if f8 else 4 if dtype == INT1 else 3   # fields before the optional a_shared
+        # fields before the optional a_shared
+        nfix = (6 if blocked else 5) if f8 else 4 if dtype == INT1 else 3
         shared = bool(pr[nfix]) if len(pr) > nfix else False
+        nb = lambda b: 1 if shared else b  # noqa: E731
         elem = torch.uint8 if f8 else torch.int32 if dtype == INT1 else torch.float16
         cdt = torch.int32 if dtype == INT1 else torch.float32
         if W.dtype != elem or X.dtype != elem or C.dtype != cdt:
             raise ValueError("problem %d: W, X %s and C %s expected" % (i, elem, cdt))
-        if W.dim() != 4 or X.dim() != 4 or W.shape[1] != 2 or X.shape[1] != 2:
-            raise ValueError("problem %d: planar W [b, 2, M, K] and X [b, 2, ., .] expected" % i)
+        if W.dim() not in (4, 5) or X.dim() not in (4, 5) or W.shape[1] != 2 or X.shape[1] != 2:
+            raise ValueError("problem %d: W [b, 2, ...] and X [b, 2, ...] expected" % i)
         if dtype == INT1:
             if len(pr) < 4:
                 raise ValueError("problem %d: 1-bit problems are (W, X, C, K[, a_shared])" % i)
@@ -507,28 +515,41 @@ def group_execute(problems, c_layout=PLANAR, workspace=None, device=0, stream=No
             K = int(pr[3])
             if not 0 < K <= 32 * kw or (K + 31) // 32 != kw:
                 raise ValueError("problem %d: K does not match the word count" % i)
+            M = W.shape[2]
+            want_w = (nb(batch), 2, M, kw)
+        elif f8 and blocked:
+            if len(pr) < 6:
+                raise ValueError("problem %d: blocked FP8 problems are (W, X, C, a_scale, b_scale, K[, a_shared])" % i)
+            K = int(pr[5])
+            batch, N, M = X.shape[0], X.shape[3], W.shape[3]
+            if tuple(X.shape) != f8_codes_shape(batch, N, K, BLOCKED):
+                raise ValueError("problem %d: X must be %s" % (i, f8_codes_shape(batch, N, K, BLOCKED)))
+            want_w = f8_codes_shape(nb(batch), M, K, BLOCKED)
         elif f8:
             batch, N, K = X.shape[0], X.shape[2], X.shape[3]
             if K % 32:
                 raise ValueError("problem %d: FP8 rows must be Kp = 32 * ceil(K / 32) bytes" % i)
+            M = W.shape[2]
+            want_w = (nb(batch), 2, M, K)
         else:
             batch, K, N = X.shape[0], X.shape[2], X.shape[3]
-        M = W.shape[2]
-        if W.shape[3] != X.shape[3 if dtype != F16 else 2] or W.shape[0] != (1 if shared else batch):
-            raise ValueError("problem %d: W does not match X" % i)
+            M = W.shape[3] if blocked else W.shape[2]
+            want_w = blocked_shape(nb(batch), M, K) if blocked else (nb(batch), 2, M, K)
+        if tuple(W.shape) != tuple(want_w):
+            raise ValueError("problem %d: W must have shape %s to match X" % (i, tuple(want_w)))
         want = (batch, 2, M, N) if c_layout == PLANAR else (batch, M, N, 2)
         if tuple(C.shape) != want:
             raise ValueError("problem %d: C must have shape %s" % (i, want))
         sa = sb = None
         if f8:
             st = torch.float32 if dtype == F8_E4M3 else torch.uint8
-            for t, shape, nm in ((pr[3], _scale_shape(dtype, 1 if shared else batch, M, K), "a_scale"),
+            for t, shape, nm in ((pr[3], _scale_shape(dtype, nb(batch), M, K), "a_scale"),
                                  (pr[4], _scale_shape(dtype, batch, N, K), "b_scale")):
                 if t.dtype != st or tuple(t.shape) != tuple(shape):
                     raise ValueError("problem %d: %s must be %s %s" % (i, nm, st, tuple(shape)))
             sa, sb = _dev_ptr(pr[3], "a_scale").value, _dev_ptr(pr[4], "b_scale").value
         arr[i] = GroupProblem(_dev_ptr(W, "W").value, _dev_ptr(X, "X").value, _dev_ptr(C, "C").value,
-                              batch, M, N, K, int(shared), 0, sa, sb)
+                              batch, M, N, K, int(shared), int(layout), sa, sb)
     if workspace is None:
         workspace = torch.empty(GROUP_WORKSPACE_BYTES, dtype=torch.uint8, device="cuda:%d" % device)
     if workspace.numel() * workspace.element_size() < GROUP_WORKSPACE_BYTES:

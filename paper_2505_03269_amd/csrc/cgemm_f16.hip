@@ -843,7 +843,8 @@ __global__ __launch_bounds__(256, 2) void cgemm_f16_split_kernel(const uint16_t 
 // the plain kernel); a workgroup takes the next tile index from a device
 // counter, finds its problem among the problem table's first-tile offsets,
 // runs the same tile code as the fast kernel (128 x 128, 32 receivers per
-// stage, 2-deep ring) and asks again until the list is exhausted.  The table
+// stage, 2-deep ring; planar or receiver-blocked W, one layout per launch)
+// and asks again until the list is exhausted.  The table
 // travels in the kernel arguments, so a captured graph replays it unchanged.
 struct GroupProblem {
     const uint16_t *A;
@@ -859,7 +860,7 @@ struct GroupArgs {
     int count, total_tiles;
 };
 
-template <int CIL>
+template <int CIL, int AB>
 __global__ __launch_bounds__(256, 2) void cgemm_f16_group_kernel(const GroupArgs args,
                                                                  unsigned int *__restrict__ counter) {
     TCBF_FAST_LDS(2, 32, 2)
@@ -881,8 +882,8 @@ __global__ __launch_bounds__(256, 2) void cgemm_f16_group_kernel(const GroupArgs
         const int rem = local - c * per_c;
         int tm, tn;
         tile_coords(rem, q.tiles_m, q.tiles_n, tm, tn);
-        fast_tile<2, 32, 2, CIL, 0>(q.A, q.B, q.C, q.M, q.N, q.K, q.a_shared, c, tm, tn, lds0, lds1, lds2, lds3, lds4,
-                                 lds5);
+        fast_tile<2, 32, 2, CIL, AB>(q.A, q.B, q.C, q.M, q.N, q.K, q.a_shared, c, tm, tn, lds0, lds1, lds2, lds3,
+                                     lds4, lds5);
         // next_tile is rewritten only after the tile's own barriers, which
         // every wave passes after reading it
     }
@@ -1014,7 +1015,7 @@ hipError_t f16_launch(const Problem &p, const F16Config &cfg, const void *A, con
     return hipGetLastError();
 }
 
-bool f16_group_problem_ok(const Problem &p) { return p.a_layout == TCBF_PLANAR && fast_ok(p); }
+bool f16_group_problem_ok(const Problem &p) { return fast_ok(p); }
 
 int64_t f16_group_tiles(const Problem &p) { return p.batch * ((p.M + BM - 1) / BM) * ((p.N + BN - 1) / BN); }
 
@@ -1043,10 +1044,12 @@ hipError_t f16_group_launch(const Problem *probs, const void *const *A, const vo
     args.count = count;
     args.total_tiles = (int)first;
     hipLaunchKernelGGL(group_reset_kernel, dim3(1), dim3(1), 0, stream, counter);
-    if (c_layout == TCBF_INTERLEAVED)
-        hipLaunchKernelGGL(cgemm_f16_group_kernel<1>, dim3((uint32_t)grid), dim3(NT), 0, stream, args, counter);
-    else
-        hipLaunchKernelGGL(cgemm_f16_group_kernel<0>, dim3((uint32_t)grid), dim3(NT), 0, stream, args, counter);
+    // one operand layout per launch (the API checks it)
+    const bool ab = probs[order[0]].a_layout == TCBF_BLOCKED, cil = c_layout == TCBF_INTERLEAVED;
+    void (*fn)(const GroupArgs, unsigned int *) =
+        ab ? (cil ? cgemm_f16_group_kernel<1, 1> : cgemm_f16_group_kernel<0, 1>)
+           : (cil ? cgemm_f16_group_kernel<1, 0> : cgemm_f16_group_kernel<0, 0>);
+    hipLaunchKernelGGL(fn, dim3((uint32_t)grid), dim3(NT), 0, stream, args, counter);
     return hipGetLastError();
 }
 

@@ -338,7 +338,7 @@ struct F8GroupArgs {
     int count, total_tiles;
 };
 
-template <int CIL, int MX>
+template <int CIL, int MX, int BL>
 __global__ __launch_bounds__(NT, 2) void cgemm_f8_group_kernel(const F8GroupArgs args,
                                                                 unsigned int *__restrict__ counter) {
     TCBF_F8_LDS(2, MX)
@@ -361,7 +361,7 @@ __global__ __launch_bounds__(NT, 2) void cgemm_f8_group_kernel(const F8GroupArgs
         const int rem = local - c * per_c;
         int tm, tn;
         tile_coords(rem, q.tiles_m, q.tiles_n, tm, tn);
-        f8_tile<2, CIL, MX, 0>(q.A, q.B, q.C, q.a_scale, q.b_scale, q.M, q.N, q.Kp, q.a_shared, c, tm, tn, lds0, lds1,
+        f8_tile<2, CIL, MX, BL>(q.A, q.B, q.C, q.a_scale, q.b_scale, q.M, q.N, q.Kp, q.a_shared, c, tm, tn, lds0, lds1,
                             lds2, lds3, slabs);
         // next_tile is rewritten only after the tile's own barriers, which
         // every wave passes after reading it
@@ -454,9 +454,13 @@ hipError_t f8_group_launch(const Problem *probs, const void *const *A, const voi
     args.total_tiles = (int)first;
     hipLaunchKernelGGL(f8_group_reset_kernel, dim3(1), dim3(1), 0, stream, counter);
     const bool cil = c_layout == TCBF_INTERLEAVED;
+    // one operand layout per launch (the API checks it)
+    const bool bl = probs[order[0]].a_layout == TCBF_BLOCKED;
     void (*fn)(const F8GroupArgs, unsigned int *) =
-        mx ? (cil ? cgemm_f8_group_kernel<1, 1> : cgemm_f8_group_kernel<0, 1>)
-           : (cil ? cgemm_f8_group_kernel<1, 0> : cgemm_f8_group_kernel<0, 0>);
+        bl ? (mx ? (cil ? cgemm_f8_group_kernel<1, 1, 1> : cgemm_f8_group_kernel<0, 1, 1>)
+                 : (cil ? cgemm_f8_group_kernel<1, 0, 1> : cgemm_f8_group_kernel<0, 0, 1>))
+           : (mx ? (cil ? cgemm_f8_group_kernel<1, 1, 0> : cgemm_f8_group_kernel<0, 1, 0>)
+                 : (cil ? cgemm_f8_group_kernel<1, 0, 0> : cgemm_f8_group_kernel<0, 0, 0>));
     hipLaunchKernelGGL(fn, dim3((uint32_t)grid), dim3(NT), 0, stream, args, counter);
     return hipGetLastError();
 }

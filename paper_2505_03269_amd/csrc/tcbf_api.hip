@@ -310,14 +310,20 @@ tcbf_status tcbf_group_execute(int32_t device, int32_t dtype, int32_t c_layout, 
     const void *SB[TCBF_GROUP_MAX];
     int order[TCBF_GROUP_MAX];
     int64_t total = 0;
+    // one operand layout per launch (it picks the kernel): planar, or blocked
+    // fp16 weights / blocked FP8 codes
+    const int32_t layout = problems[0].layout;
+    if (layout != TCBF_PLANAR && !(layout == TCBF_BLOCKED && dtype != TCBF_INT1)) return TCBF_ERROR_INVALID_VALUE;
+    const bool blocked = layout == TCBF_BLOCKED;
     for (int i = 0; i < count; ++i) {
         const tcbf_group_problem &g = problems[i];
-        if (g.A == nullptr || g.B == nullptr || g.C == nullptr || g.reserved != 0) return TCBF_ERROR_INVALID_VALUE;
+        if (g.A == nullptr || g.B == nullptr || g.C == nullptr || g.layout != layout) return TCBF_ERROR_INVALID_VALUE;
         if (!aligned16(g.A) || !aligned16(g.B) || !aligned16(g.C)) return TCBF_ERROR_INVALID_VALUE;
         if (g.batch < 1 || g.M < 1 || g.N < 1 || g.K < 1) return TCBF_ERROR_INVALID_VALUE;
-        probs[i] = tcbf::Problem{g.batch, g.M, g.N, g.K, TCBF_PLANAR, TCBF_PLANAR, c_layout, g.a_shared != 0};
+        probs[i] = tcbf::Problem{g.batch, g.M, g.N, g.K, layout, (blocked && is_f8(dtype)) ? TCBF_BLOCKED : TCBF_PLANAR,
+                                 c_layout, g.a_shared != 0};
         if (dtype == TCBF_F16) {
-            if (g.K % 8 != 0 || g.N % 8 != 0) return TCBF_ERROR_INVALID_VALUE;
+            if ((!blocked && g.K % 8 != 0) || g.N % 8 != 0) return TCBF_ERROR_INVALID_VALUE;
             if (g.a_scale != nullptr || g.b_scale != nullptr) return TCBF_ERROR_INVALID_VALUE;
             if (!tcbf::f16_group_problem_ok(probs[i])) return TCBF_ERROR_NOT_SUPPORTED;
             total += tcbf::f16_group_tiles(probs[i]);
@@ -331,7 +337,7 @@ tcbf_status tcbf_group_execute(int32_t device, int32_t dtype, int32_t c_layout, 
             if (g.a_scale == nullptr || g.b_scale == nullptr) return TCBF_ERROR_INVALID_VALUE;
             if (!aligned16(g.a_scale) || !aligned16(g.b_scale)) return TCBF_ERROR_INVALID_VALUE;
             // the plan limits: byte offsets of per-channel operands and output fit 31 bits
-            const int64_t kp = tcbf::f8_kp(g.K);
+            const int64_t kp = blocked ? (tcbf::f8_kp(g.K) + 63) / 64 * 64 : tcbf::f8_kp(g.K);
             if (2 * g.M * kp >= kMaxIndex || 2 * g.N * kp >= kMaxIndex || 8 * g.M * g.N >= kMaxIndex)
                 return TCBF_ERROR_NOT_SUPPORTED;
             total += tcbf::f8_group_tiles(probs[i]);

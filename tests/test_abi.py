@@ -206,24 +206,34 @@ def test_group_argument_checks():
     assert L.tcbf_group_execute(0, tcbf.F16, 0, one, 0, p, None) == 1                  # count 0
     assert L.tcbf_group_execute(0, tcbf.F16, 0, one, tcbf.GROUP_MAX + 1, p, None) == 1
     assert L.tcbf_group_execute(0, 9, 0, one, 1, p, None) == 1                         # unknown dtype
-    int1 = dict(A=addr, B=addr, C=addr, batch=1, M=8, N=8, K=8, a_shared=0, reserved=0)
+    int1 = dict(A=addr, B=addr, C=addr, batch=1, M=8, N=8, K=8, a_shared=0, layout=0)
     for bad, want in ((dict(a_scale=addr), 1), (dict(K=(1 << 26) + 1), 2), (dict(M=1 << 16, N=1 << 15), 2)):
         d = dict(int1)
         d.update(bad)
         arr = (tcbf.GroupProblem * 1)(tcbf.GroupProblem(**d))
         assert L.tcbf_group_execute(0, tcbf.INT1, 0, arr, 1, p, None) == want, bad
     assert L.tcbf_group_execute(0, tcbf.F16, 0, one, 1, ctypes.c_void_p(addr + 4), None) == 1
-    for bad in (dict(K=12), dict(N=4), dict(batch=0), dict(reserved=1), dict(A=addr + 2), dict(a_scale=addr)):
-        d = dict(A=addr, B=addr, C=addr, batch=1, M=8, N=8, K=8, a_shared=0, reserved=0)
+    for bad in (dict(K=12), dict(N=4), dict(batch=0), dict(layout=1), dict(layout=3), dict(A=addr + 2),
+                dict(a_scale=addr), dict(layout=2, N=4)):
+        d = dict(A=addr, B=addr, C=addr, batch=1, M=8, N=8, K=8, a_shared=0, layout=0)
         d.update(bad)
         arr = (tcbf.GroupProblem * 1)(tcbf.GroupProblem(**d))
         assert L.tcbf_group_execute(0, tcbf.F16, 0, arr, 1, p, None) == 1, bad
+    # blocked layouts: not for 1-bit; one layout per launch
+    d = dict(int1)
+    d.update(layout=2)
+    arr = (tcbf.GroupProblem * 1)(tcbf.GroupProblem(**d))
+    assert L.tcbf_group_execute(0, tcbf.INT1, 0, arr, 1, p, None) == 1
+    a = dict(A=addr, B=addr, C=addr, batch=1, M=8, N=8, K=8, a_shared=0, layout=0)
+    b = dict(a, layout=2)
+    two = (tcbf.GroupProblem * 2)(tcbf.GroupProblem(**a), tcbf.GroupProblem(**b))
+    assert L.tcbf_group_execute(0, tcbf.F16, 0, two, 2, p, None) == 1
     # FP8: scales required and aligned, N a multiple of 4, the plan's size limits
     for dt in (tcbf.F8_E4M3, tcbf.MXF8_E4M3):
         for bad, want in ((dict(), 1), (dict(a_scale=addr), 1), (dict(a_scale=addr, b_scale=addr + 4), 1),
                           (dict(a_scale=addr, b_scale=addr, N=6), 1),
                           (dict(a_scale=addr, b_scale=addr, M=1 << 14, K=1 << 16), 2)):
-            d = dict(A=addr, B=addr, C=addr, batch=1, M=8, N=8, K=40, a_shared=0, reserved=0)
+            d = dict(A=addr, B=addr, C=addr, batch=1, M=8, N=8, K=40, a_shared=0, layout=0)
             d.update(bad)
             arr = (tcbf.GroupProblem * 1)(tcbf.GroupProblem(**d))
             assert L.tcbf_group_execute(0, dt, 0, arr, 1, p, None) == want, (dt, bad)

@@ -246,3 +246,96 @@ def test_group_int1_equals_single_plans_and_oracle(layout):
         gr, gi = (g64[:, 0], g64[:, 1]) if layout == tcbf.PLANAR else (g64[..., 0], g64[..., 1])
         assert np.array_equal(gr, rr) and np.array_equal(gi, ri), (b, M, N, K)
 
+
+
+# --------------------------------------------------------------------------
+# receiver-blocked operands in a grouped launch
+# --------------------------------------------------------------------------
+
+MIX_BLOCKED = MIX + [(2, 200, 136, 100), (1, 70, 64, 7)]  # receiver counts that are not multiples of 8
+
+
+@pytest.mark.parametrize("layout", [tcbf.PLANAR, tcbf.INTERLEAVED])
+def test_group_blocked_weights_equal_single_plans(layout):
+    """fp16 with receiver-blocked W: every problem equals its planar single
+    plan's output bit for bit (blocked single plans where K is not a multiple
+    of 8, which planar W cannot take on the fast path)."""
+    cases = []
+    for i, (b, M, N, K) in enumerate(MIX_BLOCKED):
+        shared = i == 3
+        W, X, Wd, Xd, C = make(60 + i, b, M, N, K, shared, layout)
+        cases.append((b, M, N, K, shared, Wd, tcbf.block_weights(Wd), Xd, C))
+    log("blocked group of %d problems, layout %d" % (len(cases), layout))
+    tcbf.group_execute([(c[6], c[7], c[8], c[4]) for c in cases], c_layout=layout, layout=tcbf.BLOCKED)
+    torch.cuda.synchronize()
+    for (b, M, N, K, shared, Wd, Wb, Xd, C) in cases:
+        if K % 8 == 0:
+            ref = single(Wd, Xd, b, M, N, K, shared, layout)
+        else:
+            plan = tcbf.Plan(b, M, N, K, tcbf.F16, a_layout=tcbf.BLOCKED, c_layout=layout, a_shared=shared)
+            ref = plan.empty_output()
+            plan.execute(Wb, Xd, ref)
+        torch.cuda.synchronize()
+        got = C.cpu().numpy()
+        assert not np.isnan(got).any(), (b, M, N, K)
+        assert np.array_equal(got, ref.cpu().numpy()), (b, M, N, K)
+
+
+@pytest.mark.parametrize("dtype", [tcbf.F8_E4M3, tcbf.MXF8_E4M3])
+def test_group_f8_blocked_codes_equal_single_plans(dtype):
+    """FP8 with receiver-blocked codes (the quantiser writes them): every
+    problem equals its row-major single plan's output bit for bit."""
+    block = 0 if dtype == tcbf.F8_E4M3 else 32
+    BL = tcbf.BLOCKED
+    cases = []
+    for i, (b, M, N, K) in enumerate(MIX + [(2, 70, 36, 40), (1, 64, 64, 100)]):
+        shared = i == 3
+        nw = 1 if shared else b
+        W = to_dev(wl.random_f16_case(80 + i, nw, M, 8, K)[0])
+        X = to_dev(wl.random_f16_case(90 + i, b, 8, N, K)[1])
+        pw, px = tcbf.quantize_e4m3(W, k_major=True, block=block), tcbf.quantize_e4m3(X, k_major=False, block=block)
+        bw = tcbf.quantize_e4m3(W, k_major=True, block=block, out_layout=BL)
+        bx = tcbf.quantize_e4m3(X, k_major=False, block=block, out_layout=BL)
+        C = torch.full((b, 2, M, N), float("nan"), device="cuda:0")
+        cases.append((b, M, N, K, shared, pw, px, bw, bx, C))
+    log("blocked f8 group dtype %d: %d problems" % (dtype, len(cases)))
+    tcbf.group_execute([(c[7][0], c[8][0], c[9], c[7][1], c[8][1], c[3], c[4]) for c in cases], dtype=dtype,
+                       layout=BL)
+    torch.cuda.synchronize()
+    for (b, M, N, K, shared, pw, px, bw, bx, C) in cases:
+        plan = tcbf.Plan(b, M, N, K, dtype, a_shared=shared)
+        ref = plan.empty_output()
+        plan.execute(pw[0], px[0], ref, pw[1], px[1])
+        torch.cuda.synchronize()
+        got = C.cpu().numpy()
+        assert not np.isnan(got).any(), (b, M, N, K)
+        assert np.array_equal(got, ref.cpu().numpy()), (b, M, N, K)
+
+
+def test_group_blocked_graph_replays_match_eager():
+    """A captured blocked-weight grouped launch replays to the eager result."""
+    cases = []
+    for i, (b, M, N, K) in enumerate(MIX[:4]):
+        W, X, Wd, Xd, C = make(100 + i, b, M, N, K)
+        cases.append((tcbf.block_weights(Wd), Xd, C))
+    ws = torch.zeros(tcbf.GROUP_WORKSPACE_BYTES, dtype=torch.uint8, device="cuda:0")
+    probs = [(a, x, c) for a, x, c in cases]
+    tcbf.group_execute(probs, workspace=ws, layout=tcbf.BLOCKED)
+    torch.cuda.synchronize()
+    eager = [c.clone() for _, _, c in cases]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            tcbf.group_execute(probs, workspace=ws, layout=tcbf.BLOCKED, stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    for r in range(3):
+        for _, _, c in cases:
+            c.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for c, e in zip([c for _, _, c in cases], eager):
+            assert torch.equal(c, e), "replay %d differs" % r
