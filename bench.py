@@ -437,9 +437,14 @@ def bench_secondary(steps, serving=True, copy_gbs=None):
             for pl, (Wg, Xg, Cg) in zip(plans, probs):
                 pl.execute(Wg, Xg, Cg)
         ms_s = time_launches(each, st, 1)
+        # the same launch with receiver-blocked weights (repacked once)
+        probs_b = [(tcbf.block_weights(Wg), Xg, Cg) for (Wg, Xg, Cg) in probs]
+        ms_gb = time_launches(lambda: tcbf.group_execute(probs_b, workspace=ws, layout=tcbf.BLOCKED), st, 1)
+        del probs_b
         tops = ops / (ms_g * 1e-3) / 1e12
         out.append({"workload": "grouped fp16: " + label, "kernel": "cgemm_f16_group_kernel", "value": round(tops, 1),
                     "unit": "TeraOps/s", "ms_per_launch": round(ms_g, 4),
+                    "blocked_weights_tops": round(ops / (ms_gb * 1e-3) / 1e12, 1),
                     "separate_launches_tops": round(ops / (ms_s * 1e-3) / 1e12, 1),
                     "separate_launches_ms": round(ms_s, 4), "dtype": "f16",
                     "roofline": {"bound": "mfma", "achieved": round(tops, 1), "peak": PEAK_F16_TFLOPS,
