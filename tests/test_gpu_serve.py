@@ -16,7 +16,11 @@ from paper_2505_03269_amd import serve  # noqa: E402
 
 @pytest.fixture(scope="module")
 def server():
-    return serve.Server(pool_per_dtype=3, budget_bytes=1 << 30, streams=3, max_slots=24, seed=3)
+    srv = serve.Server(pool_per_dtype=3, budget_bytes=1 << 30, streams=3, max_slots=24, seed=3)
+    # a serving process warms up before it takes traffic: the overlap checks
+    # below are about steady state, not a fresh process's first launches
+    srv.warmup()
+    return srv
 
 
 def test_results_same_alone_and_in_the_mix(server):
@@ -49,7 +53,9 @@ def test_mixed_results_match_oracle(server):
         X = serve.job_input(job, server.device).cpu().numpy().astype(np.float64)
         got = job.out.cpu().numpy()
         if job.dtype == tcbf.F16:
-            W = ws.A.cpu().numpy().astype(np.float64)
+            # resident weights are receiver-blocked [1, 2, Kb, M, 32]: back to [1, 2, M, K]
+            Wb = ws.A.cpu().numpy().astype(np.float64)
+            W = Wb.transpose(0, 1, 3, 2, 4).reshape(1, 2, job.M, -1)[..., :job.K]
             Wc, Xc = W[:, 0] + 1j * W[:, 1], X[:, 0] + 1j * X[:, 1]
             check_fp_full(got[:, 0] + 1j * got[:, 1], oracle.cgemm(Wc, Xc), np.matmul(np.abs(Wc), np.abs(Xc)), job.K)
         else:
