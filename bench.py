@@ -520,28 +520,40 @@ def sweep(steps):
     g = torch.Generator(device="cuda:0")
     g.manual_seed(11)
     for name, dt, batch, M, N, K in shapes:
-        plan = tcbf.Plan(batch, M, N, K, dt)
+        # fp16: receiver-blocked weights (repacked once), planar timed beside
+        lay = tcbf.BLOCKED if dt == tcbf.F16 else tcbf.PLANAR
+        plan = tcbf.Plan(batch, M, N, K, dt, a_layout=lay)
         info = plan.info()
+        ms_p = None
         if dt == tcbf.INT1:
             A = torch.randint(-2**31, 2**31 - 1, plan.shape_a(), dtype=torch.int32, device="cuda:0", generator=g)
             B = torch.randint(-2**31, 2**31 - 1, plan.shape_b(), dtype=torch.int32, device="cuda:0", generator=g)
             peak = PEAK_I8_TOPS
+            C = plan.empty_output()
+            ms = time_launches(lambda: plan.execute(A, B, C), steps, 2)
         else:
-            A = torch.randn(plan.shape_a(), device="cuda:0", generator=g).half()
+            Ap = torch.randn((batch, 2, M, K), device="cuda:0", generator=g).half()
+            A = tcbf.block_weights(Ap)
             B = torch.randint(-127, 128, plan.shape_b(), device="cuda:0", generator=g).half()
             peak = PEAK_F16_TFLOPS
-        C = plan.empty_output()
-        ms = time_launches(lambda: plan.execute(A, B, C), steps, 2)
+            C = plan.empty_output()
+            plan_p = tcbf.Plan(batch, M, N, K, dt)
+            ms, ms_p = time_interleaved([lambda: plan.execute(A, B, C), lambda: plan_p.execute(Ap, B, C)],
+                                        steps, 2)
+            del Ap
         tops = info["useful_ops"] / (ms * 1e-3) / 1e12
         gbs = info["algorithmic_bytes"] / (ms * 1e-3) / 1e9
         ai = info["useful_ops"] / info["algorithmic_bytes"]
         ridge = peak * 1e3 / PEAK_HBM_GBS
         bound = "mfma" if ai >= ridge else "hbm"
         frac = tops / peak if bound == "mfma" else gbs / PEAK_HBM_GBS
-        print(json.dumps({"sweep": name, "batch": batch, "M": M, "N": N, "K": K, "dtype": "f16" if dt == tcbf.F16 else "int1",
-                          "kernel": info["kernel_name"], "variant": info["variant"], "ms": round(ms, 4),
-                          "tops": round(tops, 1), "gbs_algorithmic": round(gbs, 1), "ops_per_byte": round(ai, 1),
-                          "bound": bound, "frac_of_bound": round(frac, 4)}), flush=True)
+        rec = {"sweep": name, "batch": batch, "M": M, "N": N, "K": K, "dtype": "f16" if dt == tcbf.F16 else "int1",
+               "kernel": info["kernel_name"], "variant": info["variant"], "ms": round(ms, 4),
+               "tops": round(tops, 1), "gbs_algorithmic": round(gbs, 1), "ops_per_byte": round(ai, 1),
+               "bound": bound, "frac_of_bound": round(frac, 4)}
+        if ms_p is not None:
+            rec.update({"weights": "blocked", "planar_weights_tops": round(info["useful_ops"] / (ms_p * 1e-3) / 1e12, 1)})
+        print(json.dumps(rec), flush=True)
         del A, B, C
         torch.cuda.empty_cache()
 
