@@ -228,7 +228,7 @@ def bench_c2(steps, warmup):
     import torch
     import paper_2505_03269_amd as tcbf
     import workloads as wl
-    cfg = wl.CONFIGS[2]
+    cfg = wl.WORKLOADS["radio-astro-fp16"]
     t0 = time.perf_counter()
     W, X = wl.generate_c2()
     log("c2 inputs generated in %.1f s" % (time.perf_counter() - t0))
@@ -266,7 +266,7 @@ def bench_c1_latency(launches=200):
     import torch
     import paper_2505_03269_amd as tcbf
     import workloads as wl
-    cfg = wl.CONFIGS[1]
+    cfg = wl.WORKLOADS["plain-fp16-4ch"]
     chans = [wl.c1_channel(c) for c in range(cfg["batch"])]
     W = np.stack([w for w, _ in chans])
     X = np.stack([x for _, x in chans])
@@ -302,7 +302,7 @@ def bench_secondary(steps, serving=True, copy_gbs=None):
     st = max(3, steps // 4)
     out.append(bench_c1_latency())
     # 1-bit: 64 x 2048 x 8192 x 8192 from random words
-    cfg = wl.CONFIGS[3]
+    cfg = wl.WORKLOADS["one-bit"]
     Wp, Xp = wl.generate_c3()
     A = torch.from_numpy(Wp.view(np.int32)).to("cuda:0")
     B = torch.from_numpy(Xp.view(np.int32)).to("cuda:0")
@@ -359,7 +359,7 @@ def bench_secondary(steps, serving=True, copy_gbs=None):
     del src, dst, A, B
     torch.cuda.empty_cache()
     # ultrasound shape, fp16: 1 x 32768 x 8192 x 256
-    cfg = wl.CONFIGS[4]
+    cfg = wl.WORKLOADS["ultrasound-fp16"]
     W, X = wl.c4_channel(0)
     # the model matrix is tiled once before the experiment (Sec. V-A): blocked
     # weights, with the planar-weight product beside it
@@ -573,7 +573,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the beamforming product shards over channels with no "
-              "exchange, and this build runs and reports a single MI355X (got --gpus %d)" % args.gpus,
+              "exchange, and this benchmark runs and reports a single MI355X (got --gpus %d)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
     if int(os.environ.get("WORLD_SIZE", "1")) > 1:

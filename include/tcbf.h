@@ -42,7 +42,7 @@ extern "C" {
 typedef enum tcbf_status {
     TCBF_SUCCESS = 0,
     TCBF_ERROR_INVALID_VALUE = 1, /* bad size, pointer, alignment or enum value  */
-    TCBF_ERROR_NOT_SUPPORTED = 2, /* valid request this build/device cannot run  */
+    TCBF_ERROR_NOT_SUPPORTED = 2, /* valid request the library/device cannot run */
     TCBF_ERROR_OUT_OF_MEMORY = 3, /* host allocation for a plan failed           */
     TCBF_ERROR_DEVICE = 4,        /* HIP runtime error (no device, launch failed) */
     TCBF_ERROR_INTERNAL = 5

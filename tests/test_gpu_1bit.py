@@ -155,13 +155,13 @@ def test_pack_then_gemm_end_to_end():
 
 
 # ---------------------------------------------------------------------------
-# config 3 at full size
+# the one-bit workload at full size
 # ---------------------------------------------------------------------------
 
 def test_c3_full_size():
     """64 x 2048 x 8192 x 8192: channel 0 compared in full, plus 100k sampled
     entries over all channels (tile edges included), for the default plan."""
-    cfg = wl.CONFIGS[3]
+    cfg = wl.WORKLOADS["one-bit"]
     batch, M, N, K = cfg["batch"], cfg["M"], cfg["N"], cfg["K"]
     log("c3 full size: generating inputs")
     Wp, Xp = wl.generate_c3()

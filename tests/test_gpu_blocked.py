@@ -119,11 +119,11 @@ def test_blocked_rejects_bad_tensors():
 
 
 def test_c2_full_size_blocked_equals_planar():
-    """Config 2 at its full size in the launch configuration the benchmark
+    """The radio-astronomy workload at its full size in the launch configuration the benchmark
     times (blocked weights, default variant): the whole output equals the
     planar-weight product bit for bit (that product is checked against the
     oracle on sampled entries by the fp16 tests)."""
-    cfg = wl.CONFIGS[2]
+    cfg = wl.WORKLOADS["radio-astro-fp16"]
     log("c2 blocked: generating inputs")
     W, X = wl.generate_c2()
     A, B = to_dev(W), to_dev(X)

@@ -43,7 +43,7 @@ def oracle_ref(W, X, shared=False):
 
 
 def test_c1_full_output():
-    """Config 1 (4 channels, 128 x 64 x 512), every output entry."""
+    """The plain 4-channel workload (128 x 64 x 512), every output entry."""
     chans = [wl.c1_channel(c) for c in range(4)]
     W = np.stack([w for w, _ in chans])
     X = np.stack([x for _, x in chans])
@@ -170,9 +170,9 @@ def _sampled_parity(W, X, C, K, shared=False, count=20000):
 
 
 def test_c2_full_size_sampled():
-    """Config 2 at its full size (256 x 1024 x 576 x 4096), the plan the
+    """The radio-astronomy workload at full size (256 x 1024 x 576 x 4096), the plan the
     benchmark times; 20k random entries plus tile edges of every channel."""
-    cfg = wl.CONFIGS[2]
+    cfg = wl.WORKLOADS["radio-astro-fp16"]
     log("c2 full size: generating inputs")
     W, X = wl.generate_c2()
     plan = tcbf.Plan(cfg["batch"], cfg["M"], cfg["N"], cfg["K"], tcbf.F16)
@@ -187,8 +187,8 @@ def test_c2_full_size_sampled():
 
 
 def test_c4_full_size_sampled():
-    """Config 4 (1 x 32768 x 8192 x 256), fp16."""
-    cfg = wl.CONFIGS[4]
+    """The ultrasound workload (1 x 32768 x 8192 x 256), fp16."""
+    cfg = wl.WORKLOADS["ultrasound-fp16"]
     log("c4 full size: generating inputs")
     W, X = wl.c4_channel(0)
     W, X = W[None], X[None]

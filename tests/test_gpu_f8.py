@@ -367,7 +367,7 @@ def test_rejects_bad_scales():
 
 
 # --------------------------------------------------------------------------
-# config 4 (ultrasound, 1 x 32768 x 8192 x 256) at full size
+# the ultrasound workload (1 x 32768 x 8192 x 256) at full size
 # --------------------------------------------------------------------------
 
 @pytest.fixture(scope="module")
@@ -385,7 +385,7 @@ def test_c4_full_size_sampled(c4_inputs, dtype):
     the dequantised inputs.  The error against the unquantised inputs is
     logged as the stated accuracy of the mode."""
     W, X = c4_inputs
-    cfg = wl.CONFIGS[4]
+    cfg = wl.WORKLOADS["ultrasound-fp16"]
     M, N, K = cfg["M"], cfg["N"], cfg["K"]
     block = 0 if dtype == tcbf.F8_E4M3 else 32
     log("c4 fp8 dtype=%d: quantise + execute" % dtype)

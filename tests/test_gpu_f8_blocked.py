@@ -126,10 +126,10 @@ def test_mixed_layouts_rejected():
 
 @pytest.mark.parametrize("dtype", [tcbf.F8_E4M3, tcbf.MXF8_E4M3])
 def test_c4_full_size_blocked_equals_planar(dtype):
-    """Config 4 (1 x 32768 x 8192 x 256) in the launch configuration the
+    """The ultrasound workload (1 x 32768 x 8192 x 256) in the launch configuration the
     benchmark times: the whole output equals the planar product bit for bit."""
     block = 0 if dtype == tcbf.F8_E4M3 else 32
-    cfg = wl.CONFIGS[4]
+    cfg = wl.WORKLOADS["ultrasound-fp16"]
     log("c4 f8 blocked: dtype=%d" % dtype)
     W, X = wl.c4_channel(0)
     A, B = to_dev(W[None]), to_dev(X[None])
