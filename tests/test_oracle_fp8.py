@@ -51,6 +51,27 @@ def test_quantiser_rounding_matches_torch_cast():
     assert np.array_equal(qr, ref_r) and np.array_equal(qi, ref_i)
 
 
+@pytest.mark.parametrize("k", [-20, -7, -1, 1, 3, 12, 40])
+def test_quantiser_at_power_of_two_scales_matches_torch_cast(k):
+    """Rows whose largest magnitude is 448 * 2^k: the scale is exactly 2^k,
+    and every code must equal torch's nearest-even cast of x * 2^-k (exact in
+    fp32), ties and subnormals included -- the rule pinned away from unit
+    scale, on an independent implementation of the rounding."""
+    g = np.random.default_rng(100 + k)
+    rows, cols = 24, 130
+    base = np.concatenate([g.uniform(-448, 448, (rows, cols - 10)), g.normal(0, 1e-2, (rows, 10))], axis=1)
+    base[:, :6] = [448.0, 1.0625, 1.1875, 17.0, 2.0 ** -10, 3 * 2.0 ** -10]  # ties and subnormals
+    base[::2, 0] = -448.0
+    re = np.ldexp(base, k).astype(np.float32)
+    im = np.ldexp(np.roll(base, 3, axis=1) * 0.5, k).astype(np.float32)
+    qr, qi, sc = oracle.quantize_e4m3_rows(re, im)
+    assert np.all(sc == np.float32(np.ldexp(1.0, k)))
+    for v, q in ((re, qr), (im, qi)):
+        y = np.ldexp(v.astype(np.float64), -k).astype(np.float32)
+        ref = torch.from_numpy(y).to(torch.float8_e4m3fn).view(torch.uint8).numpy()
+        assert np.array_equal(q, ref)
+
+
 def test_quantiser_scale_and_error_bound():
     g = np.random.default_rng(1)
     re = g.normal(0, 3.0, (50, 300)).astype(np.float32)
