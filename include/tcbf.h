@@ -88,7 +88,7 @@ typedef enum tcbf_src_type {
  *                       entries at k >= K must be zero (tcbf_block_weights
  *                       writes them so).  A layout only; needs b_layout
  *                       TCBF_PLANAR and N a multiple of 8 (any K); variants
- *                       0 (default), 2, 5, 6, 8.  Results are bitwise
+ *                       0 (default), 2, 5, 6, 8, 9.  Results are bitwise
  *                       identical to the planar layout's.
  *   B = X   planar      [batch][2][K][N]   N contiguous
  *           interleaved [batch][K][N][2]
@@ -144,16 +144,20 @@ typedef struct tcbf_plan_desc {
     int32_t variant;      /* 0 = automatic kernel choice; >0 forces a variant  */
 } tcbf_plan_desc;
 /* Variants.  TCBF_F16: 1 register-staged kernel for any layout and alignment;
- * 2..8 the direct-to-LDS kernel (planar or blocked W, planar X, N a multiple
- * of 8, K a multiple of 8 for planar W): 2 (default) 128 x 128 tile, 32
+ * 2..9 the direct-to-LDS kernels (planar or blocked W, planar X, N a
+ * multiple of 8, K a multiple of 8 for planar W): 2 128 x 128 tile, 32
  * receivers per stage, two-deep ring; 3 / 4 16 receivers, four / five deep;
  * 5 32 receivers, three deep; 6 / 7 a 256 x 128 tile (512 threads); 8 separate
- * rings for W (two deep) and X (three deep).  TCBF_F8_E4M3 / TCBF_MXF8_E4M3:
- * 1 (default) two-deep ring, 2 three-deep.  TCBF_INT1: 1 (default) int8
- * matrix instructions on +-1 expanded to {0, 1}, 2 XOR + popcount on the
- * vector ALU.  Every variant of a dtype gives bitwise identical results.
- * A variant that does not accept the problem makes tcbf_plan fail with
- * TCBF_ERROR_INVALID_VALUE. */
+ * rings for W (two deep) and X (three deep); 9 a persistent 256 x 128 tile
+ * whose two wave groups alternate matrix and data phases (one workgroup per
+ * CU).  The default is 9 for problems with at least as many 256 x 128 tiles
+ * as the device has CUs, else 2.  TCBF_F8_E4M3 / TCBF_MXF8_E4M3: 1 (default)
+ * two-deep ring, 2 three-deep.  TCBF_INT1: 1 int8 matrix instructions on
+ * +-1 expanded to {0, 1}, 2 XOR + popcount on the vector ALU, 3 e2m1 (4-bit
+ * float) matrix instructions on the +-1 values, for K <= 2^23 with
+ * ceil(K/32) a multiple of 4 (default where it applies, else 1).  Every
+ * variant of a dtype gives bitwise identical results.  A variant that does
+ * not accept the problem makes tcbf_plan fail with TCBF_ERROR_INVALID_VALUE. */
 
 typedef struct tcbf_plan_s *tcbf_plan_t;
 

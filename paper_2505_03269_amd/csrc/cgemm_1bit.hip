@@ -29,7 +29,7 @@
 // with Kp the number of bit positions processed and Kpad = Kp - K.
 #include <cstring>
 
-#include "tcbf_internal.h"
+#include "tcbf_tile.h"
 
 namespace tcbf {
 namespace {
@@ -378,17 +378,265 @@ __global__ __launch_bounds__(V_NT, 2) void cgemm_1bit_valu_kernel(
         }
 }
 
+// ---------------------------------------------------------------------------
+// Variant 3: e2m1 matrix instructions on the +-1 values themselves.
+// ---------------------------------------------------------------------------
+// Every sign bit becomes the 4-bit float +1 (code 0x2) or -1 (code 0xA), and
+// v_mfma_scale_f32_32x32x64_f8f6f4 (e2m1 operands, unit scales) multiplies
+// them with the complex product of Sec. III-B: Re += Wr.Xr + (-Wi).Xi,
+// Im += Wr.Xi + Wi.Xr, -Wi by flipping the sign bit of every code.  Every
+// partial sum is an integer of magnitude at most 2K, exact in the fp32
+// accumulators while 2K <= 2^24, so the plan takes this variant for K <= 2^23
+// only.  Bits of receivers past K are cleared in both operands, as the
+// paper's padding does (Sec. III-D): each such receiver then adds
+// (-1)(-1) + (-(-1))(-1) = 0 to Re and 2 to Im, and the epilogue takes
+// 2 K_pad off Im (K_pad: receivers processed past K).  A word
+// expands into four dwords of eight codes: code i of dword d is bit 4i + d of
+// the word, the same fixed permutation of the word's 32 receivers for both
+// operands, which leaves every sum unchanged.  The instruction takes 64
+// receivers per lane pair: lanes 0-31 supply one word and lanes 32-63 another.
+//
+// Workgroup: 128 beams x 128 samples, 4 waves of 64 x 64, two workgroups per
+// CU.  A stage holds 16 words (512 receivers) of every row of both operands
+// (2 operands x 2 planes x 128 rows x 64 bytes = 32 KiB), moved with
+// direct-to-LDS loads through a two-deep ring; the 16-byte chunks of a row sit
+// XOR-swizzled by (row / 4) % 4, so the fragment reads (16 rows per phase)
+// meet no bank conflicts.  Lane half h of a wave takes words 8h .. 8h + 7 of
+// each staged row: step s of the stage contracts words s and 8 + s (any
+// split works, as long as both operands use the same one).  The
+// matrix instructions take W as the first operand, so the tile is stored
+// straight from the accumulators in whole 128-byte row runs.
+constexpr int F_BKW = 16;                // words per stage
+constexpr int F_ROWB = F_BKW * 4;        // staged row bytes
+constexpr int F_PLANE = U_BM * F_ROWB;   // 8 KiB
+constexpr int F_STAGE = 4 * F_PLANE;     // W planes then X planes: 32 KiB
+constexpr int F_MAX_K = 1 << 23;         // exact fp32 sums
+
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16v __attribute__((ext_vector_type(16)));
+
+// Four dwords of e2m1 codes from one word: +1 (0x2) for a set bit, -1 (0xA)
+// for a clear one; code i of dword d takes bit 4i + d.
+__device__ __forceinline__ i32x8 e2m1_expand(uint32_t x) {
+    const uint32_t n = ~x;  // bit 3 of a code is the sign: set for a clear bit
+    i32x8 v;
+    v[0] = (int)(((n << 3) & 0x88888888u) | 0x22222222u);
+    v[1] = (int)(((n << 2) & 0x88888888u) | 0x22222222u);
+    v[2] = (int)(((n << 1) & 0x88888888u) | 0x22222222u);
+    v[3] = (int)((n & 0x88888888u) | 0x22222222u);
+    v[4] = v[5] = v[6] = v[7] = 0;
+    return v;
+}
+
+__device__ __forceinline__ i32x8 e2m1_negate(i32x8 v) {
+#pragma unroll
+    for (int d = 0; d < 4; ++d) v[d] ^= (int)0x88888888u;
+    return v;
+}
+
+__device__ __forceinline__ f32x16v mma4(const i32x8 &a, const i32x8 &b, const f32x16v &c) {
+    // format 4 = e2m1 for both operands, E8M0 scales 127 = 2^0
+    return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 4, 4, 0, 127, 0, 127);
+}
+
+template <int CIL>
+__global__ __launch_bounds__(U_NT, 2) void cgemm_1bit_fp4_kernel(const uint32_t *__restrict__ A,
+                                                                 const uint32_t *__restrict__ B,
+                                                                 int32_t *__restrict__ C, int M, int N, int K,
+                                                                 int kw, int a_shared, int tiles_m, int tiles_n,
+                                                                 int nblocks) {
+    __shared__ __attribute__((aligned(1024))) char lds0[F_STAGE];
+    __shared__ __attribute__((aligned(1024))) char lds1[F_STAGE];
+    const int t = (int)xcd_remap(blockIdx.x, nblocks);
+    const int per_c = tiles_m * tiles_n;
+    const int c = t / per_c;
+    int tm, tn;
+    tile_coords(t - c * per_c, tiles_m, tiles_n, tm, tn);
+    const int m0 = tm * U_BM, n0 = tn * U_BN;
+
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int hl = lane >> 5, l32 = lane & 31;
+
+    // Loads: wave w moves the 8 KiB plane (w % 2) of operand (w / 2) in eight
+    // 1 KiB pieces of 16 rows; lane l fills LDS slot l of a piece: row l / 4,
+    // stored chunk l % 4, which holds global chunk (l % 4) ^ ((row / 4) % 4).
+    const int op = wave >> 1, plane = wave & 1;
+    const int rows = op ? N : M, r0 = op ? n0 : m0;
+    const uint32_t *base = op ? B + (int64_t)c * 2 * N * kw : A + (a_shared ? (int64_t)0 : (int64_t)c * 2 * M * kw);
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void *)base, 0, 8 * rows * kw, tile::RSRC_FLAGS);
+    const int lrow = lane >> 2;
+    const int gch = (lane & 3) ^ ((lane >> 4) & 3);
+    const uint32_t voff = (uint32_t)(((plane * rows + r0 + lrow) * kw + gch * 4) * 4);
+    const int lds_piece0 = (op * 2 + plane) * F_PLANE;
+    const int nk = (kw + F_BKW - 1) / F_BKW;
+    // A stage past the last is issued too, all out of range (zeros into a
+    // buffer nobody reads again): the code has no branch around the loads,
+    // so nothing can be moved across the stage barriers.
+    auto issue = [&](char *buf, int kt) __attribute__((always_inline)) {
+        const int k0w = kt < nk ? kt * F_BKW : 0;
+        const bool chunk_ok = kt < nk && k0w + gch * 4 < kw;  // kw % 4 == 0: a chunk is wholly in or out
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            // per-lane range check in the lane offset; the uniform offset
+            // (< 2^31, so OOB plus it cannot wrap into range) stays uniform
+            const bool ok = chunk_ok && r0 + q * 16 + lrow < rows;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (TCBF_LDS_AS void *)(buf + lds_piece0 + q * 1024), 16,
+                                                     ok ? voff : tile::OOB, (q * 16 * kw + k0w) * 4, 0, 0);
+        }
+    };
+
+    // fragment offsets: row R of a plane, chunk (2h or 2h + 1) ^ ((R / 4) % 4)
+    int fo[2][2][2];  // [operand][sub-tile][chunk]
+#pragma unroll
+    for (int o = 0; o < 2; ++o)
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int R = (o ? wn : wm) * 64 + i * 32 + l32;
+#pragma unroll
+            for (int ch = 0; ch < 2; ++ch)
+                fo[o][i][ch] = o * 2 * F_PLANE + R * F_ROWB + (((2 * hl + ch) ^ ((R >> 2) & 3)) * 16);
+        }
+
+    f32x16v acc_r[2][2], acc_i[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            acc_r[i][j] = (f32x16v){};
+            acc_i[i][j] = (f32x16v){};
+        }
+
+    auto compute = [&](const char *st, int kt) __attribute__((always_inline)) {
+#pragma unroll
+        for (int ch = 0; ch < 2; ++ch) {
+            __builtin_amdgcn_sched_barrier(0);
+            // this lane's words of steps 4ch .. 4ch + 3: [operand][sub-tile][plane]
+            tile::u32x4 wd[2][2][2];
+#pragma unroll
+            for (int o = 0; o < 2; ++o)
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int p = 0; p < 2; ++p)
+                        wd[o][i][p] = *reinterpret_cast<const tile::u32x4 *>(st + fo[o][i][ch] + p * F_PLANE);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                // bits of receivers past K cleared in both operands (their
+                // -1 x -1 products are taken out of Im in the epilogue)
+                const int valid = K - 32 * (kt * F_BKW + 8 * hl + 4 * ch + q);
+                const uint32_t vm = valid >= 32 ? 0xffffffffu : valid <= 0 ? 0u : (1u << valid) - 1u;
+                i32x8 ar[2], ai[2], br[2], bi[2];
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    ar[i] = e2m1_expand(wd[0][i][0][q] & vm);
+                    ai[i] = e2m1_expand(wd[0][i][1][q] & vm);
+                    br[i] = e2m1_expand(wd[1][i][0][q] & vm);
+                    bi[i] = e2m1_expand(wd[1][i][1][q] & vm);
+                }
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        acc_r[i][j] = mma4(ar[i], br[j], acc_r[i][j]);
+                        acc_i[i][j] = mma4(ar[i], bi[j], acc_i[i][j]);
+                        acc_i[i][j] = mma4(ai[i], br[j], acc_i[i][j]);
+                    }
+                    ai[i] = e2m1_negate(ai[i]);  // -Wi
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) acc_r[i][j] = mma4(ai[i], bi[j], acc_r[i][j]);
+                }
+                // one step's operands live at a time (two workgroups per CU
+                // leave 256 registers per lane)
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+    };
+
+    // two-deep ring: stage kt in buffer kt % 2, stage kt + 1 in flight
+    constexpr int kWait0 = tile::vmcnt_imm(0);
+    issue(lds0, 0);
+    int kt = 0;
+    auto step = [&](char *cur, char *nxt) __attribute__((always_inline)) {
+        // this wave's loads of stage kt landed; then every wave's, and stage
+        // kt - 1 fully read.  The scheduling barriers keep the previous
+        // stage's matrix instructions from being moved past the wait.
+        __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_s_waitcnt(kWait0);
+        asm volatile("s_barrier" ::: "memory");
+        __builtin_amdgcn_sched_barrier(0);
+        issue(nxt, kt + 1);
+        compute(cur, kt);
+        ++kt;
+    };
+    for (; kt + 2 <= nk;) {
+        step(lds0, lds1);
+        step(lds1, lds0);
+    }
+    if (kt < nk) step(lds0, lds1);
+
+    // store from the accumulators: element r of lane l = sample l % 32 of
+    // beam 8 (r / 4) + 4 (l / 32) + r % 4 of the 32 x 32 sub-tile
+    __builtin_amdgcn_s_waitcnt(kWait0);  // the zero fills past the last stage landed
+    // every processed receiver past K (cleared bits, -1 in both operands)
+    // added (-1)(-1) + (-1)(-1) = 2 to Im and (-1)(-1) - (-1)(-1) = 0 to Re
+    const int kpad2 = 2 * (nk * F_BKW * 32 - K);
+    int32_t *Cc = C + (int64_t)c * 2 * M * N;
+    const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc((void *)Cc, 0, 8 * M * N, tile::RSRC_FLAGS);
+    const int mw = m0 + wm * 64, nw = n0 + wn * 64;
+    const bool whole = mw + 64 <= M && nw + 64 <= N;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int n = nw + 32 * j + l32;
+            const int mb = mw + 32 * i + 4 * hl;
+            const bool n_ok = n < N;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int m = mb + 8 * (r >> 2) + (r & 3);
+                const bool ok = whole || (n_ok && m < M);
+                const int re = (int)acc_r[i][j][r], im = (int)acc_i[i][j][r] - kpad2;
+                if (CIL) {
+                    const uint32_t off = ok ? (uint32_t)((m * N + n) * 8) : tile::OOB;
+                    const tile::u32x2 v = {(uint32_t)re, (uint32_t)im};
+                    __builtin_amdgcn_raw_buffer_store_b64(v, rc, off, 0, tile::kStoreStreaming);
+                } else {
+                    const uint32_t off = ok ? (uint32_t)((m * N + n) * 4) : tile::OOB;
+                    const uint32_t offi = ok ? (uint32_t)(((M + m) * N + n) * 4) : tile::OOB;
+                    __builtin_amdgcn_raw_buffer_store_b32((uint32_t)re, rc, off, 0, tile::kStoreStreaming);
+                    __builtin_amdgcn_raw_buffer_store_b32((uint32_t)im, rc, offi, 0, tile::kStoreStreaming);
+                }
+            }
+        }
+}
+
 }  // namespace
 
+// Variant 3 (e2m1): exact fp32 sums (K <= 2^23), whole 16-byte chunks of
+// packed words (kw a multiple of 4), and 32-bit byte offsets for every
+// per-channel operand and output.
+static bool fp4_ok(const Problem &p) {
+    const int64_t kw = (p.K + 31) / 32, lim = (int64_t)1 << 31;
+    return p.K <= F_MAX_K && kw % 4 == 0 && 8 * p.M * kw < lim && 8 * p.N * kw < lim && 8 * p.M * p.N < lim;
+}
+
 bool int1_select(const Problem &p, int forced_variant, Int1Config *cfg) {
-    (void)p;
-    int v = forced_variant == 0 ? 1 : forced_variant;
+    // default: e2m1 where it applies (measured 1.5x the int8 variant on the
+    // 64 x 2048 x 8192 x 8192 workload), else int8
+    int v = forced_variant == 0 ? (fp4_ok(p) ? 3 : 1) : forced_variant;
     if (v == 1) {
         *cfg = Int1Config{1, U_BM, U_BN, U_BKW, U_NT};
         return true;
     }
     if (v == 2) {
         *cfg = Int1Config{2, V_BM, V_BN, V_BKW, V_NT};
+        return true;
+    }
+    if (v == 3 && fp4_ok(p)) {
+        *cfg = Int1Config{3, U_BM, U_BN, F_BKW, U_NT};
         return true;
     }
     return false;
@@ -399,7 +647,9 @@ int64_t int1_workgroups(const Problem &p, const Int1Config &cfg) {
 }
 
 const char *int1_kernel_name(const Int1Config &cfg) {
-    return cfg.variant == 1 ? "cgemm_1bit_mfma_kernel" : "cgemm_1bit_valu_kernel";
+    return cfg.variant == 1 ? "cgemm_1bit_mfma_kernel"
+           : cfg.variant == 3 ? "cgemm_1bit_fp4_kernel"
+                              : "cgemm_1bit_valu_kernel";
 }
 
 hipError_t int1_launch(const Problem &p, const Int1Config &cfg, const uint32_t *A, const uint32_t *B,
@@ -410,7 +660,11 @@ hipError_t int1_launch(const Problem &p, const Int1Config &cfg, const uint32_t *
     const int64_t nblocks = p.batch * tiles_m * tiles_n;
     const int vec = (kw % 4) == 0;
     const bool cil = p.c_layout == TCBF_INTERLEAVED;
-    if (cfg.variant == 1) {
+    if (cfg.variant == 3) {
+        auto fn = cil ? cgemm_1bit_fp4_kernel<1> : cgemm_1bit_fp4_kernel<0>;
+        hipLaunchKernelGGL(fn, dim3((uint32_t)nblocks), dim3(U_NT), 0, stream, A, B, C, (int)p.M, (int)p.N, (int)p.K,
+                           (int)kw, p.a_shared, tiles_m, tiles_n, (int)nblocks);
+    } else if (cfg.variant == 1) {
         auto fn = cil ? cgemm_1bit_mfma_kernel<1> : cgemm_1bit_mfma_kernel<0>;
         hipLaunchKernelGGL(fn, dim3((uint32_t)nblocks), dim3(U_NT), 0, stream, A, B, C, p.M, p.N, p.K,
                            kw, p.a_shared, tiles_m, tiles_n, nblocks, vec);

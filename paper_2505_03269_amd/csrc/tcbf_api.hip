@@ -113,7 +113,7 @@ tcbf_status tcbf_plan(const tcbf_plan_desc *desc, tcbf_plan_t *plan) {
     if (st != TCBF_SUCCESS) return st;
 
     tcbf::Problem p{desc->batch, desc->M, desc->N, desc->K,
-                    desc->a_layout, desc->b_layout, desc->c_layout, desc->a_shared != 0};
+                    desc->a_layout, desc->b_layout, desc->c_layout, desc->a_shared != 0, desc->device};
     tcbf_plan_s tmp;
     memset(&tmp, 0, sizeof(tmp));
     memcpy(&tmp.desc, desc, kDescV1);
@@ -321,7 +321,7 @@ tcbf_status tcbf_group_execute(int32_t device, int32_t dtype, int32_t c_layout, 
         if (!aligned16(g.A) || !aligned16(g.B) || !aligned16(g.C)) return TCBF_ERROR_INVALID_VALUE;
         if (g.batch < 1 || g.M < 1 || g.N < 1 || g.K < 1) return TCBF_ERROR_INVALID_VALUE;
         probs[i] = tcbf::Problem{g.batch, g.M, g.N, g.K, layout, (blocked && is_f8(dtype)) ? TCBF_BLOCKED : TCBF_PLANAR,
-                                 c_layout, g.a_shared != 0};
+                                 c_layout, g.a_shared != 0, device};
         if (dtype == TCBF_F16) {
             if ((!blocked && g.K % 8 != 0) || g.N % 8 != 0) return TCBF_ERROR_INVALID_VALUE;
             if (g.a_scale != nullptr || g.b_scale != nullptr) return TCBF_ERROR_INVALID_VALUE;

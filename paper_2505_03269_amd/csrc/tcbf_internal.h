@@ -14,6 +14,7 @@ struct Problem {
     int64_t batch, M, N, K;
     int a_layout, b_layout, c_layout;  // tcbf_layout
     int a_shared;
+    int device;  // HIP device ordinal the problem runs on
 };
 
 // FP16 mode (16-bit in, fp32 out).

@@ -62,7 +62,7 @@ def _plan_status(**kw):
 
 @pytest.mark.parametrize("bad", [
     dict(struct_size=4), dict(batch=0), dict(M=0), dict(N=-1), dict(K=0), dict(dtype=7),
-    dict(a_layout=3), dict(b_layout=-1), dict(c_layout=5), dict(variant=-1), dict(variant=9),
+    dict(a_layout=3), dict(b_layout=-1), dict(c_layout=5), dict(variant=-1), dict(variant=10),
     # the receiver-blocked layout: fp16 weights only, fast kernel with 32 receivers per stage
     dict(b_layout=tcbf.BLOCKED), dict(c_layout=tcbf.BLOCKED), dict(dtype=tcbf.INT1, a_layout=tcbf.BLOCKED),
     dict(dtype=tcbf.F8_E4M3, a_layout=tcbf.BLOCKED), dict(dtype=tcbf.MXF8_E4M3, a_layout=tcbf.BLOCKED),

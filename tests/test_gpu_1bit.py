@@ -1,5 +1,8 @@
-"""GPU parity of the 1-bit mode (sign packing and both GEMM variants) against
-the int64 oracle, through the C ABI.  Every comparison is bit-exact."""
+"""GPU parity of the 1-bit mode (sign packing and the three GEMM variants)
+against the int64 oracle, through the C ABI.  Every comparison is bit-exact.
+Variant 3 (e2m1 matrix instructions) takes K <= 2^23 with a whole number of
+16-byte chunks per packed row (ceil(K / 32) a multiple of 4); other shapes
+must be refused by the plan."""
 import numpy as np
 import pytest
 
@@ -12,13 +15,22 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 import paper_2505_03269_amd as tcbf  # noqa: E402
 
-VARIANTS = [1, 2]
+VARIANTS = [1, 2, 3]
+
+
+def fp4_accepts(K, M=1, N=1):
+    kw = (K + 31) // 32
+    return K <= (1 << 23) and kw % 4 == 0 and 8 * M * kw < 2**31 and 8 * N * kw < 2**31 and 8 * M * N < 2**31
 
 
 def run_1bit(Wp, Xp, K, variant, c_layout=tcbf.PLANAR, shared=False):
     """Wp [nb,2,M,kw], Xp [batch,2,N,kw] uint32 -> int64 (Re, Im) [batch,M,N]."""
     batch, _, N, kw = Xp.shape
     M = Wp.shape[2]
+    if variant == 3 and not fp4_accepts(K, M, N):
+        with pytest.raises(tcbf.TcbfError):
+            tcbf.Plan(batch, M, N, K, tcbf.INT1, c_layout=c_layout, a_shared=shared, variant=variant)
+        pytest.skip("variant 3 refuses K=%d (checked)" % K)
     plan = tcbf.Plan(batch, M, N, K, tcbf.INT1, c_layout=c_layout, a_shared=shared, variant=variant)
     A, B = words_to_dev(Wp), words_to_dev(Xp)
     C = plan.empty_output()
@@ -40,6 +52,7 @@ SHAPES = [
     (1, 1, 1, 1), (1, 5, 7, 31), (2, 33, 17, 32), (1, 17, 33, 33), (1, 128, 128, 128), (2, 129, 65, 63),
     (1, 64, 64, 64), (1, 65, 64, 65), (1, 130, 257, 127), (1, 100, 100, 129), (1, 64, 200, 577),
     (1, 256, 130, 1000), (1, 70, 90, 8191), (1, 128, 128, 8192),
+    (2, 129, 65, 100), (1, 130, 257, 511), (1, 17, 33, 1280), (1, 200, 136, 3060), (3, 64, 64, 2048),
 ]
 
 
@@ -56,7 +69,7 @@ def test_gemm_bit_exact(variant, batch, M, N, K):
 
 @pytest.mark.parametrize("variant", VARIANTS)
 def test_interleaved_output_and_shared(variant):
-    K = 300
+    K = 300 if variant != 3 else 490
     Wp, Xp = wl.random_bits_case(5, 3, 70, 50, K, shared_w=True)
     rr, ri = oracle_1bit(Wp, Xp, K, shared=True)
     gr, gi = run_1bit(Wp, Xp, K, variant, c_layout=tcbf.INTERLEAVED, shared=True)
@@ -66,7 +79,7 @@ def test_interleaved_output_and_shared(variant):
 @pytest.mark.parametrize("variant", VARIANTS)
 def test_nonzero_pad_bits_are_ignored(variant):
     """Bits past K in the last word do not affect the result."""
-    K = 45
+    K = 45 if variant != 3 else 109
     Wp, Xp = wl.random_bits_case(8, 1, 40, 40, K)
     rr, ri = oracle_1bit(Wp, Xp, K)
     Wd, Xd = Wp.copy(), Xp.copy()
@@ -146,6 +159,8 @@ def test_pack_then_gemm_end_to_end():
     sgn = lambda a: np.where(a >= 0, 1, -1).astype(np.int8)  # noqa: E731
     rr, ri = oracle.cgemm_1bit_def(sgn(wsrc[..., 0]), sgn(wsrc[..., 1]), sgn(xsrc[..., 0]), sgn(xsrc[..., 1]))
     for v in VARIANTS:
+        if v == 3 and not fp4_accepts(K, M, N):
+            continue
         plan = tcbf.Plan(batch, M, N, K, tcbf.INT1, variant=v)
         C = plan.empty_output()
         plan.execute(Wd, Xd, C)
@@ -195,6 +210,11 @@ def test_longest_supported_k(variant):
     popcount form on every output."""
     M = N = 32
     K = (1 << 26) - 3
+    if variant == 3:
+        # its own limit: 2^23 (exact fp32 sums); past it the plan refuses
+        with pytest.raises(tcbf.TcbfError):
+            tcbf.Plan(1, M, N, (1 << 23) + 128, tcbf.INT1, variant=3)
+        K = 32 * 262140 - 3  # a ragged last word, and a last stage only partly inside K
     kw = (K + 31) // 32
     g = torch.Generator(device="cuda:0")
     g.manual_seed(41)

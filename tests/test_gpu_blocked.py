@@ -76,10 +76,14 @@ def test_blocked_products_match_planar(batch, M, N, K):
     check_fp_full(planar, oracle.cgemm(Wc, Xc), np.matmul(np.abs(Wc), np.abs(Xc)), K)
     Wb = tcbf.block_weights(to_dev(W))
     Xd = to_dev(X)
-    for v in (0, 2, 5, 6, 8):
+    names = {8: "cgemm_f16_split_kernel", 9: "cgemm_f16_pp_kernel"}
+    for v in (0, 2, 5, 6, 8, 9):
         got, plan = _run(Wb, Xd, M, K, tcbf.BLOCKED, variant=v)
-        assert plan.info()["kernel_name"] == ("cgemm_f16_split_kernel" if v == 8 else "cgemm_f16_fast_kernel")
+        assert plan.info()["kernel_name"] == names.get(v, "cgemm_f16_fast_kernel")
         assert np.array_equal(got, planar), "blocked weights, variant %d, differ from planar" % v
+        if v == 9:
+            got_il, _ = _run(Wb, Xd, M, K, tcbf.BLOCKED, c_layout=tcbf.INTERLEAVED, variant=v)
+            assert np.array_equal(got_il, planar), "blocked weights, variant 9, interleaved output differs"
     got_il, _ = _run(Wb, Xd, M, K, tcbf.BLOCKED, c_layout=tcbf.INTERLEAVED)
     assert np.array_equal(got_il, planar)
 
@@ -130,7 +134,7 @@ def test_c2_full_size_blocked_equals_planar():
     del W, X
     pp = tcbf.Plan(cfg["batch"], cfg["M"], cfg["N"], cfg["K"], tcbf.F16)
     pb = tcbf.Plan(cfg["batch"], cfg["M"], cfg["N"], cfg["K"], tcbf.F16, a_layout=tcbf.BLOCKED)
-    assert pb.info()["variant"] == pp.info()["variant"] == 2
+    assert pb.info()["variant"] == pp.info()["variant"] == 9
     Ab = tcbf.block_weights(A)
     Cp, Cb = pp.empty_output(), pb.empty_output()
     log("c2 blocked: execute both")

@@ -222,7 +222,7 @@ ALIGNED_SHAPES = [(1, 1, 8, 8), (1, 130, 136, 40), (2, 200, 264, 72), (1, 129, 8
                   (1, 257, 392, 576), (2, 128, 128, 8), (1, 300, 264, 112)]
 
 
-FAST_VARIANTS = [2, 3, 4, 5, 6, 7, 8]
+FAST_VARIANTS = [2, 3, 4, 5, 6, 7, 8, 9]
 
 
 @pytest.mark.parametrize("batch,M,N,K", ALIGNED_SHAPES)

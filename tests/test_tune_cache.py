@@ -27,4 +27,4 @@ def test_cache_round_trip(tmp_path):
 
 def test_fp16_sweep_starts_from_table3_point():
     assert tune.CANDIDATES[F16][0] == 2
-    assert sorted(tune.CANDIDATES[F16]) == [1, 2, 3, 4, 5, 6, 7, 8]
+    assert sorted(tune.CANDIDATES[F16]) == [1, 2, 3, 4, 5, 6, 7, 8, 9]
