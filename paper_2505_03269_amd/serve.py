@@ -4,8 +4,8 @@ A job asks for B = W . X with one of the resident weight sets (fp16, FP8 or
 1-bit) and its own data X of N samples.  The server
 
   * keeps every weight set resident on the device in the form its kernel
-    reads (fp16 planes; e4m3 codes with per-row scales; packed sign words),
-    built once at start-up;
+    reads (receiver-blocked fp16 weights; receiver-blocked e4m3 codes with
+    per-row scales; packed sign words), built once at start-up;
   * admits arrived jobs in arrival order while the device-memory budget and
     the slot count allow (a job's budget is its input and output buffers);
   * launches the admitted jobs as soon as a stream is free: the jobs of a
@@ -16,7 +16,14 @@ A job asks for B = W . X with one of the resident weight sets (fp16, FP8 or
     sees its batch complete (an event query, no blocking wait);
   * reports per-job latency (completion seen by the host minus arrival, both
     on the host clock, queueing included), p50 / p99, and throughput as useful
-    operations (8 per complex multiply-accumulate) over the makespan.
+    operations (8 per complex multiply-accumulate) over the makespan; and
+    each batch's device-time interval (timing events on its stream), from
+    which device_overlap() measures how much batches overlapped on the GPU.
+
+A job's data is a view of a device-resident data pool (the stand-in for
+samples an instrument has delivered into device memory), so the served path
+runs only the library's kernels: the FP8 quantisation or sign packing of the
+data and the grouped products.
 
 Failure handling: a job that can never run (unknown dtype or weight set, a
 sample count the kernels do not take, more memory than the whole budget) is
@@ -49,13 +56,9 @@ class WeightSet:
     registration), packed sign words for 1-bit."""
 
     def __init__(self, wid, dtype, M, K, seed, device):
-        import torch
         self.wid, self.dtype, self.M, self.K = wid, dtype, M, K
-        g = torch.Generator(device=device)
-        g.manual_seed(seed)
-        # unit-modulus phasors (steering-like weights), fp16
-        phi = torch.rand((M, K), device=device, generator=g, dtype=torch.float64) * (2 * np.pi)
-        W16 = torch.stack([torch.cos(phi), torch.sin(phi)])[None].to(torch.float16).contiguous()
+        self.seed, self.device = seed, device
+        W16 = self.source()
         self.scale = None
         if dtype == F16:
             self.A = block_weights(W16)
@@ -65,6 +68,15 @@ class WeightSet:
             self.A = pack1bit(W16, k_major=True)
         self.bytes = self.A.numel() * self.A.element_size() + (0 if self.scale is None else
                                                                self.scale.numel() * self.scale.element_size())
+
+    def source(self):
+        """The fp16 weights [1, 2, M, K] the resident form was made from
+        (unit-modulus phasors, steering-like), regenerated from the seed."""
+        import torch
+        g = torch.Generator(device=self.device)
+        g.manual_seed(self.seed)
+        phi = torch.rand((self.M, self.K), device=self.device, generator=g, dtype=torch.float64) * (2 * np.pi)
+        return torch.stack([torch.cos(phi), torch.sin(phi)])[None].to(torch.float16).contiguous()
 
 
 DONE, REJECTED, CANCELLED, FAILED = "done", "rejected", "cancelled", "failed"
@@ -94,15 +106,32 @@ def out_dtype(dtype):
     return torch.int32 if dtype == INT1 else torch.float32
 
 
-def job_input(job, device, gen=None):
-    """The job's data X [1, 2, K, N] fp16, drawn from its seed (8-bit range)."""
+def make_data_pool(elements, seed, device):
+    """Device-resident sample data (8-bit range complex Gaussian values in
+    fp16, sigma 32, clipped to +-127): the stand-in for data an instrument
+    has already delivered into device memory.  Jobs take their X from it, so
+    no random-number or copy kernel sits inside a job's latency."""
     import torch
-    g = gen if gen is not None else torch.Generator(device=device)
-    g.manual_seed(int(job.seed))
-    return torch.randint(-127, 128, (1, 2, job.K, job.N), device=device, generator=g, dtype=torch.float16)
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    v = torch.randn(elements, device=device, generator=g, dtype=torch.float32) * 32.0
+    return v.round().clamp(-127, 127).to(torch.float16)
+
+
+def job_input(job, data):
+    """The job's data X [1, 2, K, N] fp16: a view of the data pool at an
+    offset fixed by the job's seed (16-byte aligned)."""
+    need = 2 * job.K * job.N
+    if need > data.numel():
+        raise ValueError("job data larger than the data pool")
+    off = (int(job.seed) % ((data.numel() - need) // 8 + 1)) * 8
+    return data[off:off + need].view(1, 2, job.K, job.N)
 
 
 class Server:
+    # largest job data: K 2048 x N 8192 complex fp16 values (two planes)
+    DATA_POOL_ELEMENTS = 2 * 2048 * 8192 * 2
+
     def __init__(self, pool_per_dtype=16, dtypes=(F16, F8_E4M3, INT1), budget_frac=0.5, budget_bytes=None,
                  streams=3, max_slots=64, seed=0, device=0):
         import torch
@@ -118,6 +147,7 @@ class Server:
                 self.pool[(d, i)] = WeightSet(i, d, M, K, seed * 1000 + d * 100 + i, self.device)
         self.dtypes = tuple(dtypes)
         self.pool_per_dtype = pool_per_dtype
+        self.data = make_data_pool(self.DATA_POOL_ELEMENTS, seed * 1000 + 999, self.device)
         if budget_bytes is None:
             free, _ = torch.cuda.mem_get_info(device)
             budget_bytes = int(free * budget_frac)
@@ -127,7 +157,7 @@ class Server:
                            for _ in range(streams)]
         self.max_slots = max_slots
         self.plans = {}
-        self.gen = torch.Generator(device=self.device)
+        self.batch_log = []
 
     # -- jobs ---------------------------------------------------------------
     def make_jobs(self, count, rate, seed=1):
@@ -190,17 +220,46 @@ class Server:
         and job.t_done when it left the server."""
         import torch
         torch.cuda.synchronize()
+        self.batch_log = []
+        self.t_ref = torch.cuda.Event(enable_timing=True)
+        self.t_ref.record(torch.cuda.current_stream(self.device))
         sched = Scheduler(self.budget, self.max_slots, len(self.streams), max_batch, self.validate)
         summary = sched.run(jobs, GpuExecutor(self), keep_outputs)
         self.batch_sizes, self.max_inflight = sched.batch_sizes, sched.max_inflight
         summary["by_dtype"] = {DTYPE_NAMES[d]: int(sum(1 for j in jobs if j.dtype == d)) for d in self.dtypes}
         return summary
 
+    def device_intervals(self):
+        """Device-time interval of every batch of the last run, from timing
+        events recorded on its stream before its first and after its last
+        kernel: [(stream index, start ms, end ms)], times relative to an
+        event recorded when the run started.  Call after the run."""
+        import torch
+        torch.cuda.synchronize()
+        return [(si, self.t_ref.elapsed_time(a), self.t_ref.elapsed_time(b)) for si, a, b in self.batch_log]
+
+    def device_overlap(self):
+        """How much the batches of the last run overlapped in device time:
+        pairs of batches on different streams whose intervals intersect, and
+        the total time at least two streams had a batch in progress (ms)."""
+        iv = self.device_intervals()
+        pairs = sum(1 for i in range(len(iv)) for j in range(i + 1, len(iv))
+                    if iv[i][0] != iv[j][0] and min(iv[i][2], iv[j][2]) > max(iv[i][1], iv[j][1]))
+        edges = sorted([(a, 1) for _, a, _ in iv] + [(b, -1) for _, _, b in iv])
+        depth, last, multi = 0, None, 0.0
+        for t, d in edges:
+            if depth >= 2 and last is not None:
+                multi += t - last
+            depth += d
+            last = t
+        busy = sum(b - a for _, a, b in iv)
+        return {"batches": len(iv), "overlapping_pairs": pairs, "overlap_ms": multi, "batch_ms_total": busy}
+
     def run_alone(self, job):
         """The job's product on its own (one plain launch), for comparison."""
         import torch
         ws = self.pool[(job.dtype, job.wid)]
-        X = job_input(job, self.device)
+        X = job_input(job, self.data)
         out = torch.empty((1, 2, job.M, job.N), dtype=out_dtype(job.dtype), device=self.device)
         if job.dtype == F16:
             self._plan(F16, job.M, job.N, job.K).execute(ws.A, X, out)
@@ -227,10 +286,12 @@ class GpuExecutor:
         srv = self.srv
         s = srv.streams[si]
         with torch.cuda.stream(s):
+            start = torch.cuda.Event(enable_timing=True)
+            start.record(s)
             f16, f8, i1 = [], [], []
             for job in batch:
                 ws = srv.pool[(job.dtype, job.wid)]
-                X = job_input(job, srv.device, srv.gen)
+                X = job_input(job, srv.data)
                 job.out = torch.empty((1, 2, job.M, job.N), dtype=out_dtype(job.dtype), device=srv.device)
                 if job.dtype == F16:
                     job.X = X
@@ -247,8 +308,9 @@ class GpuExecutor:
                 for i in range(0, len(probs), GROUP_MAX):
                     group_execute(probs[i:i + GROUP_MAX], workspace=srv.workspaces[si], device=srv.dev_index,
                                   dtype=dt, layout=PLANAR if dt == INT1 else BLOCKED)
-            ev = torch.cuda.Event()
+            ev = torch.cuda.Event(enable_timing=True)
             ev.record(s)
+        srv.batch_log.append((si, start, ev))
         return ev
 
     def done(self, handle):

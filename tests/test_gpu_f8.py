@@ -417,4 +417,8 @@ def test_c4_full_size_sampled(c4_inputs, dtype):
     exact = oracle.cgemm(wl.planar_to_complex(sub), wl.planar_to_complex(X))
     log("c4 fp8 dtype=%d: rel Frobenius vs dequantised %.3e, vs unquantised %.3e"
         % (dtype, rel_fro(got, ref), rel_fro(got, exact)))
+    # e4m3 on both operands misses the 3e-2 tolerance against the unquantised
+    # inputs on this workload (about 3.7e-2: round-to-nearest with a 3-bit
+    # mantissa costs about 2.6e-2 per operand); this is a regression bound on
+    # that quantisation error only, not the mode's accuracy gate
     assert rel_fro(got, exact) < 6e-2

@@ -1,11 +1,14 @@
 """Serving loop (continuous batching): every job's result is the same alone
-and in the mix; jobs that arrive while others run are batched and overlap;
-the loop reports latency percentiles and throughput."""
+and in the mix; jobs that arrive while others run are batched, and batches on
+different streams overlap in device time (timing events on the streams); the
+loop reports latency percentiles and throughput; served results of every
+dtype match the oracle (FP8: the FP64 oracle on the inputs dequantised by the
+oracle's own quantiser)."""
 import numpy as np
 import pytest
 
 import oracle
-from gpu_util import check_fp_full, log
+from gpu_util import U32, check_fp_full, gamma, log
 
 pytestmark = pytest.mark.gpu
 
@@ -34,7 +37,13 @@ def test_results_same_alone_and_in_the_mix(server):
     assert summary["jobs"] == 48 and all(j.t_done is not None and j.t_done >= j.arrival for j in jobs)
     assert summary["p99_ms"] >= summary["p50_ms"] > 0 and summary["tops"] > 0
     assert max(server.batch_sizes) > 1          # arrivals during a batch were batched together
-    assert server.max_inflight > 1              # batches overlapped on the device
+    # batches on different streams were in progress on the device at the same
+    # time (device timestamps of events recorded before the first and after
+    # the last kernel of each batch on its own stream)
+    ov = server.device_overlap()
+    log("device overlap %s" % ov)
+    assert ov["batches"] == len(server.batch_sizes)
+    assert ov["overlapping_pairs"] > 0 and ov["overlap_ms"] > 0
     for job in jobs:
         alone = server.run_alone(job)
         assert torch.equal(job.out, alone), "job %d (dtype %d) differs alone and in the mix" % (job.jid, job.dtype)
@@ -46,24 +55,41 @@ def test_mixed_results_match_oracle(server):
     server.run(jobs, keep_outputs=True)
     seen = set()
     for job in jobs:
-        if job.dtype in seen or job.dtype == tcbf.F8_E4M3:
+        if job.dtype in seen:
             continue
         seen.add(job.dtype)
         ws = server.pool[(job.dtype, job.wid)]
-        X = serve.job_input(job, server.device).cpu().numpy().astype(np.float64)
+        X = serve.job_input(job, server.data).cpu().numpy().astype(np.float64)
         got = job.out.cpu().numpy()
-        if job.dtype == tcbf.F16:
-            # resident weights are receiver-blocked [1, 2, Kb, M, 32]: back to [1, 2, M, K]
-            Wb = ws.A.cpu().numpy().astype(np.float64)
-            W = Wb.transpose(0, 1, 3, 2, 4).reshape(1, 2, job.M, -1)[..., :job.K]
+        log("served job %d dtype %d: %d x %d x %d" % (job.jid, job.dtype, job.M, job.N, job.K))
+        if job.dtype == tcbf.F8_E4M3:
+            # the oracle's own quantiser on the fp16 inputs (per-row scales:
+            # W per beam, X per sample), exact decoding, FP64 product
+            W16 = ws.source().cpu().numpy()[0].astype(np.float32)
+            wr, wi, wsc = oracle.quantize_e4m3_rows(W16[0], W16[1])
+            xr, xi, xsc = oracle.quantize_e4m3_rows(X[0, 0].T, X[0, 1].T)
+            d = oracle.e4m3_decode
+            Wd = (d(wr) + 1j * d(wi)) * np.asarray(wsc, np.float64)[:, None]
+            Xd = ((d(xr) + 1j * d(xi)) * np.asarray(xsc, np.float64)[:, None]).T
+            ref = oracle.cgemm(Wd[None], np.ascontiguousarray(Xd)[None])[0]
+            g = got[0, 0] + 1j * got[0, 1]
+            rel = float(np.linalg.norm(g - ref) / np.linalg.norm(ref))
+            bound = (2.0 ** -9 + 2.0 * gamma(2 * job.K) + 4 * U32) * np.matmul(np.abs(Wd), np.abs(Xd))
+            err = np.maximum(np.abs(g.real - ref.real), np.abs(g.imag - ref.imag))
+            log("served FP8 job: rel Frobenius %.3e vs the dequantised-input oracle" % rel)
+            assert rel <= 3e-2 and np.all(err <= bound)
+        elif job.dtype == tcbf.F16:
+            # the fp16 weights the resident (receiver-blocked) form was made from
+            W = ws.source().cpu().numpy().astype(np.float64)
             Wc, Xc = W[:, 0] + 1j * W[:, 1], X[:, 0] + 1j * X[:, 1]
             check_fp_full(got[:, 0] + 1j * got[:, 1], oracle.cgemm(Wc, Xc), np.matmul(np.abs(Wc), np.abs(Xc)), job.K)
         else:
-            Wp = ws.A.cpu().numpy().view(np.uint32)
-            Xp = tcbf.pack1bit(serve.job_input(job, server.device), k_major=False).cpu().numpy().view(np.uint32)
-            rr, ri = oracle.cgemm_1bit_popc(Wp[:, 0], Wp[:, 1], Xp[:, 0], Xp[:, 1], job.K)
+            # sign bits packed by the oracle from the fp16 weights and data
+            Wp = oracle.pack1bit(ws.source().cpu().numpy()[0])
+            Xp = oracle.pack1bit(np.ascontiguousarray(X[0].transpose(0, 2, 1)))
+            rr, ri = oracle.cgemm_1bit_popc(Wp[None, 0], Wp[None, 1], Xp[None, 0], Xp[None, 1], job.K)
             assert np.array_equal(got[:, 0].astype(np.int64), rr) and np.array_equal(got[:, 1].astype(np.int64), ri)
-    assert seen == {tcbf.F16, tcbf.INT1}
+    assert seen == {tcbf.F16, tcbf.F8_E4M3, tcbf.INT1}
 
 
 def test_budget_too_small_is_reported():
