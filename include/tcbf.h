@@ -343,6 +343,28 @@ tcbf_status tcbf_group_execute(int32_t device, int32_t dtype, int32_t c_layout,
                                void *workspace, void *stream);
 
 /*
+ * Allocation-free grouped launch, for callers that cannot allocate device
+ * memory or pass a workspace (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): the same launch as
+ * tcbf_group_execute, with the same arguments, checks and results, except
+ * that the tile counter lives in a library-owned scratch array of
+ * TCBF_GROUP_SCRATCH_BYTES per GPU (a static device array, held by every GPU
+ * the library runs on until the process ends) instead of a workspace.  The
+ * counter is reset by a kernel at the start of every launch.  All calls on
+ * one GPU share that array: calls whose launches overlap in time on one GPU
+ * (different streams, or different threads) race on the counter and give
+ * wrong results; use tcbf_group_execute with one workspace per stream for
+ * those.  Rejects count outside 1..TCBF_GROUP_MAX (the launch's size limit)
+ * and a device index of 64 or more with an error; calls no allocating
+ * routine.  The current device must be `device`.
+ */
+#define TCBF_GROUP_SCRATCH_BYTES 256
+
+tcbf_status tcbf_group_execute_noalloc(int32_t device, int32_t dtype, int32_t c_layout,
+                                       const tcbf_group_problem *problems, int32_t count,
+                                       void *stream);
+
+/*
  * Peak probe (measurement tool, not a step of the product): the throughput of
  * one matrix instruction (or of the VALU xor/popcount pair) on register
  * operands with no global-memory traffic, the measured ceiling the paper

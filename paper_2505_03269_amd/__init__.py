@@ -13,9 +13,9 @@ import os
 
 __all__ = [
     "F16", "INT1", "F8_E4M3", "MXF8_E4M3", "PLANAR", "INTERLEAVED", "BLOCKED", "SRC_I8", "SRC_F16", "SRC_F32",
-    "TcbfError", "Plan", "block_weights", "blocked_shape", "f8_codes_shape", "pack1bit", "quantize_e4m3", "steering_weights", "group_execute", "peak_probe", "f8_kp", "mx_scale_pitch", "mx_scales_to_rows",
+    "TcbfError", "Plan", "block_weights", "blocked_shape", "f8_codes_shape", "pack1bit", "quantize_e4m3", "steering_weights", "group_execute", "group_execute_noalloc", "peak_probe", "f8_kp", "mx_scale_pitch", "mx_scales_to_rows",
     "mx_scales_from_rows", "lib",
-    "status_string", "EXPORTS", "GROUP_MAX", "GROUP_WORKSPACE_BYTES",
+    "status_string", "EXPORTS", "GROUP_MAX", "GROUP_WORKSPACE_BYTES", "GROUP_SCRATCH_BYTES",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -27,10 +27,11 @@ SRC_I8, SRC_F16, SRC_F32 = 0, 1, 2
 
 # every symbol include/tcbf.h declares
 EXPORTS = ("tcbf_plan", "tcbf_execute", "tcbf_block_weights", "tcbf_pack1bit", "tcbf_quantize_e4m3", "tcbf_steering_weights",
-           "tcbf_peak_probe", "tcbf_group_execute", "tcbf_plan_query", "tcbf_plan_destroy", "tcbf_status_string",
+           "tcbf_peak_probe", "tcbf_group_execute", "tcbf_group_execute_noalloc", "tcbf_plan_query", "tcbf_plan_destroy", "tcbf_status_string",
            "tcbf_version")
 GROUP_MAX = 32
 GROUP_WORKSPACE_BYTES = 256
+GROUP_SCRATCH_BYTES = 256
 # peak-probe kinds, and the operand pattern of each whose products are all 1
 PROBE_F16, PROBE_I8, PROBE_F8, PROBE_F4, PROBE_VALU_XOR_POPC = 0, 1, 2, 3, 4
 PROBE_UNIT_OPERAND = {PROBE_F16: 0x3C00, PROBE_I8: 0x01010101, PROBE_F8: 0x38383838, PROBE_F4: 0x22222222,
@@ -97,6 +98,8 @@ def lib():
     L.tcbf_peak_probe.restype = i32
     L.tcbf_group_execute.argtypes = [i32, i32, i32, ctypes.POINTER(GroupProblem), i32, vp, vp]
     L.tcbf_group_execute.restype = i32
+    L.tcbf_group_execute_noalloc.argtypes = [i32, i32, i32, ctypes.POINTER(GroupProblem), i32, vp]
+    L.tcbf_group_execute_noalloc.restype = i32
     L.tcbf_plan_query.argtypes = [vp, ctypes.POINTER(PlanInfo)]
     L.tcbf_plan_query.restype = i32
     L.tcbf_plan_destroy.argtypes = [vp]
@@ -487,6 +490,32 @@ def group_execute(problems, c_layout=PLANAR, workspace=None, device=0, stream=No
     if None; pass one to stay allocation-free).
     """
     import torch
+    arr = _group_table(problems, c_layout, dtype, layout)
+    if workspace is None:
+        workspace = torch.empty(GROUP_WORKSPACE_BYTES, dtype=torch.uint8, device="cuda:%d" % device)
+    if workspace.numel() * workspace.element_size() < GROUP_WORKSPACE_BYTES:
+        raise ValueError("workspace too small")
+    _check(lib().tcbf_group_execute(int(device), int(dtype), int(c_layout), arr, len(problems),
+                                    _dev_ptr(workspace, "workspace"), _stream_handle(stream)),
+           "tcbf_group_execute")
+    return [pr[2] for pr in problems]
+
+
+def group_execute_noalloc(problems, c_layout=PLANAR, device=0, stream=None, dtype=F16, layout=PLANAR):
+    """The grouped launch of group_execute (same problem tuples and results)
+    through the allocation-free entry point: its tile counter lives in the
+    library's per-GPU scratch array, so launches of this call that overlap in
+    time on one GPU race (use group_execute with one workspace per stream)."""
+    arr = _group_table(problems, c_layout, dtype, layout)
+    _check(lib().tcbf_group_execute_noalloc(int(device), int(dtype), int(c_layout), arr, len(problems),
+                                            _stream_handle(stream)),
+           "tcbf_group_execute_noalloc")
+    return [pr[2] for pr in problems]
+
+
+def _group_table(problems, c_layout, dtype, layout):
+    """Check the problem tuples of a grouped launch and build its C table."""
+    import torch
     if not 1 <= len(problems) <= GROUP_MAX:
         raise ValueError("1..%d problems per launch" % GROUP_MAX)
     f8 = _is_f8(dtype)
@@ -550,11 +579,4 @@ def group_execute(problems, c_layout=PLANAR, workspace=None, device=0, stream=No
             sa, sb = _dev_ptr(pr[3], "a_scale").value, _dev_ptr(pr[4], "b_scale").value
         arr[i] = GroupProblem(_dev_ptr(W, "W").value, _dev_ptr(X, "X").value, _dev_ptr(C, "C").value,
                               batch, M, N, K, int(shared), int(layout), sa, sb)
-    if workspace is None:
-        workspace = torch.empty(GROUP_WORKSPACE_BYTES, dtype=torch.uint8, device="cuda:%d" % device)
-    if workspace.numel() * workspace.element_size() < GROUP_WORKSPACE_BYTES:
-        raise ValueError("workspace too small")
-    _check(lib().tcbf_group_execute(int(device), int(dtype), int(c_layout), arr, len(problems),
-                                    _dev_ptr(workspace, "workspace"), _stream_handle(stream)),
-           "tcbf_group_execute")
-    return [pr[2] for pr in problems]
+    return arr

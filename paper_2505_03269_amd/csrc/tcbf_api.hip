@@ -4,6 +4,7 @@
 // entry point throws, aborts or allocates device memory.
 #include <algorithm>
 #include <atomic>
+#include <mutex>
 #include <new>
 #include <stdio.h>
 #include <string.h>
@@ -295,13 +296,44 @@ tcbf_status tcbf_peak_probe(int32_t kind, int64_t blocks, int64_t iterations, ui
     return e == hipSuccess ? TCBF_SUCCESS : TCBF_ERROR_DEVICE;
 }
 
-tcbf_status tcbf_group_execute(int32_t device, int32_t dtype, int32_t c_layout, const tcbf_group_problem *problems,
-                               int32_t count, void *workspace, void *stream) {
-    if (problems == nullptr || workspace == nullptr) return TCBF_ERROR_INVALID_VALUE;
+}  // extern "C"
+
+namespace {
+
+// Scratch memory of tcbf_group_execute_noalloc: the grouped launch's tile
+// counter, one copy per GPU, held until the process ends.  In host code the
+// array's name is not a device address: kernels get the address that
+// hipGetSymbolAddress returns with the device current (kept per device).
+static __device__ __align__(256) unsigned char scratch[TCBF_GROUP_SCRATCH_BYTES];
+static_assert(TCBF_GROUP_WORKSPACE_BYTES <= TCBF_GROUP_SCRATCH_BYTES, "the scratch array holds one workspace");
+
+std::mutex g_scratch_mutex;
+void *g_scratch_ptr[kMaxDevices];
+
+// Device address of `device`'s scratch array (the device must be current),
+// looked up on the first call on that device.
+tcbf_status scratch_of(int device, void **out) {
+    if (device < 0 || device >= kMaxDevices) return TCBF_ERROR_NOT_SUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (g_scratch_ptr[device] == nullptr) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || ptr == nullptr) return TCBF_ERROR_DEVICE;
+        g_scratch_ptr[device] = ptr;
+    }
+    *out = g_scratch_ptr[device];
+    return TCBF_SUCCESS;
+}
+
+// The grouped launch behind both entry points: the device tile counter is in
+// the caller's `workspace`, or with `use_scratch` in this device's scratch
+// array (looked up after every argument check).
+tcbf_status group_execute(int32_t device, int32_t dtype, int32_t c_layout, const tcbf_group_problem *problems,
+                          int32_t count, void *workspace, bool use_scratch, void *stream) {
+    if (problems == nullptr || (workspace == nullptr && !use_scratch)) return TCBF_ERROR_INVALID_VALUE;
     if ((dtype != TCBF_F16 && dtype != TCBF_INT1 && !is_f8(dtype)) || !is_layout(c_layout))
         return TCBF_ERROR_INVALID_VALUE;
     if (count < 1 || count > TCBF_GROUP_MAX) return TCBF_ERROR_INVALID_VALUE;
-    if (!aligned16(workspace)) return TCBF_ERROR_INVALID_VALUE;
+    if (!use_scratch && !aligned16(workspace)) return TCBF_ERROR_INVALID_VALUE;
     tcbf::Problem probs[TCBF_GROUP_MAX];
     const void *A[TCBF_GROUP_MAX];
     const void *B[TCBF_GROUP_MAX];
@@ -354,6 +386,10 @@ tcbf_status tcbf_group_execute(int32_t device, int32_t dtype, int32_t c_layout, 
     std::stable_sort(order, order + count, [&](int a, int b) { return probs[a].K > probs[b].K; });
     tcbf_status st = current_device_is(device);
     if (st != TCBF_SUCCESS) return st;
+    if (use_scratch) {
+        st = scratch_of(device, &workspace);
+        if (st != TCBF_SUCCESS) return st;
+    }
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1)
         return TCBF_ERROR_DEVICE;
@@ -368,6 +404,20 @@ tcbf_status tcbf_group_execute(int32_t device, int32_t dtype, int32_t c_layout, 
         e = tcbf::f8_group_launch(probs, A, B, C, SA, SB, order, count, dtype == TCBF_MXF8_E4M3, c_layout, grid,
                                   counter, (hipStream_t)stream);
     return e == hipSuccess ? TCBF_SUCCESS : TCBF_ERROR_DEVICE;
+}
+
+}  // namespace
+
+extern "C" {
+
+tcbf_status tcbf_group_execute(int32_t device, int32_t dtype, int32_t c_layout, const tcbf_group_problem *problems,
+                               int32_t count, void *workspace, void *stream) {
+    return group_execute(device, dtype, c_layout, problems, count, workspace, false, stream);
+}
+
+tcbf_status tcbf_group_execute_noalloc(int32_t device, int32_t dtype, int32_t c_layout,
+                                       const tcbf_group_problem *problems, int32_t count, void *stream) {
+    return group_execute(device, dtype, c_layout, problems, count, nullptr, true, stream);
 }
 
 }  // extern "C"

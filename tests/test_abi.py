@@ -239,6 +239,26 @@ def test_group_argument_checks():
             assert L.tcbf_group_execute(0, dt, 0, arr, 1, p, None) == want, (dt, bad)
 
 
+def test_group_noalloc_argument_checks():
+    """The allocation-free grouped launch makes the same argument checks as
+    the workspace launch, before it looks for a device."""
+    L = tcbf.lib()
+    buf = ctypes.create_string_buffer(1024)
+    addr = (ctypes.addressof(buf) + 15) & ~15
+    good = tcbf.GroupProblem(addr, addr, addr, 1, 8, 8, 8, 0, 0, None, None)
+    one = (tcbf.GroupProblem * 1)(good)
+    assert L.tcbf_group_execute_noalloc(0, tcbf.F16, 0, None, 1, None) == 1                 # no problems
+    assert L.tcbf_group_execute_noalloc(0, tcbf.F16, 0, one, 0, None) == 1                  # count 0
+    assert L.tcbf_group_execute_noalloc(0, tcbf.F16, 0, one, tcbf.GROUP_MAX + 1, None) == 1
+    assert L.tcbf_group_execute_noalloc(0, 9, 0, one, 1, None) == 1                         # unknown dtype
+    assert L.tcbf_group_execute_noalloc(0, tcbf.F16, 4, one, 1, None) == 1                  # unknown layout
+    for bad in (dict(K=12), dict(N=4), dict(batch=0), dict(A=addr + 2), dict(a_scale=addr)):
+        d = dict(A=addr, B=addr, C=addr, batch=1, M=8, N=8, K=8, a_shared=0, layout=0)
+        d.update(bad)
+        arr = (tcbf.GroupProblem * 1)(tcbf.GroupProblem(**d))
+        assert L.tcbf_group_execute_noalloc(0, tcbf.F16, 0, arr, 1, None) == 1, bad
+
+
 def test_valid_descriptor_without_gpu_reports_device():
     import torch
     if torch.cuda.is_available():
