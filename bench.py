@@ -49,6 +49,7 @@ def log(msg):
 # the sources each profiled kernel is compiled from (hashed together, in order)
 KERNEL_SOURCES = {
     "cgemm_f16_fast_kernel": ("cgemm_f16.hip", "tcbf_tile.h", "tcbf_internal.h"),
+    "cgemm_f16_pp_kernel": ("cgemm_f16.hip", "tcbf_tile.h", "tcbf_internal.h"),
 }
 
 
@@ -71,7 +72,7 @@ def recorded_traffic(kernel):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             rec[k.strip()] = v.strip()
-    if rec.get("kernel_source_sha256_16") != kernel_source_hash(kernel):
+    if kernel not in KERNEL_SOURCES or rec.get("kernel_source_sha256_16") != kernel_source_hash(kernel):
         return None
     try:
         return float(rec["traffic_bytes_per_launch"])

@@ -8,14 +8,16 @@ sweep starts from the variant closest to Table 3's MI300X/MI300A float16 point
 (128 x 128 complex outputs per workgroup, 64-row wave tiles), then tries the
 rest.  Timing uses HIP events on the stream the library launches on, over
 inputs resident on the device; the cache key is the device architecture, the
-dtype and the exact problem shape and layouts.
+dtype, the exact problem shape and layouts, and the kernel set (a hash of the
+built library and the candidate lists).
 
 Only timing and bookkeeping happen here; every product runs in the library.
 """
+import hashlib
 import json
 import os
 
-from . import F16, F8_E4M3, INT1, MXF8_E4M3, PLANAR, Plan, TcbfError
+from . import F16, F8_E4M3, INT1, LIB_PATH, MXF8_E4M3, PLANAR, Plan, TcbfError
 
 
 def _layouts(dtype, operand_layout):
@@ -33,9 +35,31 @@ CANDIDATES = {
 }
 
 
-def cache_key(arch, dtype, batch, M, N, K, c_layout=PLANAR, a_shared=False, operand_layout=PLANAR):
+_KERNEL_SET = None
+
+
+def kernel_set_id():
+    """Identity of the kernel set a cached choice refers to: a hash of the
+    built library and of the candidate lists.  A rebuilt library with other
+    kernels behind the same variant numbers, or a changed candidate list,
+    gets new cache keys (so it is tuned again instead of reusing a choice
+    made among other kernels)."""
+    global _KERNEL_SET
+    if _KERNEL_SET is None:
+        h = hashlib.sha256()
+        with open(LIB_PATH, "rb") as f:
+            for chunk in iter(lambda: f.read(1 << 20), b""):
+                h.update(chunk)
+        h.update(json.dumps({str(k): v for k, v in CANDIDATES.items()}, sort_keys=True).encode())
+        _KERNEL_SET = h.hexdigest()[:12]
+    return _KERNEL_SET
+
+
+def cache_key(arch, dtype, batch, M, N, K, c_layout=PLANAR, a_shared=False, operand_layout=PLANAR, kernel_set=None):
     key = "%s|dtype%d|%dx%dx%dx%d|c%d|s%d" % (arch, int(dtype), batch, M, N, K, int(c_layout), int(bool(a_shared)))
-    return key if operand_layout == PLANAR else key + "|op%d" % int(operand_layout)
+    if operand_layout != PLANAR:
+        key += "|op%d" % int(operand_layout)
+    return key + "|ks" + (kernel_set if kernel_set is not None else kernel_set_id())
 
 
 def load_cache(path):
