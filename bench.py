@@ -453,6 +453,44 @@ def bench_c2(steps, warmup):
     return W, X, info, ms, tops, spread, planar, blocking, C_head
 
 
+def bench_c2_interleaved(W, X, steps):
+    """The radio-astronomy product in the interleaved complex layouts (weights
+    [batch][M][K][2] repacked once into the receiver-blocked layout, data
+    [batch][K][N][2] read as is, output [batch][M][N][2]), timed against the
+    planar-data product in alternating rounds."""
+    import torch
+    import paper_2505_03269_amd as tcbf
+    import workloads as wl
+    cfg = wl.WORKLOADS["radio-astro-fp16"]
+    shape = (cfg["batch"], cfg["M"], cfg["N"], cfg["K"])
+    Ai = torch.from_numpy(W).to("cuda:0").permute(0, 2, 3, 1).contiguous()
+    Ab = tcbf.block_weights(Ai, layout=tcbf.INTERLEAVED)
+    del Ai
+    B = torch.from_numpy(X).to("cuda:0")
+    Bi = B.permute(0, 2, 3, 1).contiguous()
+    pi = tcbf.Plan(*shape, tcbf.F16, a_layout=tcbf.BLOCKED, b_layout=tcbf.INTERLEAVED, c_layout=tcbf.INTERLEAVED)
+    pp = tcbf.Plan(*shape, tcbf.F16, a_layout=tcbf.BLOCKED)
+    pm = tcbf.Plan(*shape, tcbf.F16, a_layout=tcbf.BLOCKED, b_layout=tcbf.INTERLEAVED)
+    info = pi.info()
+    Ci, Cp = pi.empty_output(), pp.empty_output()
+    ms_i, ms_p, ms_m = time_interleaved([lambda: pi.execute(Ab, Bi, Ci), lambda: pp.execute(Ab, B, Cp),
+                                         lambda: pm.execute(Ab, Bi, Cp)], max(steps // 2, 5), 2)
+    ops = info["useful_ops"]
+    tops = ops / (ms_i * 1e-3) / 1e12
+    del Ab, B, Bi, Ci, Cp
+    torch.cuda.empty_cache()
+    return {"workload": "radio-astro-fp16 interleaved: batch=256 M=1024 K=576 N=4096", "kernel": info["kernel_name"],
+            "variant": info["variant"], "value": round(tops, 1), "unit": "TeraOps/s", "ms_per_launch": round(ms_i, 4),
+            "dtype": "f16",
+            "layout": "W interleaved, repacked once into the receiver-blocked layout; X interleaved [K][N][2]; "
+                      "output interleaved [M][N][2]",
+            "planar_data_tops": round(ops / (ms_p * 1e-3) / 1e12, 1),
+            "interleaved_data_planar_output_tops": round(ops / (ms_m * 1e-3) / 1e12, 1),
+            "ratio_to_planar": round(ms_p / ms_i, 3),
+            "roofline": {"bound": "mfma", "achieved": round(tops, 1), "peak": PEAK_F16_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(tops / PEAK_F16_TFLOPS, 4)}}
+
+
 def bench_c1_latency(samples, launches=200):
     """The small plain-fp16 case (4 x 128 x 64 x 512): one launch is far too
     short to fill the GPU, so what counts is latency.  Per launch: eager
@@ -745,9 +783,10 @@ def bench_serving(warmup=1000, measured=10000):
     srv.run(srv.make_jobs(warmup, None, seed=100))
     closed = srv.run(srv.make_jobs(measured, None, seed=200))
     cap = measured / closed["makespan_s"]
-    runs = {}
+    runs, overlap = {}, {}
     for load in (0.8, 0.5):
         runs[load] = srv.run(srv.make_jobs(measured, load * cap, seed=300 + int(load * 10)))
+        overlap[load] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in srv.device_overlap().items()}
     r = runs[0.8]
     rnd = lambda d: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()}  # noqa: E731
     return {"workload": "served mixed stream: fp16/fp8/1-bit jobs, 16 resident weight sets per dtype, "
@@ -756,6 +795,9 @@ def bench_serving(warmup=1000, measured=10000):
             "value": round(r["tops"], 1), "unit": "TeraOps/s", "p50_ms": round(r["p50_ms"], 3),
             "p99_ms": round(r["p99_ms"], 3), "capacity_jobs_per_s": round(cap, 1),
             "closed_loop": rnd(closed), "load_0.8": rnd(runs[0.8]), "load_0.5": rnd(runs[0.5]),
+            "device_overlap_0.8": overlap[0.8], "device_overlap_0.5": overlap[0.5],
+            "device_overlap_note": "batches on different streams in progress at the same device time "
+                                   "(timing events around each batch on its own stream)",
             "completed": r["completed"], "rejected": r["rejected"], "failed": r["failed"],
             "warmup_jobs": warmup, "measured_jobs": measured, "streams": len(srv.streams),
             "budget_bytes": srv.budget}
@@ -904,6 +946,7 @@ def main():
         roofline["frac_of_measured_peak"] = round(ach_flops / probes["f16"]["uniform"]["tops"], 4)
         roofline["measured_peak_random_operands"] = probes["f16"]["random"]["tops"]
     samples = {}
+    il_line = None if args.no_secondary else bench_c2_interleaved(W, X, args.steps)
     secondary = [] if args.no_secondary else bench_secondary(
         args.steps, samples, serving=not args.no_serving, copy_gbs=probes["hbm_copy"]["gbs"],
         valu_peak=probes["valu_xor_popc"]["uniform"]["tops"])
@@ -926,6 +969,8 @@ def main():
                 if key in acc:
                     secondary[i]["accuracy"] = acc[key]
     del W, X, C_head
+    if il_line is not None:
+        secondary.insert(0, il_line)  # after the CPU legs, which address lines by index
     line = {
         "metric": METRIC, "value": round(tops, 2), "unit": "TeraOps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),

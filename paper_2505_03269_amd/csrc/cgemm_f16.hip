@@ -462,7 +462,18 @@ __device__ __forceinline__ void fast_tile(const uint16_t *__restrict__ A, const 
     constexpr int TM = G::TM, NW = G::NW;
     static_assert(NS >= 2 && NS <= 6, "ring depth");
     static_assert(G::WREG % (NW * 1024) == 0 && G::XREG % (NW * 1024) == 0, "whole wave loads");
-    char *const bufs[6] = {lds0, lds1, lds2, lds3, lds4, lds5};
+    // stage buffer i: a select chain, not an array -- an array of LDS
+    // pointers that the compiler cannot index statically goes to scratch
+    // memory as generic pointers, and every fragment read becomes a flat load
+    auto bufs = [&](int i) __attribute__((always_inline)) -> char * {
+        char *b = lds0;
+        if (i == 1) b = lds1;
+        if (i == 2) b = lds2;
+        if (i == 3) b = lds3;
+        if (i == 4) b = lds4;
+        if (i == 5) b = lds5;
+        return b;
+    };
 
     const int tid = threadIdx.x;
     const int m0 = tm * TM, n0 = tn * BN;
@@ -529,7 +540,7 @@ __device__ __forceinline__ void fast_tile(const uint16_t *__restrict__ A, const 
         }
     }
 
-    auto issue = [&](char *base, int k0) {
+    auto issue = [&](char *base, int k0) __attribute__((always_inline)) {
         const bool tail = k0 + BK > K;
 #pragma unroll
         for (int q = 0; q < WPW; ++q) {
@@ -552,7 +563,7 @@ __device__ __forceinline__ void fast_tile(const uint16_t *__restrict__ A, const 
 
     Acc acc;
     acc.zero();
-    auto compute = [&](const char *st) {
+    auto compute = [&](const char *st) __attribute__((always_inline)) {
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
             half8 wr[2], wi[2], xr[2], xi[2];
@@ -579,7 +590,7 @@ __device__ __forceinline__ void fast_tile(const uint16_t *__restrict__ A, const 
     static_assert((NS - 2) * PER_STAGE < 64, "vmcnt range");
     constexpr int kWaitRing = vmcnt_imm((NS - 2) * PER_STAGE), kWaitAll = vmcnt_imm(0);
     const int nk = (K + BK - 1) / BK;
-    auto stage_step = [&](int kt, int u) {
+    auto stage_step = [&](int kt, int u) __attribute__((always_inline)) {
         // stage kt's loads (issued NS-1 stages ago) must have landed; the NS-2
         // younger stages may still be in flight
         if (kt + NS - 2 < nk) __builtin_amdgcn_s_waitcnt(kWaitRing);
@@ -590,12 +601,12 @@ __device__ __forceinline__ void fast_tile(const uint16_t *__restrict__ A, const 
         // loads that the ring keeps in flight.  The clobber keeps the compiler
         // from moving LDS accesses across it.
         asm volatile("s_barrier" ::: "memory");
-        if (kt + NS - 1 < nk) issue(bufs[(u + NS - 1) % NS], (kt + NS - 1) * BK);
-        compute(bufs[u]);
+        if (kt + NS - 1 < nk) issue(bufs((u + NS - 1) % NS), (kt + NS - 1) * BK);
+        compute(bufs(u));
     };
 #pragma unroll
     for (int s = 0; s < NS - 1; ++s)
-        if (s < nk) issue(bufs[s], s * BK);
+        if (s < nk) issue(bufs(s), s * BK);
     // whole groups of NS stages, then the remainder; no early exits, so the
     // accumulators keep a single home through the loop
     int kt0 = 0;
@@ -611,7 +622,7 @@ __device__ __forceinline__ void fast_tile(const uint16_t *__restrict__ A, const 
     constexpr int ROWS_PER_BUF = G::STAGE / staging_pitch<CIL>();
     static_assert(G::STAGE % staging_pitch<CIL>() == 0, "staged rows stay inside one buffer");
     static_assert(ROWS_PER_BUF * NS >= staging_rows<WM, CIL>(), "stage buffers hold a staging round");
-    auto row_ptr = [&](int row) -> char * {  // select chain: no dynamically indexed array
+    auto row_ptr = [&](int row) __attribute__((always_inline)) -> char * {  // select chain: no dynamically indexed array
         constexpr int NB = (staging_rows<WM, CIL>() + ROWS_PER_BUF - 1) / ROWS_PER_BUF;  // buffers in use
         const int b = row / ROWS_PER_BUF;
         char *base = lds0;
@@ -666,8 +677,14 @@ __device__ __forceinline__ void split_tile(const uint16_t *__restrict__ A, const
     typedef FastGeo<WM, BK> G;
     constexpr int TM = G::TM, NW = G::NW;
     static_assert(G::WREG == G::XREG, "equal operand regions");
-    char *const wbs[2] = {wb0, wb1};
-    char *const xbs[3] = {xb0, xb1, xb2};
+    // select chains, not arrays (see fast_tile)
+    auto wbs = [&](int i) __attribute__((always_inline)) -> char * { return i == 1 ? wb1 : wb0; };
+    auto xbs = [&](int i) __attribute__((always_inline)) -> char * {
+        char *b = xb0;
+        if (i == 1) b = xb1;
+        if (i == 2) b = xb2;
+        return b;
+    };
 
     const int tid = threadIdx.x;
     const int m0 = tm * TM, n0 = tn * BN;
@@ -728,7 +745,7 @@ __device__ __forceinline__ void split_tile(const uint16_t *__restrict__ A, const
     // of range (the loads write zeros into a buffer no stage reads again), so
     // the sequence of loads, and with it every wait count, is the same on
     // every path; the compiler then needs no conservative full waits.
-    auto issue_w = [&](char *base, int kt) {
+    auto issue_w = [&](char *base, int kt) __attribute__((always_inline)) {
         const int k0 = kt * BK;
         const bool tail = k0 + BK > K;
 #pragma unroll
@@ -743,7 +760,7 @@ __device__ __forceinline__ void split_tile(const uint16_t *__restrict__ A, const
                                                      so, 0, 0);
         }
     };
-    auto issue_x = [&](char *base, int kt) {
+    auto issue_x = [&](char *base, int kt) __attribute__((always_inline)) {
         const int k0 = kt * BK;
         const bool tail = k0 + BK > K;
 #pragma unroll
@@ -758,7 +775,7 @@ __device__ __forceinline__ void split_tile(const uint16_t *__restrict__ A, const
 
     Acc acc;
     acc.zero();
-    auto compute = [&](const char *wst, const char *xst) {
+    auto compute = [&](const char *wst, const char *xst) __attribute__((always_inline)) {
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
             half8 wr[2], wi[2], xr[2], xi[2];
@@ -781,20 +798,20 @@ __device__ __forceinline__ void split_tile(const uint16_t *__restrict__ A, const
     static_assert(XPW < 64, "vmcnt range");
     constexpr int kWaitNewestX = vmcnt_imm(XPW), kWaitAll = vmcnt_imm(0);
     // stage kt: W in wbs[kt % 2], X in xbs[kt % 3]
-    auto stage_step = [&](int kt, int uw, int ux) {
+    auto stage_step = [&](int kt, int uw, int ux) __attribute__((always_inline)) {
         // W(kt) and X(kt) landed; X(kt+1), issued last, may be in flight
         __builtin_amdgcn_s_waitcnt(kWaitNewestX);
         // every wave's loads landed and stage kt-1 fully read (bare barrier:
         // the release fence of __syncthreads would wait for X(kt+1) too)
         asm volatile("s_barrier" ::: "memory");
-        issue_w(wbs[(uw + 1) % 2], kt + 1);
-        issue_x(xbs[(ux + 2) % 3], kt + 2);
-        compute(wbs[uw], xbs[ux]);
+        issue_w(wbs((uw + 1) % 2), kt + 1);
+        issue_x(xbs((ux + 2) % 3), kt + 2);
+        compute(wbs(uw), xbs(ux));
     };
     // prologue, in the order of the steady state: X(0), then W(0), X(1)
-    issue_x(xbs[0], 0);
-    issue_w(wbs[0], 0);
-    issue_x(xbs[1], 1);
+    issue_x(xbs(0), 0);
+    issue_w(wbs(0), 0);
+    issue_x(xbs(1), 1);
     // groups of 6 stages keep both rings' buffer choices compile-time
     int kt0 = 0;
     for (; kt0 + 6 <= nk; kt0 += 6) {
@@ -810,7 +827,7 @@ __device__ __forceinline__ void split_tile(const uint16_t *__restrict__ A, const
     __builtin_amdgcn_s_waitcnt(kWaitAll);
     constexpr int ROWS_PER_BUF = G::WREG / staging_pitch<CIL>();
     static_assert(ROWS_PER_BUF * 4 >= staging_rows<WM, CIL>(), "four buffers hold a staging round");
-    auto row_ptr = [&](int row) -> char * {
+    auto row_ptr = [&](int row) __attribute__((always_inline)) -> char * {
         const int b = row / ROWS_PER_BUF;
         char *base = wb0;
         if (b == 1) base = wb1;
@@ -941,7 +958,108 @@ __device__ __forceinline__ void pp_barrier() {
     __builtin_amdgcn_sched_barrier(0);
 }
 
-template <int CIL, int AB>
+// Interleaved data (X as [K][N][2], BIL = 1).  A stage's X tile is 32 rows
+// of 128 complex samples = 256 real columns (512 bytes: re, im, re, im, ...)
+// in LDS, read with the same transposing fragment reads as a plane of 256
+// "samples"; a fragment then holds 32 real columns, re and im alternating
+// with the lane (real column 2n + p in lane parity p).  The complex product
+// stays the same four real products in the same order per output: for
+// weights-first matrix instructions the real column is the output row, so
+//   out[2n]     += Wr . Xr[n]  then  Wi . (-Xi[n])     (Re)
+//   out[2n + 1] += Wr . Xi[n]  then  Wi . Xr[n]        (Im)
+// i.e. one product with the fragment as read and one with a fragment whose
+// adjacent lanes are exchanged and whose even lanes are negated (DPP quad
+// permute plus a sign flip: exact).  Every output gets the same two exact
+// products in the same order as from planar data, so results are bitwise
+// identical; the accumulator row of an element is its real column, so the
+// tile stores as rows of 2 x 64 floats per wave.
+__device__ __forceinline__ half8 swap_negate_even(half8 v, uint32_t sign) {
+    u32x4 u = __builtin_bit_cast(u32x4, v);
+    u32x4 w;
+    w.x = (uint32_t)__builtin_amdgcn_mov_dpp((int)u.x, 0xB1, 0xF, 0xF, false) ^ sign;  // quad_perm [1, 0, 3, 2]
+    w.y = (uint32_t)__builtin_amdgcn_mov_dpp((int)u.y, 0xB1, 0xF, 0xF, false) ^ sign;
+    w.z = (uint32_t)__builtin_amdgcn_mov_dpp((int)u.z, 0xB1, 0xF, 0xF, false) ^ sign;
+    w.w = (uint32_t)__builtin_amdgcn_mov_dpp((int)u.w, 0xB1, 0xF, 0xF, false) ^ sign;
+    return __builtin_bit_cast(half8, w);
+}
+
+// One 16-receiver step on interleaved data: a[i][j] rows are the real
+// columns 32 j .. 32 j + 31 of the wave's 128.
+__device__ __forceinline__ void mma_step_wx_il(f32x16 (&a)[2][4], const half8 (&wr)[2], const half8 (&wi)[2],
+                                               const half8 (&x)[4], uint32_t sign) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const half8 y = swap_negate_even(x[j], sign);
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            a[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(wr[i], x[j], a[i][j], 0, 0, 0);
+            a[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(wi[i], y, a[i][j], 0, 0, 0);
+        }
+    }
+}
+
+// Store a wave's 64 beams x 128 real columns (64 samples from sample nw)
+// from accumulators laid out as mma_step_wx_il leaves them, one 4-byte store
+// per register, each writing two whole 128-byte row runs.  Interleaved output:
+// the registers as they are.  Planar output: a register holds Re and Im of
+// 16 samples in alternating lanes (a store of it would write half lines,
+// measured 14 times slower), so the two registers of the same beam rows in
+// fragments j and j + 1 (samples 16 j .. 16 j + 31) are regrouped across
+// lanes first (ds_bpermute, no LDS memory): lane t then holds Re, and in a
+// second register Im, of sample 16 j + t.
+template <int CIL>
+__device__ __forceinline__ void store_block_wx_il(const f32x16 (&a)[2][4], float *Cc, int M, int N, int mw, int nw,
+                                                  int lane) {
+    const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc((void *)Cc, 0, 8 * M * N, RSRC_FLAGS);
+    const int hl = lane >> 5, l32 = lane & 31;
+    const bool whole = mw + 64 <= M && nw + 64 <= N;
+    if constexpr (!CIL) {
+        // source lanes (byte addresses for ds_bpermute) of Re and Im of sample t % 16
+        const int src_re = ((lane & 32) + 2 * (l32 & 15)) * 4, src_im = src_re + 4;
+        const bool upper = l32 >= 16;  // samples 16..31 of the pair come from fragment j + 1
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int jp = 2 * q;
+                const int n = nw + 16 * jp + l32;
+                const bool n_ok = n < N;
+                const int mb = mw + 32 * i + 4 * hl;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const float f0 = a[i][jp][r], f1 = a[i][jp + 1][r];  // through scalars (see below)
+                    const int v0 = __builtin_bit_cast(int, f0), v1 = __builtin_bit_cast(int, f1);
+                    const int re0 = __builtin_amdgcn_ds_bpermute(src_re, v0), re1 = __builtin_amdgcn_ds_bpermute(src_re, v1);
+                    const int im0 = __builtin_amdgcn_ds_bpermute(src_im, v0), im1 = __builtin_amdgcn_ds_bpermute(src_im, v1);
+                    const int m = mb + 8 * (r >> 2) + (r & 3);
+                    const bool ok = whole || (n_ok && m < M);
+                    const uint32_t off = ok ? (uint32_t)((m * N + n) * 4) : OOB;
+                    const uint32_t offi = ok ? (uint32_t)(((M + m) * N + n) * 4) : OOB;
+                    __builtin_amdgcn_raw_buffer_store_b32((uint32_t)(upper ? re1 : re0), rc, off, 0, kStoreStreaming);
+                    __builtin_amdgcn_raw_buffer_store_b32((uint32_t)(upper ? im1 : im0), rc, offi, 0, kStoreStreaming);
+                }
+            }
+        return;
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int c = 2 * nw + 32 * j + l32;  // real column of this lane
+            const bool n_ok = (c >> 1) < N;
+            const int mb = mw + 32 * i + 4 * hl;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int m = mb + 8 * (r >> 2) + (r & 3);
+                const bool ok = whole || (n_ok && m < M);
+                const uint32_t off = ok ? (uint32_t)((m * 2 * N + c) * 4) : OOB;
+                const float v = a[i][j][r];  // through a scalar: a bit cast of a vector element reads element 0
+                __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), rc, off, 0, kStoreStreaming);
+            }
+        }
+}
+
+template <int CIL, int AB, int BIL>
 __global__ __launch_bounds__(512, 1) void cgemm_f16_pp_kernel(const uint16_t *__restrict__ A,
                                                               const uint16_t *__restrict__ B,
                                                               float *__restrict__ C, int M, int N, int K,
@@ -982,12 +1100,27 @@ __global__ __launch_bounds__(512, 1) void cgemm_f16_pp_kernel(const uint16_t *__
         am = m;
         va = AB ? (uint32_t)(((p * (KW / 32)) * M + m) * 64 + ch * 16) : (uint32_t)(((p * M + m) * K + ch * 8) * 2);
     }
-    {
+    // interleaved data: piece q of this wave is rows 2 (wave XPW + q) and +1
+    // (512 bytes each, 32 chunks of 4 complex samples); the chunk swizzle
+    // follows the row, so each piece has its own lane offset
+    uint32_t vbi[XPW];
+    int xchi[XPW];
+    if constexpr (!BIL) {
         const int s = wave * XPW * 64 + lane;
         const int p = s / (32 * 16), k = (s / 16) % 32, ch = (s & 15) ^ G::swzX(k);
         kb = k;
         xch = ch;
         vb0 = (uint32_t)(((p * K + k) * N + ch * 8) * 2);
+    } else {
+        kb = 2 * wave * XPW + hl;  // row of piece 0
+        xch = 0;
+        vb0 = 0;
+#pragma unroll
+        for (int q = 0; q < XPW; ++q) {
+            const int k = kb + 2 * q;
+            xchi[q] = l32 ^ G::swzX(k);
+            vbi[q] = (uint32_t)((k * N + 4 * xchi[q]) * 4);
+        }
     }
     // fragment offsets in a stage (plane 0), as in the fast kernel with TM = 256
     int ow[2], ox[2];
@@ -996,6 +1129,7 @@ __global__ __launch_bounds__(512, 1) void cgemm_f16_pp_kernel(const uint16_t *__
         const int m = wm * 64 + l32;
         ow[s] = m * 64 + (((2 * s + hl) ^ G::swzW(m)) * 16);
     }
+    int oxi[4];  // interleaved data: 4 fragments of 32 real columns, rows of 512 bytes
     {
         const int g = lane >> 4, j16 = lane & 15;
         const int krow = 8 * (g >> 1) + (j16 >> 2);
@@ -1004,9 +1138,15 @@ __global__ __launch_bounds__(512, 1) void cgemm_f16_pp_kernel(const uint16_t *__
             const int ns = wn * 64 + 32 * j + 16 * (g & 1) + 4 * (j16 & 3);
             ox[j] = G::WREG + krow * 256 + (((ns >> 3) ^ G::swzX(krow)) * 16) + (ns & 7) * 2;
         }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int cs = wn * 128 + 32 * j + 16 * (g & 1) + 4 * (j16 & 3);
+            oxi[j] = G::WREG + krow * 512 + (((cs >> 3) ^ G::swzX(krow)) * 16) + (cs & 7) * 2;
+        }
     }
+    const uint32_t neg_even = (lane & 1) ? 0u : 0x80008000u;  // sign flip of both halves in even lanes
 
-    auto tile_of = [&](int round, int &c, int &m0, int &n0) {
+    auto tile_of = [&](int round, int &c, int &m0, int &n0) __attribute__((always_inline)) {
         const int t = round * grid + pos;
         c = t / per_c;
         int tm, tn;
@@ -1019,8 +1159,11 @@ __global__ __launch_bounds__(512, 1) void cgemm_f16_pp_kernel(const uint16_t *__
     int l_round = 0, l_kt = 0, l_m0 = 0, l_wso = 0;
     bool l_live = true, l_rows_full = true;
     uint32_t l_vb = OOB;
+    uint32_t l_vbi[XPW];
+#pragma unroll
+    for (int q = 0; q < XPW; ++q) l_vbi[q] = OOB;
     __amdgpu_buffer_rsrc_t rw, rx;
-    auto load_tile = [&]() {
+    auto load_tile = [&]() __attribute__((always_inline)) {
         l_live = l_round < ntiles;
         if (l_live) {
             int c, m0, n0;
@@ -1033,13 +1176,17 @@ __global__ __launch_bounds__(512, 1) void cgemm_f16_pp_kernel(const uint16_t *__
             l_rows_full = m0 + TM <= M;
             l_wso = AB ? m0 * 64 : m0 * K * 2;
             l_vb = (n0 + xch * 8 < N) ? vb0 + (uint32_t)(n0 * 2) : OOB;
+            if constexpr (BIL) {
+#pragma unroll
+                for (int q = 0; q < XPW; ++q) l_vbi[q] = (n0 + 4 * xchi[q] < N) ? vbi[q] + (uint32_t)(n0 * 4) : OOB;
+            }
         }
     };
     // Issue this wave's loads of the cursor's stage into `base` and advance.
     // Stages past the last are issued too, with every offset out of range
     // (zero fills of buffers nobody reads again), so every wait count is the
     // same on every path.
-    auto issue = [&](char *base) {
+    auto issue = [&](char *base) __attribute__((always_inline)) {
         const int k0 = l_kt * 32;
         const bool tail = k0 + 32 > K;
 #pragma unroll
@@ -1054,10 +1201,11 @@ __global__ __launch_bounds__(512, 1) void cgemm_f16_pp_kernel(const uint16_t *__
         }
 #pragma unroll
         for (int q = 0; q < XPW; ++q) {
-            uint32_t off = l_vb;
-            if (tail && k0 + kb + q * XROWS >= K) off = OOB;  // receivers past K
+            uint32_t off = BIL ? l_vbi[q] : l_vb;
+            const int krow = BIL ? kb + 2 * q : kb + q * XROWS;
+            if (tail && k0 + krow >= K) off = OOB;  // receivers past K
             if (!l_live) off = OOB;
-            const int so = !l_live ? 0 : (k0 + q * XROWS) * N * 2;
+            const int so = !l_live ? 0 : BIL ? k0 * N * 4 : (k0 + q * XROWS) * N * 2;
             __builtin_amdgcn_raw_ptr_buffer_load_lds(rx, (LDS_AS void *)(base + G::WREG + (wave * XPW + q) * 1024),
                                                      16, off, so, 0, 0);
         }
@@ -1069,7 +1217,8 @@ __global__ __launch_bounds__(512, 1) void cgemm_f16_pp_kernel(const uint16_t *__
     };
 
     half8 wr[2][2], wi[2][2], xr[2][2], xi[2][2];  // [step][sub-tile]
-    auto read_frags = [&](const char *st) {
+    half8 xc[2][4];                                 // interleaved data: [step][32 real columns]
+    auto read_frags = [&](const char *st) __attribute__((always_inline)) {
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
 #pragma unroll
@@ -1077,38 +1226,65 @@ __global__ __launch_bounds__(512, 1) void cgemm_f16_pp_kernel(const uint16_t *__
                 wr[s][i] = *reinterpret_cast<const half8 *>(st + ow[s] + i * 32 * 64);
                 wi[s][i] = *reinterpret_cast<const half8 *>(st + ow[s] + i * 32 * 64 + TM * 64);
             }
+            if constexpr (BIL) {
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const int o = ox[j] + s * 16 * 256;
-                xr[s][j] = tr_frag(st, o, o + 4 * 256);
-                xi[s][j] = tr_frag(st, o + 32 * BN * 2, o + 32 * BN * 2 + 4 * 256);
+                for (int j = 0; j < 4; ++j) {
+                    const int o = oxi[j] + s * 16 * 512;
+                    xc[s][j] = tr_frag(st, o, o + 4 * 512);
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < 2; ++j) {
+                    const int o = ox[j] + s * 16 * 256;
+                    xr[s][j] = tr_frag(st, o, o + 4 * 256);
+                    xi[s][j] = tr_frag(st, o + 32 * BN * 2, o + 32 * BN * 2 + 4 * 256);
+                }
             }
         }
     };
 
-    Acc acc;
-    acc.zero();
+    Acc acc;  // planar data; interleaved data keeps its rows (real columns) in ail
+    f32x16 ail[2][4];
+    auto acc_zero = [&]() __attribute__((always_inline)) {
+        if constexpr (BIL) {
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) ail[i][j] = (f32x16){};
+        } else {
+            acc.zero();
+        }
+    };
+    acc_zero();
     int c_round = 0, c_kt = 0;  // compute cursor
-    auto store_round = [&](int round) {
+    auto store_round = [&](int round) __attribute__((always_inline)) {
         int c, m0, n0;
         tile_of(round, c, m0, n0);
-        store_block_wx<CIL>(acc, C + (int64_t)c * 2 * M * N, M, N, m0 + wm * 64, n0 + wn * 64, lane);
+        if constexpr (BIL)
+            store_block_wx_il<CIL>(ail, C + (int64_t)c * 2 * M * N, M, N, m0 + wm * 64, n0 + wn * 64, lane);
+        else
+            store_block_wx<CIL>(acc, C + (int64_t)c * 2 * M * N, M, N, m0 + wm * 64, n0 + wn * 64, lane);
     };
     constexpr int kWaitNext = vmcnt_imm(PER_STAGE), kWaitAll = vmcnt_imm(0);
-    auto step = [&](char *rd, char *ld) {
+    auto step = [&](char *rd, char *ld) __attribute__((always_inline)) {
         // data phase
         issue(ld);
         read_frags(rd);
         __builtin_amdgcn_s_waitcnt(kWaitNext);  // own loads of the next stage landed
         if (c_kt == 0 && c_round > 0) {         // the previous stage ended a tile
             store_round(c_round - 1);
-            acc.zero();
+            acc_zero();
         }
         __builtin_amdgcn_s_waitcnt(kWaitLds);
         pp_barrier();
         // matrix phase
-        mma_step_wx(acc, wr[0], wi[0], xr[0], xi[0]);
-        mma_step_wx(acc, wr[1], wi[1], xr[1], xi[1]);
+        if constexpr (BIL) {
+            mma_step_wx_il(ail, wr[0], wi[0], xc[0], neg_even);
+            mma_step_wx_il(ail, wr[1], wi[1], xc[1], neg_even);
+        } else {
+            mma_step_wx(acc, wr[0], wi[0], xr[0], xi[0]);
+            mma_step_wx(acc, wr[1], wi[1], xr[1], xi[1]);
+        }
         if (++c_kt == nk) {
             c_kt = 0;
             ++c_round;
@@ -1270,6 +1446,15 @@ static bool fast_ok(const Problem &p) {
 
 static bool reads_blocked(int v) { return v == 2 || v == 5 || v == 6 || v == 8 || v == 9; }
 
+// The ping-pong kernel also reads interleaved data (X as [K][N][2]): the
+// fast kernels' conditions with X planar or interleaved.
+static bool pp_ok(const Problem &p) {
+    if (p.b_layout != TCBF_INTERLEAVED) return fast_ok(p);
+    Problem q = p;
+    q.b_layout = TCBF_PLANAR;
+    return fast_ok(q);
+}
+
 // Compute units of `device` (the persistent kernel runs one workgroup on
 // each); 256, the MI355X's count, when the runtime cannot say (no device).
 static int device_cus(int device) {
@@ -1283,10 +1468,16 @@ static int device_cus(int device) {
 // CU and measured 4-13% faster than variant 2 on such shapes), variant 2 for
 // smaller problems, the generic kernel where the fast ones do not apply.
 static int default_variant(const Problem &p) {
-    if (!fast_ok(p)) return 1;
     const int64_t tiles = p.batch * ((p.M + 255) / 256) * ((p.N + BN - 1) / BN);
-    if (tiles >= device_cus(p.device) && tiles * ((p.K + 31) / 32) < ((int64_t)1 << 31)) return kPingPong;
-    return kDefaultFast;
+    const bool big = tiles >= device_cus(p.device) && tiles * ((p.K + 31) / 32) < ((int64_t)1 << 31);
+    // interleaved data: the ping-pong kernel (also for fewer tiles than CUs
+    // when W is receiver-blocked, which only the fast kernels read)
+    if (p.b_layout == TCBF_INTERLEAVED)
+        return pp_ok(p) && tiles * ((p.K + 31) / 32) < ((int64_t)1 << 31) && (big || p.a_layout == TCBF_BLOCKED)
+                   ? kPingPong
+                   : 1;
+    if (!fast_ok(p)) return 1;
+    return big ? kPingPong : kDefaultFast;
 }
 
 bool f16_select(const Problem &p, int forced_variant, F16Config *cfg) {
@@ -1294,7 +1485,7 @@ bool f16_select(const Problem &p, int forced_variant, F16Config *cfg) {
     int v = forced_variant;
     if (v == 0) v = default_variant(p);
     if (v < 1 || v >= kFirstFast + kNumFast) return false;
-    if (v >= kFirstFast && !fast_ok(p)) return false;
+    if (v >= kFirstFast && !(v == kPingPong ? pp_ok(p) : fast_ok(p))) return false;
     if (ab && !reads_blocked(v)) return false;
     if (v == kPingPong) {
         // the persistent kernel counts a workgroup's stages in 32 bits
@@ -1332,8 +1523,11 @@ hipError_t f16_launch(const Problem &p, const F16Config &cfg, const void *A, con
     int64_t nblocks = p.batch * tiles_m * tiles_n;
     if (cfg.variant == kPingPong) {
         const bool ab = p.a_layout == TCBF_BLOCKED, cil = p.c_layout == TCBF_INTERLEAVED;
-        FastFn fn = ab ? (cil ? cgemm_f16_pp_kernel<1, 1> : cgemm_f16_pp_kernel<0, 1>)
-                       : (cil ? cgemm_f16_pp_kernel<1, 0> : cgemm_f16_pp_kernel<0, 0>);
+        static const FastFn pp[8] = {cgemm_f16_pp_kernel<0, 0, 0>, cgemm_f16_pp_kernel<0, 0, 1>,
+                                     cgemm_f16_pp_kernel<0, 1, 0>, cgemm_f16_pp_kernel<0, 1, 1>,
+                                     cgemm_f16_pp_kernel<1, 0, 0>, cgemm_f16_pp_kernel<1, 0, 1>,
+                                     cgemm_f16_pp_kernel<1, 1, 0>, cgemm_f16_pp_kernel<1, 1, 1>};
+        const FastFn fn = pp[(cil << 2) | (ab << 1) | (p.b_layout == TCBF_INTERLEAVED)];
         const int grid = (int)std::min<int64_t>(nblocks, device_cus(p.device));
         hipLaunchKernelGGL(fn, dim3((uint32_t)grid), dim3(cfg.threads), 0, stream, (const uint16_t *)A,
                            (const uint16_t *)B, (float *)C, (int)p.M, (int)p.N, (int)p.K, p.a_shared, tiles_m,

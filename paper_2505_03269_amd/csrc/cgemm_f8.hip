@@ -98,7 +98,15 @@ __device__ __forceinline__ void f8_tile(const uint8_t *__restrict__ A, const uin
                                         int c, int tm, int tn, char *lds0, char *lds1, char *lds2, char *lds3,
                                         char *slabs) {
     static_assert(NS >= 2 && NS <= 4 && NS <= SLAB_STAGES + 1, "ring depth");
-    char *const bufs[4] = {lds0, lds1, lds2, lds3};
+    // stage buffer i: a select chain, not an array (an LDS pointer array the
+    // compiler cannot index statically goes to scratch as generic pointers)
+    auto bufs = [&](int i) __attribute__((always_inline)) -> char * {
+        char *b = lds0;
+        if (i == 1) b = lds1;
+        if (i == 2) b = lds2;
+        if (i == 3) b = lds3;
+        return b;
+    };
     const int tid = threadIdx.x;
     const int m0 = tm * BM, n0 = tn * BN;
 
@@ -163,7 +171,7 @@ __device__ __forceinline__ void f8_tile(const uint8_t *__restrict__ A, const uin
         group_bytes = rows * SLAB_ROWB;
     }
 
-    auto issue = [&](char *base, int kt) {
+    auto issue = [&](char *base, int kt) __attribute__((always_inline)) {
         const int k0 = kt * BK;
         const bool kin = k0 + kc < Kp;
 #pragma unroll
@@ -195,7 +203,7 @@ __device__ __forceinline__ void f8_tile(const uint8_t *__restrict__ A, const uin
     // makes an LDS read wait for every direct load into the same array still
     // in flight; with a two-stage ring none is at that point (with three, the
     // next stage's loads are waited for here).
-    auto read_scales = [&](int kt, int *sc) {
+    auto read_scales = [&](int kt, int *sc) __attribute__((always_inline)) {
         const char *sl = slabs + (kt / SLAB_STAGES % 2) * SLAB + 2 * (kt % SLAB_STAGES) + hl;
         const bool bin = 2 * kt + hl < nkb;
 #pragma unroll
@@ -206,7 +214,7 @@ __device__ __forceinline__ void f8_tile(const uint8_t *__restrict__ A, const uin
             sc[2 + i] = bin ? x : SCALE_ONE;
         }
     };
-    auto compute = [&](const char *st, const int *sc) {
+    auto compute = [&](const char *st, const int *sc) __attribute__((always_inline)) {
         i32x8 xr[2], xi[2];
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
@@ -237,19 +245,19 @@ __device__ __forceinline__ void f8_tile(const uint8_t *__restrict__ A, const uin
     static_assert((NS - 2) * PER_STAGE < 64, "vmcnt range");
     constexpr int kWaitRing = vmcnt_imm((NS - 2) * PER_STAGE), kWaitAll = vmcnt_imm(0);
     const int nk = (Kp + BK - 1) / BK;
-    auto stage_step = [&](int kt, int u) {
+    auto stage_step = [&](int kt, int u) __attribute__((always_inline)) {
         if (kt + NS - 2 < nk) __builtin_amdgcn_s_waitcnt(kWaitRing);
         else __builtin_amdgcn_s_waitcnt(kWaitAll);
         // all waves' loads for stage kt landed, stage kt-1 fully read
         asm volatile("s_barrier" ::: "memory");
         int sc[4] = {SCALE_ONE, SCALE_ONE, SCALE_ONE, SCALE_ONE};
         if (MX) read_scales(kt, sc);
-        if (kt + NS - 1 < nk) issue(bufs[(u + NS - 1) % NS], kt + NS - 1);
-        compute(bufs[u], sc);
+        if (kt + NS - 1 < nk) issue(bufs((u + NS - 1) % NS), kt + NS - 1);
+        compute(bufs(u), sc);
     };
 #pragma unroll
     for (int s = 0; s < NS - 1; ++s)
-        if (s < nk) issue(bufs[s], s);
+        if (s < nk) issue(bufs(s), s);
     int kt0 = 0;
     for (; kt0 + NS <= nk; kt0 += NS) {
 #pragma unroll
@@ -295,7 +303,7 @@ __device__ __forceinline__ void f8_tile(const uint8_t *__restrict__ A, const uin
     // Epilogue through the (now idle) stage buffers.
     constexpr int ROWS_PER_BUF = STAGE / staging_pitch<CIL>();
     static_assert(ROWS_PER_BUF * 2 >= (CIL ? 64 : 128), "two stage buffers hold a staging round");
-    auto row_ptr = [&](int row) -> char * {
+    auto row_ptr = [&](int row) __attribute__((always_inline)) -> char * {
         return (row < ROWS_PER_BUF ? lds0 : lds1) + (row % ROWS_PER_BUF) * staging_pitch<CIL>();
     };
     store_tile_staged<2, CIL>(acc, row_ptr, C + (int64_t)c * 2 * M * N, M, N, m0, n0, wave, lane);

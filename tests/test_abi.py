@@ -68,7 +68,8 @@ def _plan_status(**kw):
     dict(dtype=tcbf.F8_E4M3, a_layout=tcbf.BLOCKED), dict(dtype=tcbf.MXF8_E4M3, a_layout=tcbf.BLOCKED),
     dict(dtype=tcbf.F8_E4M3, b_layout=tcbf.BLOCKED), dict(dtype=tcbf.INT1, b_layout=tcbf.BLOCKED),
     dict(dtype=tcbf.F8_E4M3, a_layout=tcbf.BLOCKED, b_layout=tcbf.BLOCKED, N=6),
-    dict(a_layout=tcbf.BLOCKED, b_layout=tcbf.INTERLEAVED), dict(a_layout=tcbf.BLOCKED, N=12),
+    dict(a_layout=tcbf.BLOCKED, b_layout=tcbf.INTERLEAVED, N=12), dict(a_layout=tcbf.BLOCKED, N=12),
+    dict(a_layout=tcbf.BLOCKED, b_layout=tcbf.INTERLEAVED, variant=2),
     dict(a_layout=tcbf.BLOCKED, variant=1), dict(a_layout=tcbf.BLOCKED, variant=3),
     dict(a_layout=tcbf.BLOCKED, variant=4), dict(a_layout=tcbf.BLOCKED, variant=7),
     dict(dtype=tcbf.INT1, a_layout=tcbf.INTERLEAVED), dict(dtype=tcbf.INT1, b_layout=tcbf.INTERLEAVED),

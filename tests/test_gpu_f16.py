@@ -279,3 +279,76 @@ def test_largest_channel_takes_the_generic_kernel():
     ref = oracle.cgemm_entries(Wc, Xc, np.zeros(ms.size, np.int64), np.arange(ms.size), ns)
     assert np.array_equal(got[0, ms, ns], ref.real) and np.array_equal(got[1, ms, ns], ref.imag)
 
+
+
+# interleaved data (X as [batch][K][N][2]) through the ping-pong kernel: small,
+# ragged, multi-tile and long-K shapes (several 32-receiver stages, several
+# tiles per workgroup)
+IL_SHAPES = [(1, 130, 136, 40), (2, 200, 264, 72), (1, 129, 8, 520), (2, 1024, 1024, 576), (1, 300, 1000, 104),
+             (1, 64, 4096, 2048)]
+
+
+@pytest.mark.parametrize("batch,M,N,K", IL_SHAPES)
+def test_interleaved_data_ping_pong_bitwise(batch, M, N, K):
+    """Interleaved data through the ping-pong kernel (planar and receiver-blocked
+    weights, planar and interleaved output) equals the generic kernel on
+    planar data bit for bit, which passes the oracle gate."""
+    W, X = wl.random_f16_case(17, batch, M, N, K)
+    gen, _ = run_f16(W, X, variant=1)
+    ref, absdot = oracle_ref(W, X)
+    check_fp_full(gen, ref, absdot, K)
+    Xi = to_dev(np.ascontiguousarray(X.transpose(0, 2, 3, 1)))
+    for al in (tcbf.PLANAR, tcbf.BLOCKED):
+        A = to_dev(W) if al == tcbf.PLANAR else tcbf.block_weights(to_dev(W))
+        for cl in (tcbf.PLANAR, tcbf.INTERLEAVED):
+            log("interleaved data: a=%d c=%d shape=%s" % (al, cl, (batch, M, N, K)))
+            plan = tcbf.Plan(batch, M, N, K, tcbf.F16, a_layout=al, b_layout=tcbf.INTERLEAVED, c_layout=cl,
+                             variant=9)
+            C = plan.empty_output()
+            plan.execute(A, Xi, C)
+            torch.cuda.synchronize()
+            Ch = C.cpu().numpy()
+            got = c_planar_to_complex(Ch) if cl == tcbf.PLANAR else c_inter_to_complex(Ch)
+            assert np.array_equal(got, gen), "interleaved data, a=%d c=%d differs" % (al, cl)
+
+
+def test_interleaved_data_plan_choice():
+    """Large interleaved-data problems take the ping-pong kernel; small ones the
+    generic kernel, or the ping-pong kernel when W is receiver-blocked."""
+    IL = tcbf.INTERLEAVED
+    assert tcbf.Plan(256, 1024, 4096, 576, tcbf.F16, b_layout=IL).info()["variant"] == 9
+    assert tcbf.Plan(256, 1024, 4096, 576, tcbf.F16, a_layout=tcbf.BLOCKED, b_layout=IL).info()["variant"] == 9
+    assert tcbf.Plan(1, 64, 64, 64, tcbf.F16, b_layout=IL).info()["variant"] == 1
+    assert tcbf.Plan(1, 64, 64, 64, tcbf.F16, a_layout=tcbf.BLOCKED, b_layout=IL).info()["variant"] == 9
+    assert tcbf.Plan(1, 64, 100, 64, tcbf.F16, b_layout=IL).info()["variant"] == 1      # N % 8 != 0
+    with pytest.raises(tcbf.TcbfError):
+        tcbf.Plan(1, 64, 64, 64, tcbf.F16, b_layout=IL, variant=2)
+
+
+def test_c2_full_size_interleaved_equals_planar():
+    """The radio-astronomy workload at full size with interleaved data and
+    interleaved output (weights receiver-blocked, the launch the benchmark's
+    interleaved line times): the whole output equals the planar-data product bit
+    for bit after de-interleaving (that product is checked against the oracle on
+    sampled entries above)."""
+    cfg = wl.WORKLOADS["radio-astro-fp16"]
+    log("c2 interleaved: generating inputs")
+    W, X = wl.generate_c2()
+    A, B = to_dev(W), to_dev(X)
+    del W, X
+    Ab = tcbf.block_weights(A)
+    del A
+    Bi = B.permute(0, 2, 3, 1).contiguous()
+    shape = (cfg["batch"], cfg["M"], cfg["N"], cfg["K"])
+    pp = tcbf.Plan(*shape, tcbf.F16, a_layout=tcbf.BLOCKED)
+    pi = tcbf.Plan(*shape, tcbf.F16, a_layout=tcbf.BLOCKED, b_layout=tcbf.INTERLEAVED, c_layout=tcbf.INTERLEAVED)
+    assert pi.info()["variant"] == 9
+    Cp = pp.empty_output()
+    log("c2 interleaved: execute planar")
+    pp.execute(Ab, B, Cp)
+    del B
+    Ci = pi.empty_output()
+    log("c2 interleaved: execute interleaved")
+    pi.execute(Ab, Bi, Ci)
+    torch.cuda.synchronize()
+    assert torch.equal(Cp, Ci.permute(0, 3, 1, 2))
