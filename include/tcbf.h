@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define TCBF_VERSION 2
+#define TCBF_VERSION 3
 
 typedef enum tcbf_status {
     TCBF_SUCCESS = 0,
@@ -305,8 +305,12 @@ tcbf_status tcbf_steering_weights(const double *positions, const double *directi
  * (the paper's Sec. IV-C size sweep shows per-shape padding and tail effects;
  * one shared list keeps every CU busy across shape boundaries); persistent
  * workgroups (two per CU) take tiles from a device counter until the list is
- * empty.  The problem table travels in the launch's kernel arguments, so the
- * call can be captured in a HIP graph and replayed.
+ * empty.  fp16 problems whose variant (given, or the plan's default) has
+ * 256-beam tiles (6, 7, 9) run instead in a grouped form of the ping-pong
+ * kernel (one 512-thread workgroup per CU, a static tile list), so a call
+ * makes at most two persistent launches, one after the other on `stream`.
+ * The problem table travels in the launch's kernel arguments, so the call
+ * can be captured in a HIP graph and replayed.
  *   problems: host array of `count` descriptors (1 <= count <= TCBF_GROUP_MAX);
  *     each needs batch, M, N, K >= 1, 16-byte aligned device pointers and
  *     the size limits of a plan of its dtype; fp16: N a multiple of 8 and
@@ -336,6 +340,10 @@ typedef struct tcbf_group_problem {
                             launch.                                           */
     const void *a_scale; /* FP8 modes: W scales; fp16: NULL                   */
     const void *b_scale; /* FP8 modes: X scales; fp16: NULL                   */
+    int32_t variant;     /* fp16: 0 = the plan's default for this problem, or
+                            a fast variant 2..9 a plan of this problem takes
+                            (e.g. the autotuner's choice); FP8, 1-bit: 0     */
+    int32_t reserved;    /* 0                                                 */
 } tcbf_group_problem;
 
 tcbf_status tcbf_group_execute(int32_t device, int32_t dtype, int32_t c_layout,

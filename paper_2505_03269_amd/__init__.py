@@ -59,7 +59,8 @@ class GroupProblem(ctypes.Structure):
     _fields_ = [("A", ctypes.c_void_p), ("B", ctypes.c_void_p), ("C", ctypes.c_void_p),
                 ("batch", ctypes.c_int64), ("M", ctypes.c_int64), ("N", ctypes.c_int64), ("K", ctypes.c_int64),
                 ("a_shared", ctypes.c_int32), ("layout", ctypes.c_int32),
-                ("a_scale", ctypes.c_void_p), ("b_scale", ctypes.c_void_p)]
+                ("a_scale", ctypes.c_void_p), ("b_scale", ctypes.c_void_p),
+                ("variant", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -470,7 +471,8 @@ def peak_probe(kind, blocks, iterations, operand_bits=None, random=False, sink=N
     return ops.value, values, marks
 
 
-def group_execute(problems, c_layout=PLANAR, workspace=None, device=0, stream=None, dtype=F16, layout=PLANAR):
+def group_execute(problems, c_layout=PLANAR, workspace=None, device=0, stream=None, dtype=F16, layout=PLANAR,
+                  variants=None):
     """One grouped persistent launch over up to GROUP_MAX problems of one dtype.
 
     dtype F16: problems are (W, X, C) or (W, X, C, a_shared) device tensors
@@ -488,9 +490,13 @@ def group_execute(problems, c_layout=PLANAR, workspace=None, device=0, stream=No
     (interleaved).
     workspace: uint8 device tensor of GROUP_WORKSPACE_BYTES (allocated here
     if None; pass one to stay allocation-free).
+    variants: fp16 only, one kernel variant per problem (0 = the plan's
+    default; e.g. the autotuner's choice, tune.tuned_variant); problems with
+    256-beam-tile variants (6, 7, 9) run in a grouped ping-pong launch, the
+    rest in the grouped 128 x 128 launch.
     """
     import torch
-    arr = _group_table(problems, c_layout, dtype, layout)
+    arr = _group_table(problems, c_layout, dtype, layout, variants)
     if workspace is None:
         workspace = torch.empty(GROUP_WORKSPACE_BYTES, dtype=torch.uint8, device="cuda:%d" % device)
     if workspace.numel() * workspace.element_size() < GROUP_WORKSPACE_BYTES:
@@ -501,21 +507,24 @@ def group_execute(problems, c_layout=PLANAR, workspace=None, device=0, stream=No
     return [pr[2] for pr in problems]
 
 
-def group_execute_noalloc(problems, c_layout=PLANAR, device=0, stream=None, dtype=F16, layout=PLANAR):
+def group_execute_noalloc(problems, c_layout=PLANAR, device=0, stream=None, dtype=F16, layout=PLANAR,
+                          variants=None):
     """The grouped launch of group_execute (same problem tuples and results)
     through the allocation-free entry point: its tile counter lives in the
     library's per-GPU scratch array, so launches of this call that overlap in
     time on one GPU race (use group_execute with one workspace per stream)."""
-    arr = _group_table(problems, c_layout, dtype, layout)
+    arr = _group_table(problems, c_layout, dtype, layout, variants)
     _check(lib().tcbf_group_execute_noalloc(int(device), int(dtype), int(c_layout), arr, len(problems),
                                             _stream_handle(stream)),
            "tcbf_group_execute_noalloc")
     return [pr[2] for pr in problems]
 
 
-def _group_table(problems, c_layout, dtype, layout):
+def _group_table(problems, c_layout, dtype, layout, variants=None):
     """Check the problem tuples of a grouped launch and build its C table."""
     import torch
+    if variants is not None and len(variants) != len(problems):
+        raise ValueError("one variant per problem")
     if not 1 <= len(problems) <= GROUP_MAX:
         raise ValueError("1..%d problems per launch" % GROUP_MAX)
     f8 = _is_f8(dtype)
@@ -578,5 +587,6 @@ def _group_table(problems, c_layout, dtype, layout):
                     raise ValueError("problem %d: %s must be %s %s" % (i, nm, st, tuple(shape)))
             sa, sb = _dev_ptr(pr[3], "a_scale").value, _dev_ptr(pr[4], "b_scale").value
         arr[i] = GroupProblem(_dev_ptr(W, "W").value, _dev_ptr(X, "X").value, _dev_ptr(C, "C").value,
-                              batch, M, N, K, int(shared), int(layout), sa, sb)
+                              batch, M, N, K, int(shared), int(layout), sa, sb,
+                              0 if variants is None else int(variants[i]), 0)
     return arr

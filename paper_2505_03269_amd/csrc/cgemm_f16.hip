@@ -1368,6 +1368,239 @@ __global__ __launch_bounds__(256, 2) void cgemm_f16_group_kernel(const GroupArgs
     }
 }
 
+// Grouped form of the ping-pong kernel: the tiles (256 beams x 128 samples)
+// of several problems form one list, longest receiver count first, and
+// workgroup `pos` runs tiles pos, pos + grid, ... (a static list: the stage
+// sequence runs on across tiles, so each workgroup must know its next tile
+// two stages ahead).  The loop is the ping-pong kernel's, with the problem
+// of the load cursor's tile and of the compute cursor's tile looked up in
+// the table when each cursor moves on; the per-lane load offsets, which
+// depend on the problem's sizes, are recomputed then.  Same fragments, same
+// matrix instructions in the same order: every problem's output equals its
+// plan's bit for bit.  Planar X.
+struct PpGroupProblem {
+    const uint16_t *A;
+    const uint16_t *B;
+    float *C;
+    int M, N, K, a_shared;
+    int tiles_m, tiles_n;  // 256 x 128 tiles per channel
+    int first_tile;
+    int nk;  // 32-receiver stages per tile
+};
+struct PpGroupArgs {
+    PpGroupProblem p[TCBF_GROUP_MAX];
+    int count, total_tiles;
+};
+
+template <int CIL, int AB>
+__global__ __launch_bounds__(512, 1) void cgemm_f16_pp_group_kernel(const PpGroupArgs args) {
+    typedef FastGeo<4, 32> G;
+    constexpr int TM = G::TM, NW = G::NW;
+    __shared__ __attribute__((aligned(1024))) char lds0[G::STAGE];
+    __shared__ __attribute__((aligned(1024))) char lds1[G::STAGE];
+    __shared__ __attribute__((aligned(1024))) char lds2[G::STAGE];
+
+    const int grid = (int)gridDim.x;
+    const int pos = (int)xcd_remap(blockIdx.x, grid);
+    const int total = args.total_tiles;
+    const int ntiles = (total - pos + grid - 1) / grid;  // >= 1: grid <= total
+
+    auto problem_of = [&](int t) __attribute__((always_inline)) {
+        int pi = 0;
+        for (int i = 1; i < args.count; ++i)
+            if (t >= args.p[i].first_tile) pi = i;
+        return pi;
+    };
+    // stages this workgroup runs
+    int S = 0;
+    for (int r = 0; r < ntiles; ++r) S += args.p[problem_of(r * grid + pos)].nk;
+
+    const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lane = tid & 63;
+    const int wm = wave >> 1, wn = wave & 1, grp = wave >> 2;
+    const int hl = lane >> 5;
+
+    // this lane's chunk coordinates in a stage (problem-independent); the
+    // byte offsets follow from the problem's sizes
+    constexpr int WPW = G::WREG / 1024 / NW, XPW = G::XREG / 1024 / NW;
+    constexpr int WROWS = 64 / G::WCH, XROWS = 64 / 16;
+    constexpr int PER_STAGE = WPW + XPW;
+    int wp, wrow, wch, xp, xk, xch;
+    {
+        const int s = wave * WPW * 64 + lane;
+        wp = s / (TM * G::WCH);
+        wrow = (s / G::WCH) % TM;
+        wch = (s % G::WCH) ^ G::swzW(wrow);
+    }
+    {
+        const int s = wave * XPW * 64 + lane;
+        xp = s / (32 * 16);
+        xk = (s / 16) % 32;
+        xch = (s & 15) ^ G::swzX(xk);
+    }
+    int ow[2], ox[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        const int m = wm * 64 + (lane & 31);
+        ow[s] = m * 64 + (((2 * s + hl) ^ G::swzW(m)) * 16);
+    }
+    {
+        const int g = lane >> 4, j16 = lane & 15;
+        const int krow = 8 * (g >> 1) + (j16 >> 2);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int ns = wn * 64 + 32 * j + 16 * (g & 1) + 4 * (j16 & 3);
+            ox[j] = G::WREG + krow * 256 + (((ns >> 3) ^ G::swzX(krow)) * 16) + (ns & 7) * 2;
+        }
+    }
+
+    auto tile_of = [&](int round, int &pi, int &c, int &m0, int &n0) __attribute__((always_inline)) {
+        const int t = round * grid + pos;
+        pi = problem_of(t);
+        const PpGroupProblem &q = args.p[pi];
+        const int local = t - q.first_tile, per_c = q.tiles_m * q.tiles_n;
+        c = local / per_c;
+        int tm, tn;
+        tile_coords(local - c * per_c, q.tiles_m, q.tiles_n, tm, tn);
+        m0 = tm * TM;
+        n0 = tn * BN;
+    };
+
+    // load cursor
+    int l_round = 0, l_kt = 0, l_m0 = 0, l_wso = 0, l_M = 0, l_N = 0, l_K = 0, l_nk = 1;
+    bool l_live = true, l_rows_full = true;
+    uint32_t l_va = OOB, l_vb = OOB;
+    __amdgpu_buffer_rsrc_t rw, rx;
+    auto load_tile = [&]() __attribute__((always_inline)) {
+        l_live = l_round < ntiles;
+        if (l_live) {
+            int pi, c, m0, n0;
+            tile_of(l_round, pi, c, m0, n0);
+            const PpGroupProblem &q = args.p[pi];
+            l_M = q.M;
+            l_N = q.N;
+            l_K = q.K;
+            l_nk = q.nk;
+            const int KW = AB ? (l_K + 31) / 32 * 32 : l_K;
+            const uint16_t *Wc = q.A + (q.a_shared ? (int64_t)0 : (int64_t)c * 2 * l_M * KW);
+            const uint16_t *Xc = q.B + (int64_t)c * 2 * l_K * l_N;
+            rw = __builtin_amdgcn_make_buffer_rsrc((void *)Wc, 0, 4 * l_M * KW, RSRC_FLAGS);
+            rx = __builtin_amdgcn_make_buffer_rsrc((void *)Xc, 0, 4 * l_K * l_N, RSRC_FLAGS);
+            l_m0 = m0;
+            l_rows_full = m0 + TM <= l_M;
+            l_wso = AB ? m0 * 64 : m0 * l_K * 2;
+            l_va = AB ? (uint32_t)(((wp * (KW / 32)) * l_M + wrow) * 64 + wch * 16)
+                      : (uint32_t)(((wp * l_M + wrow) * l_K + wch * 8) * 2);
+            l_vb = (n0 + xch * 8 < l_N) ? (uint32_t)(((xp * l_K + xk) * l_N + n0 + xch * 8) * 2) : OOB;
+        }
+    };
+    auto issue = [&](char *base) __attribute__((always_inline)) {
+        const int k0 = l_kt * 32;
+        const bool tail = k0 + 32 > l_K;
+#pragma unroll
+        for (int q = 0; q < WPW; ++q) {
+            uint32_t off = l_va;
+            if (!l_rows_full && l_m0 + wrow + q * WROWS >= l_M) off = OOB;
+            if (tail && k0 + wch * 8 >= l_K) off = OOB;
+            if (!l_live) off = OOB;
+            const int so = !l_live ? 0
+                                   : l_wso + (AB ? (k0 / 32) * l_M * 64 + q * WROWS * 64 : k0 * 2 + q * WROWS * l_K * 2);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rw, (LDS_AS void *)(base + (wave * WPW + q) * 1024), 16, off, so,
+                                                     0, 0);
+        }
+#pragma unroll
+        for (int q = 0; q < XPW; ++q) {
+            uint32_t off = l_vb;
+            if (tail && k0 + xk + q * XROWS >= l_K) off = OOB;
+            if (!l_live) off = OOB;
+            const int so = !l_live ? 0 : (k0 + q * XROWS) * l_N * 2;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rx, (LDS_AS void *)(base + G::WREG + (wave * XPW + q) * 1024),
+                                                     16, off, so, 0, 0);
+        }
+        if (++l_kt == l_nk) {
+            l_kt = 0;
+            ++l_round;
+            load_tile();
+        }
+    };
+
+    half8 wr[2][2], wi[2][2], xr[2][2], xi[2][2];
+    auto read_frags = [&](const char *st) __attribute__((always_inline)) {
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                wr[s][i] = *reinterpret_cast<const half8 *>(st + ow[s] + i * 32 * 64);
+                wi[s][i] = *reinterpret_cast<const half8 *>(st + ow[s] + i * 32 * 64 + TM * 64);
+            }
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                const int o = ox[j] + s * 16 * 256;
+                xr[s][j] = tr_frag(st, o, o + 4 * 256);
+                xi[s][j] = tr_frag(st, o + 32 * BN * 2, o + 32 * BN * 2 + 4 * 256);
+            }
+        }
+    };
+
+    Acc acc;
+    acc.zero();
+    // compute cursor: its tile's stage count, and where its output goes
+    int c_round = 0, c_kt = 0, c_nk = 1;
+    auto compute_tile = [&]() __attribute__((always_inline)) {
+        if (c_round < ntiles) {
+            int pi, c, m0, n0;
+            tile_of(c_round, pi, c, m0, n0);
+            c_nk = args.p[pi].nk;
+        }
+    };
+    auto store_round = [&](int round) __attribute__((always_inline)) {
+        int pi, c, m0, n0;
+        tile_of(round, pi, c, m0, n0);
+        const PpGroupProblem &q = args.p[pi];
+        store_block_wx<CIL>(acc, q.C + (int64_t)c * 2 * q.M * q.N, q.M, q.N, m0 + wm * 64, n0 + wn * 64, lane);
+    };
+    constexpr int kWaitNext = vmcnt_imm(PER_STAGE), kWaitAll = vmcnt_imm(0);
+    auto step = [&](char *rd, char *ld) __attribute__((always_inline)) {
+        issue(ld);
+        read_frags(rd);
+        __builtin_amdgcn_s_waitcnt(kWaitNext);
+        if (c_kt == 0 && c_round > 0) {
+            store_round(c_round - 1);
+            acc.zero();
+        }
+        __builtin_amdgcn_s_waitcnt(kWaitLds);
+        pp_barrier();
+        mma_step_wx(acc, wr[0], wi[0], xr[0], xi[0]);
+        mma_step_wx(acc, wr[1], wi[1], xr[1], xi[1]);
+        if (++c_kt == c_nk) {
+            c_kt = 0;
+            ++c_round;
+            compute_tile();
+        }
+        pp_barrier();
+    };
+
+    load_tile();
+    compute_tile();
+    issue(lds0);
+    issue(lds1);
+    __builtin_amdgcn_s_waitcnt(kWaitNext);
+    pp_barrier();
+    if (grp == 1) pp_barrier();
+    int s = 0;
+    for (; s + 3 <= S; s += 3) {
+        step(lds0, lds2);
+        step(lds1, lds0);
+        step(lds2, lds1);
+    }
+    if (s < S) step(lds0, lds2);
+    if (s + 1 < S) step(lds1, lds0);
+    store_round(c_round - 1);
+    if (grp == 0) pp_barrier();
+    __builtin_amdgcn_s_waitcnt(kWaitAll);
+}
+
 __global__ void group_reset_kernel(unsigned int *counter) { *counter = 0u; }
 
 typedef void (*KernFn)(const uint16_t *, const uint16_t *, float *, int64_t, int64_t, int64_t, int,
@@ -1459,8 +1692,11 @@ static bool pp_ok(const Problem &p) {
 // each); 256, the MI355X's count, when the runtime cannot say (no device).
 static int device_cus(int device) {
     int n = 0;
-    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || n <= 0) return 256;
-    return n;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) {
+        (void)hipGetLastError();   // a planning query: leave no error for the caller's next check
+        return 256;
+    }
+    return n > 0 ? n : 256;
 }
 
 // Default choice: the persistent ping-pong kernel once the problem has at
@@ -1553,38 +1789,73 @@ bool f16_group_problem_ok(const Problem &p) { return fast_ok(p); }
 
 int64_t f16_group_tiles(const Problem &p) { return p.batch * ((p.M + BM - 1) / BM) * ((p.N + BN - 1) / BN); }
 
+bool f16_group_pp(int variant) { return variant == 6 || variant == 7 || variant == kPingPong; }
+
 hipError_t f16_group_launch(const Problem *probs, const void *const *A, const void *const *B, void *const *C,
-                            const int *order, int count, int c_layout, int grid, unsigned int *counter,
-                            hipStream_t stream) {
+                            const int *order, const int *variants, int count, int c_layout, int cus,
+                            unsigned int *counter, hipStream_t stream) {
+    // one operand layout per launch (the API checks it)
+    const bool ab = probs[order[0]].a_layout == TCBF_BLOCKED, cil = c_layout == TCBF_INTERLEAVED;
     GroupArgs args;
+    PpGroupArgs pargs;
     memset(&args, 0, sizeof(args));
-    int64_t first = 0;
+    memset(&pargs, 0, sizeof(pargs));
+    int64_t first = 0, pfirst = 0;
+    int n = 0, pn = 0;
     for (int j = 0; j < count; ++j) {
         const int i = order[j];
         const Problem &p = probs[i];
-        GroupProblem &q = args.p[j];
-        q.A = (const uint16_t *)A[i];
-        q.B = (const uint16_t *)B[i];
-        q.C = (float *)C[i];
-        q.M = (int)p.M;
-        q.N = (int)p.N;
-        q.K = (int)p.K;
-        q.a_shared = p.a_shared;
-        q.tiles_m = (int)((p.M + BM - 1) / BM);
-        q.tiles_n = (int)((p.N + BN - 1) / BN);
-        q.first_tile = (int)first;
-        first += f16_group_tiles(p);
+        if (f16_group_pp(variants[i])) {
+            PpGroupProblem &q = pargs.p[pn++];
+            q.A = (const uint16_t *)A[i];
+            q.B = (const uint16_t *)B[i];
+            q.C = (float *)C[i];
+            q.M = (int)p.M;
+            q.N = (int)p.N;
+            q.K = (int)p.K;
+            q.a_shared = p.a_shared;
+            q.tiles_m = (int)((p.M + 255) / 256);
+            q.tiles_n = (int)((p.N + BN - 1) / BN);
+            q.first_tile = (int)pfirst;
+            q.nk = (int)((p.K + 31) / 32);
+            pfirst += p.batch * q.tiles_m * q.tiles_n;
+        } else {
+            GroupProblem &q = args.p[n++];
+            q.A = (const uint16_t *)A[i];
+            q.B = (const uint16_t *)B[i];
+            q.C = (float *)C[i];
+            q.M = (int)p.M;
+            q.N = (int)p.N;
+            q.K = (int)p.K;
+            q.a_shared = p.a_shared;
+            q.tiles_m = (int)((p.M + BM - 1) / BM);
+            q.tiles_n = (int)((p.N + BN - 1) / BN);
+            q.first_tile = (int)first;
+            first += f16_group_tiles(p);
+        }
     }
-    args.count = count;
-    args.total_tiles = (int)first;
-    hipLaunchKernelGGL(group_reset_kernel, dim3(1), dim3(1), 0, stream, counter);
-    // one operand layout per launch (the API checks it)
-    const bool ab = probs[order[0]].a_layout == TCBF_BLOCKED, cil = c_layout == TCBF_INTERLEAVED;
-    void (*fn)(const GroupArgs, unsigned int *) =
-        ab ? (cil ? cgemm_f16_group_kernel<1, 1> : cgemm_f16_group_kernel<0, 1>)
-           : (cil ? cgemm_f16_group_kernel<1, 0> : cgemm_f16_group_kernel<0, 0>);
-    hipLaunchKernelGGL(fn, dim3((uint32_t)grid), dim3(NT), 0, stream, args, counter);
-    return hipGetLastError();
+    if (n > 0) {
+        args.count = n;
+        args.total_tiles = (int)first;
+        const int grid = (int)std::min<int64_t>(first, 2 * (int64_t)cus);
+        hipLaunchKernelGGL(group_reset_kernel, dim3(1), dim3(1), 0, stream, counter);
+        void (*fn)(const GroupArgs, unsigned int *) =
+            ab ? (cil ? cgemm_f16_group_kernel<1, 1> : cgemm_f16_group_kernel<0, 1>)
+               : (cil ? cgemm_f16_group_kernel<1, 0> : cgemm_f16_group_kernel<0, 0>);
+        hipLaunchKernelGGL(fn, dim3((uint32_t)grid), dim3(NT), 0, stream, args, counter);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (pn > 0) {
+        pargs.count = pn;
+        pargs.total_tiles = (int)pfirst;
+        const int grid = (int)std::min<int64_t>(pfirst, (int64_t)cus);
+        void (*fn)(const PpGroupArgs) = ab ? (cil ? cgemm_f16_pp_group_kernel<1, 1> : cgemm_f16_pp_group_kernel<0, 1>)
+                                           : (cil ? cgemm_f16_pp_group_kernel<1, 0> : cgemm_f16_pp_group_kernel<0, 0>);
+        hipLaunchKernelGGL(fn, dim3((uint32_t)grid), dim3(512), 0, stream, pargs);
+        return hipGetLastError();
+    }
+    return hipSuccess;
 }
 
 }  // namespace tcbf

@@ -33,16 +33,25 @@ bool is_src_type(int32_t t) { return t == TCBF_SRC_I8 || t == TCBF_SRC_F16 || t 
 // Architecture check per device, remembered once it succeeded (plans are
 // created per job in a serving loop; reading the device properties each time
 // would dominate plan creation).
+// A failed HIP call is reported through the returned status; its error is
+// taken off the runtime's last-error slot so that it does not surface later
+// in the caller's own launch checks.
+tcbf_status from_hip(hipError_t e) {
+    if (e == hipSuccess) return TCBF_SUCCESS;
+    (void)hipGetLastError();
+    return TCBF_ERROR_DEVICE;
+}
+
 constexpr int kMaxDevices = 64;
 std::atomic<int> g_device_ok[kMaxDevices];
 
 tcbf_status device_check(int device) {
     int count = 0;
-    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return TCBF_ERROR_DEVICE;
+    if (from_hip(hipGetDeviceCount(&count)) != TCBF_SUCCESS || count <= 0) return TCBF_ERROR_DEVICE;
     if (device < 0 || device >= count) return TCBF_ERROR_INVALID_VALUE;
     if (device < kMaxDevices && g_device_ok[device].load(std::memory_order_acquire) == 1) return TCBF_SUCCESS;
     hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return TCBF_ERROR_DEVICE;
+    if (from_hip(hipGetDeviceProperties(&prop, device)) != TCBF_SUCCESS) return TCBF_ERROR_DEVICE;
     if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return TCBF_ERROR_NOT_SUPPORTED;
     if (device < kMaxDevices) g_device_ok[device].store(1, std::memory_order_release);
     return TCBF_SUCCESS;
@@ -50,7 +59,7 @@ tcbf_status device_check(int device) {
 
 tcbf_status current_device_is(int device) {
     int cur = -1;
-    if (hipGetDevice(&cur) != hipSuccess) return TCBF_ERROR_DEVICE;
+    if (from_hip(hipGetDevice(&cur)) != TCBF_SUCCESS) return TCBF_ERROR_DEVICE;
     return cur == device ? TCBF_SUCCESS : TCBF_ERROR_INVALID_VALUE;
 }
 
@@ -216,7 +225,7 @@ tcbf_status tcbf_execute(tcbf_plan_t plan, const void *A, const void *B, void *C
         e = tcbf::int1_launch(plan->prob, plan->int1, (const uint32_t *)A, (const uint32_t *)B, (int32_t *)C,
                               (hipStream_t)stream);
     }
-    return e == hipSuccess ? TCBF_SUCCESS : TCBF_ERROR_DEVICE;
+    return from_hip(e);
 }
 
 tcbf_status tcbf_block_weights(const void *src, int32_t src_layout, int64_t batch, int64_t M, int64_t K, void *dst,
@@ -228,7 +237,7 @@ tcbf_status tcbf_block_weights(const void *src, int32_t src_layout, int64_t batc
     if ((double)batch * (double)M * (double)(K + 31) >= 0x1p62) return TCBF_ERROR_NOT_SUPPORTED;
     if (tcbf::block_weights_workgroups(batch, M, K) >= kMaxIndex) return TCBF_ERROR_NOT_SUPPORTED;
     hipError_t e = tcbf::block_weights_launch(src, src_layout, batch, M, K, dst, (hipStream_t)stream);
-    return e == hipSuccess ? TCBF_SUCCESS : TCBF_ERROR_DEVICE;
+    return from_hip(e);
 }
 
 tcbf_status tcbf_pack1bit(const void *src, int32_t src_type, int32_t src_layout, int64_t batch, int64_t rows,
@@ -244,7 +253,7 @@ tcbf_status tcbf_pack1bit(const void *src, int32_t src_type, int32_t src_layout,
         return TCBF_ERROR_NOT_SUPPORTED;
     hipError_t e = tcbf::pack1bit_launch(src, src_type, src_layout, batch, rows, K, src_k_major != 0, dst,
                                          (hipStream_t)stream);
-    return e == hipSuccess ? TCBF_SUCCESS : TCBF_ERROR_DEVICE;
+    return from_hip(e);
 }
 
 tcbf_status tcbf_quantize_e4m3(const void *src, int32_t src_type, int32_t src_layout, int64_t batch, int64_t rows,
@@ -260,7 +269,7 @@ tcbf_status tcbf_quantize_e4m3(const void *src, int32_t src_type, int32_t src_la
         return TCBF_ERROR_NOT_SUPPORTED;
     hipError_t e = tcbf::quantize_e4m3_launch(src, src_type, src_layout, batch, rows, K, src_k_major != 0, block,
                                               dst_layout, dst, scales, (hipStream_t)stream);
-    return e == hipSuccess ? TCBF_SUCCESS : TCBF_ERROR_DEVICE;
+    return from_hip(e);
 }
 
 tcbf_status tcbf_steering_weights(const double *positions, const double *directions, const double *frequencies,
@@ -280,7 +289,7 @@ tcbf_status tcbf_steering_weights(const double *positions, const double *directi
     if (tcbf::steering_blocks(batch, M, K, out_layout == TCBF_BLOCKED) >= kMaxIndex) return TCBF_ERROR_NOT_SUPPORTED;
     hipError_t e = tcbf::steering_launch(positions, directions, frequencies, wave_speed, batch, M, K, out_type,
                                          out_layout, W, (hipStream_t)stream);
-    return e == hipSuccess ? TCBF_SUCCESS : TCBF_ERROR_DEVICE;
+    return from_hip(e);
 }
 
 tcbf_status tcbf_peak_probe(int32_t kind, int64_t blocks, int64_t iterations, uint32_t operand_bits,
@@ -293,7 +302,7 @@ tcbf_status tcbf_peak_probe(int32_t kind, int64_t blocks, int64_t iterations, ui
     if (ops != nullptr) *ops = tcbf::peak_probe_ops(kind, blocks, iterations);
     hipError_t e = tcbf::peak_probe_launch(kind, blocks, iterations, operand_bits, operand_mode == TCBF_PROBE_RANDOM,
                                            sink, (hipStream_t)stream);
-    return e == hipSuccess ? TCBF_SUCCESS : TCBF_ERROR_DEVICE;
+    return from_hip(e);
 }
 
 }  // extern "C"
@@ -317,7 +326,8 @@ tcbf_status scratch_of(int device, void **out) {
     std::lock_guard<std::mutex> lock(g_scratch_mutex);
     if (g_scratch_ptr[device] == nullptr) {
         void *ptr = nullptr;
-        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || ptr == nullptr) return TCBF_ERROR_DEVICE;
+        if (from_hip(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch))) != TCBF_SUCCESS || ptr == nullptr)
+            return TCBF_ERROR_DEVICE;
         g_scratch_ptr[device] = ptr;
     }
     *out = g_scratch_ptr[device];
@@ -341,6 +351,7 @@ tcbf_status group_execute(int32_t device, int32_t dtype, int32_t c_layout, const
     const void *SA[TCBF_GROUP_MAX];
     const void *SB[TCBF_GROUP_MAX];
     int order[TCBF_GROUP_MAX];
+    int variants[TCBF_GROUP_MAX];
     int64_t total = 0;
     // one operand layout per launch (it picks the kernel): planar, or blocked
     // fp16 weights / blocked FP8 codes
@@ -354,17 +365,27 @@ tcbf_status group_execute(int32_t device, int32_t dtype, int32_t c_layout, const
         if (g.batch < 1 || g.M < 1 || g.N < 1 || g.K < 1) return TCBF_ERROR_INVALID_VALUE;
         probs[i] = tcbf::Problem{g.batch, g.M, g.N, g.K, layout, (blocked && is_f8(dtype)) ? TCBF_BLOCKED : TCBF_PLANAR,
                                  c_layout, g.a_shared != 0, device};
+        if (g.reserved != 0 || g.variant < 0) return TCBF_ERROR_INVALID_VALUE;
+        variants[i] = 0;
         if (dtype == TCBF_F16) {
             if ((!blocked && g.K % 8 != 0) || g.N % 8 != 0) return TCBF_ERROR_INVALID_VALUE;
             if (g.a_scale != nullptr || g.b_scale != nullptr) return TCBF_ERROR_INVALID_VALUE;
             if (!tcbf::f16_group_problem_ok(probs[i])) return TCBF_ERROR_NOT_SUPPORTED;
+            // the problem's variant: given (a fast variant its plan accepts)
+            // or the plan's default; it picks the grouped launch it joins
+            tcbf::F16Config cfg;
+            if (g.variant == 1 || !tcbf::f16_select(probs[i], g.variant, &cfg) || cfg.variant < 2)
+                return TCBF_ERROR_INVALID_VALUE;
+            variants[i] = cfg.variant;
             total += tcbf::f16_group_tiles(probs[i]);
         } else if (dtype == TCBF_INT1) {
+            if (g.variant != 0) return TCBF_ERROR_INVALID_VALUE;
             if (g.a_scale != nullptr || g.b_scale != nullptr) return TCBF_ERROR_INVALID_VALUE;
             // the plan limits: int32 accumulators, 32-bit output indices
             if (g.K > ((int64_t)1 << 26) || 2 * g.M * g.N >= kMaxIndex) return TCBF_ERROR_NOT_SUPPORTED;
             total += tcbf::int1_group_tiles(probs[i]);
         } else {
+            if (g.variant != 0) return TCBF_ERROR_INVALID_VALUE;
             if (g.N % 4 != 0) return TCBF_ERROR_INVALID_VALUE;
             if (g.a_scale == nullptr || g.b_scale == nullptr) return TCBF_ERROR_INVALID_VALUE;
             if (!aligned16(g.a_scale) || !aligned16(g.b_scale)) return TCBF_ERROR_INVALID_VALUE;
@@ -384,26 +405,27 @@ tcbf_status group_execute(int32_t device, int32_t dtype, int32_t c_layout, const
     }
     // longest tiles (most receivers) first, so the list ends on short tiles
     std::stable_sort(order, order + count, [&](int a, int b) { return probs[a].K > probs[b].K; });
-    tcbf_status st = current_device_is(device);
+    tcbf_status st = device_check(device);
+    if (st == TCBF_SUCCESS) st = current_device_is(device);
     if (st != TCBF_SUCCESS) return st;
     if (use_scratch) {
         st = scratch_of(device, &workspace);
         if (st != TCBF_SUCCESS) return st;
     }
     int cus = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus < 1)
+    if (from_hip(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device)) != TCBF_SUCCESS || cus < 1)
         return TCBF_ERROR_DEVICE;
     const int grid = (int)std::min<int64_t>(total, 2 * (int64_t)cus);
     unsigned int *counter = (unsigned int *)workspace;
     hipError_t e;
     if (dtype == TCBF_F16)
-        e = tcbf::f16_group_launch(probs, A, B, C, order, count, c_layout, grid, counter, (hipStream_t)stream);
+        e = tcbf::f16_group_launch(probs, A, B, C, order, variants, count, c_layout, cus, counter, (hipStream_t)stream);
     else if (dtype == TCBF_INT1)
         e = tcbf::int1_group_launch(probs, A, B, C, order, count, c_layout, grid, counter, (hipStream_t)stream);
     else
         e = tcbf::f8_group_launch(probs, A, B, C, SA, SB, order, count, dtype == TCBF_MXF8_E4M3, c_layout, grid,
                                   counter, (hipStream_t)stream);
-    return e == hipSuccess ? TCBF_SUCCESS : TCBF_ERROR_DEVICE;
+    return from_hip(e);
 }
 
 }  // namespace

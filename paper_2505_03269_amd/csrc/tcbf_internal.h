@@ -33,9 +33,13 @@ hipError_t f16_launch(const Problem &p, const F16Config &cfg, const void *A, con
 // launch; `order` lists the problems in queue order.
 bool f16_group_problem_ok(const Problem &p);
 int64_t f16_group_tiles(const Problem &p);
+// Per-problem fp16 variants: 6, 7 and 9 (256-beam tiles) run in a grouped
+// ping-pong launch, the others in the grouped 128 x 128 launch (the tile
+// counter is used by the latter only); one launch per kind present.
+bool f16_group_pp(int variant);
 hipError_t f16_group_launch(const Problem *probs, const void *const *A, const void *const *B, void *const *C,
-                            const int *order, int count, int c_layout, int grid, unsigned int *counter,
-                            hipStream_t stream);
+                            const int *order, const int *variants, int count, int c_layout, int cus,
+                            unsigned int *counter, hipStream_t stream);
 
 // FP8 modes (e4m3 codes in, fp32 out): per-row fp32 scales or per-32-block
 // E8M0 scales (mx).  Operands are receiver-contiguous with row pitch f8_kp(K).

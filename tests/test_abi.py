@@ -43,7 +43,7 @@ def test_status_strings_and_version():
     assert tcbf.status_string(1) == "TCBF_ERROR_INVALID_VALUE"
     assert tcbf.status_string(4) == "TCBF_ERROR_DEVICE"
     assert tcbf.status_string(99) == "TCBF_UNKNOWN_STATUS"
-    assert tcbf.lib().tcbf_version() == 2
+    assert tcbf.lib().tcbf_version() == 3
 
 
 def _plan_status(**kw):
@@ -214,6 +214,17 @@ def test_group_argument_checks():
         arr = (tcbf.GroupProblem * 1)(tcbf.GroupProblem(**d))
         assert L.tcbf_group_execute(0, tcbf.INT1, 0, arr, 1, p, None) == want, bad
     assert L.tcbf_group_execute(0, tcbf.F16, 0, one, 1, ctypes.c_void_p(addr + 4), None) == 1
+    # per-problem variants: fast variants only (not the generic kernel), blocked
+    # weights only with the variants that read them, 0 for FP8 and 1-bit
+    for bad in (dict(variant=1), dict(variant=10), dict(variant=-1), dict(reserved=1),
+                dict(layout=2, variant=3)):
+        d = dict(A=addr, B=addr, C=addr, batch=1, M=8, N=8, K=8, a_shared=0, layout=0)
+        d.update(bad)
+        arr = (tcbf.GroupProblem * 1)(tcbf.GroupProblem(**d))
+        assert L.tcbf_group_execute(0, tcbf.F16, 0, arr, 1, p, None) == 1, bad
+    d = dict(int1, variant=3)
+    arr = (tcbf.GroupProblem * 1)(tcbf.GroupProblem(**d))
+    assert L.tcbf_group_execute(0, tcbf.INT1, 0, arr, 1, p, None) == 1
     for bad in (dict(K=12), dict(N=4), dict(batch=0), dict(layout=1), dict(layout=3), dict(A=addr + 2),
                 dict(a_scale=addr), dict(layout=2, N=4)):
         d = dict(A=addr, B=addr, C=addr, batch=1, M=8, N=8, K=8, a_shared=0, layout=0)

@@ -339,3 +339,84 @@ def test_group_blocked_graph_replays_match_eager():
         torch.cuda.synchronize()
         for c, e in zip([c for _, _, c in cases], eager):
             assert torch.equal(c, e), "replay %d differs" % r
+
+
+# per-problem variants: 256-beam-tile variants (6, 7, 9) run in the grouped
+# ping-pong launch, the rest in the grouped 128 x 128 launch
+PP_VARIANTS = [9, 2, 9, 6, 5, 7, 9, 8]
+
+
+@pytest.mark.parametrize("layout", [tcbf.PLANAR, tcbf.INTERLEAVED])
+def test_group_per_problem_variants_equal_single_plans(layout):
+    """A mix whose problems name variants of both grouped launches (and a large
+    problem whose default is the ping-pong kernel): every output equals its own
+    plan's bit for bit, whichever launch it ran in."""
+    shapes = MIX + [(64, 1024, 512, 128)]
+    variants = PP_VARIANTS + [0]
+    cases = []
+    for i, (b, M, N, K) in enumerate(shapes):
+        shared = i == 3
+        cases.append((b, M, N, K, shared) + make(140 + i, b, M, N, K, shared, layout))
+    assert tcbf.Plan(64, 1024, 512, 128, tcbf.F16).info()["variant"] == 9
+    log("group with per-problem variants %s, layout %d" % (variants, layout))
+    tcbf.group_execute([(c[7], c[8], c[9], c[4]) for c in cases], c_layout=layout, variants=variants)
+    torch.cuda.synchronize()
+    for v, (b, M, N, K, shared, W, X, Wd, Xd, C) in zip(variants, cases):
+        ref = single(Wd, Xd, b, M, N, K, shared, layout)
+        torch.cuda.synchronize()
+        got = C.cpu().numpy()
+        assert not np.isnan(got).any(), (v, b, M, N, K)
+        assert np.array_equal(got, ref.cpu().numpy()), (v, b, M, N, K)
+    # one of the ping-pong problems against the oracle
+    b, M, N, K, shared, W, X, Wd, Xd, C = cases[0]
+    Ch = C.cpu().numpy().astype(np.float64)
+    got = Ch[:, 0] + 1j * Ch[:, 1] if layout == tcbf.PLANAR else Ch[..., 0] + 1j * Ch[..., 1]
+    Wc, Xc = wl.planar_to_complex(W), wl.planar_to_complex(X)
+    check_fp_full(got, oracle.cgemm(Wc, Xc), np.matmul(np.abs(Wc), np.abs(Xc)), K)
+
+
+def test_group_ping_pong_blocked_and_graph_replays():
+    """Receiver-blocked weights in the grouped ping-pong launch, captured in a
+    graph with a grouped 128 x 128 launch in the same call; replays equal the
+    eager result."""
+    shapes = MIX_BLOCKED[:6]
+    variants = [9, 2, 9, 6, 9, 5]
+    cases = []
+    for i, (b, M, N, K) in enumerate(shapes):
+        W, X, Wd, Xd, C = make(160 + i, b, M, N, K)
+        cases.append((b, M, N, K, tcbf.block_weights(Wd), Xd, C, Wd))
+    ws = torch.zeros(tcbf.GROUP_WORKSPACE_BYTES, dtype=torch.uint8, device="cuda:0")
+    probs = [(c[4], c[5], c[6]) for c in cases]
+    tcbf.group_execute(probs, workspace=ws, layout=tcbf.BLOCKED, variants=variants)
+    torch.cuda.synchronize()
+    for (b, M, N, K, Wb, Xd, C, Wd) in cases:
+        ref = single(Wd, Xd, b, M, N, K)
+        torch.cuda.synchronize()
+        assert torch.equal(C, ref), (b, M, N, K)
+    eager = [c[6].clone() for c in cases]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            tcbf.group_execute(probs, workspace=ws, layout=tcbf.BLOCKED, variants=variants, stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    for r in range(3):
+        for c in cases:
+            c[6].fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for c, e in zip(cases, eager):
+            assert torch.equal(c[6], e), "replay %d differs" % r
+
+
+def test_group_rejects_variants_a_problem_cannot_take():
+    W, X, Wd, Xd, C = make(170, 1, 64, 64, 64)
+    with pytest.raises(ValueError):
+        tcbf.group_execute([(Wd, Xd, C)], variants=[9, 9])
+    with pytest.raises(tcbf.TcbfError):
+        tcbf.group_execute([(Wd, Xd, C)], variants=[1])            # the generic kernel is not grouped
+    with pytest.raises(tcbf.TcbfError):
+        tcbf.group_execute([(tcbf.block_weights(Wd), Xd, C)], layout=tcbf.BLOCKED, variants=[3])

@@ -95,3 +95,10 @@ def test_noalloc_rejects_bad_arguments():
     assert L.tcbf_group_execute_noalloc(0, tcbf.F16, 5, arr, 1, None) == 1            # unknown output layout
     assert L.tcbf_group_execute_noalloc(0, tcbf.F16, 0, arr, 0, None) == 1            # no problems
     assert L.tcbf_group_execute_noalloc(1, tcbf.F16, 0, arr, 1, None) != 0            # not the current device
+    ws = torch.empty(tcbf.GROUP_WORKSPACE_BYTES, dtype=torch.uint8, device="cuda:0")
+    assert L.tcbf_group_execute(1, tcbf.F16, 0, arr, 1, ws.data_ptr(), None) != 0    # not the current device
+    # a rejected call leaves no HIP error behind for the caller's next launch
+    # check (torch checks the runtime's last error after each of its kernels)
+    t = torch.rand(64, device="cuda:0") + 1.0
+    torch.cuda.synchronize()
+    assert float(t.min()) >= 1.0
