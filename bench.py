@@ -535,6 +535,7 @@ def bench_secondary(steps, samples, serving=True, copy_gbs=None, valu_peak=None)
     copies of sampled GPU outputs for the CPU legs' accuracy checks."""
     import torch
     import paper_2505_03269_amd as tcbf
+    from paper_2505_03269_amd import tune
     import workloads as wl
     out = []
     st = max(3, steps // 4)
@@ -627,7 +628,17 @@ def bench_secondary(steps, samples, serving=True, copy_gbs=None, valu_peak=None)
     C = plan.empty_output()
     # sub-millisecond launches: time enough of them to average out clock swings
     st4 = max(st, 20)
-    ms, ms_p = time_interleaved([lambda: plan.execute(Ab, B, C), lambda: plan_p.execute(A, B, C)], st4, 3)
+    # the autotuner's choice for this shape (blocked weights), timed beside
+    # the library's default plan
+    ent = tune.tune(1, cfg["M"], cfg["N"], cfg["K"], tcbf.F16, operand_layout=tcbf.BLOCKED, reps=10, warmup=3)
+    v_def = info["variant"]
+    plan_t = tcbf.Plan(1, cfg["M"], cfg["N"], cfg["K"], tcbf.F16, a_layout=tcbf.BLOCKED, variant=ent["variant"])
+    if ent["variant"] == v_def:
+        ms, ms_p = time_interleaved([lambda: plan.execute(Ab, B, C), lambda: plan_p.execute(A, B, C)], st4, 3)
+        ms_t = ms
+    else:
+        ms, ms_p, ms_t = time_interleaved([lambda: plan.execute(Ab, B, C), lambda: plan_p.execute(A, B, C),
+                                           lambda: plan_t.execute(Ab, B, C)], st4, 3)
     # sampled beams for the CPU leg (seeded, plus the first and the last)
     beams = np.unique(np.concatenate([[0, cfg["M"] - 1], np.random.default_rng(11).choice(cfg["M"], 62, replace=False)]))
     beams_d = torch.from_numpy(beams).to("cuda:0")
@@ -638,8 +649,11 @@ def bench_secondary(steps, samples, serving=True, copy_gbs=None, valu_peak=None)
     tops = info["useful_ops"] / (ms * 1e-3) / 1e12
     out.append({"workload": "ultrasound-fp16: batch=1 M=32768 K=8192 N=256", "kernel": info["kernel_name"],
                 "value": round(tops, 1), "unit": "TeraOps/s", "ms_per_launch": round(ms, 4), "dtype": "f16",
-                "layout": "W receiver-blocked (repacked once), X planar",
+                "layout": "W receiver-blocked (repacked once), X planar", "variant": v_def,
                 "weights_planar_tops": round(info["useful_ops"] / (ms_p * 1e-3) / 1e12, 1),
+                "tuned": {"variant": ent["variant"], "tops": round(info["useful_ops"] / (ms_t * 1e-3) / 1e12, 1),
+                          "ms_per_launch": round(ms_t, 4), "kernel": plan_t.info()["kernel_name"],
+                          "tuner_ms": ent["ms"]},
                 "roofline": {"bound": "mfma", "achieved": round(tops, 1), "peak": PEAK_F16_TFLOPS,
                              "unit": "TFLOP/s", "frac": round(tops / PEAK_F16_TFLOPS, 4)}})
     samples["c4"]["lines"]["f16"] = len(out) - 1
@@ -705,13 +719,41 @@ def bench_secondary(steps, samples, serving=True, copy_gbs=None, valu_peak=None)
         # the same launch with receiver-blocked weights (repacked once)
         probs_b = [(tcbf.block_weights(Wg), Xg, Cg) for (Wg, Xg, Cg) in probs]
         ms_gb = time_launches(lambda: tcbf.group_execute(probs_b, workspace=ws, layout=tcbf.BLOCKED), st, 1)
+        # per-problem variants chosen by the autotuner timing the grouped
+        # launch itself (candidate lists: defaults, each problem's own tuned
+        # plan, ping-pong tiles, 128 x 128 tiles), against the library's
+        # default variants, both weight layouts
+        full = [(1, M, N, K) for (M, N, K) in shapes]
+        ent = tune.tune_group(full, lambda v: time_launches(
+            lambda: tcbf.group_execute(probs, workspace=ws, variants=v), st, 1), reps=5, warmup=2)
+        entb = tune.tune_group(full, lambda v: time_launches(
+            lambda: tcbf.group_execute(probs_b, workspace=ws, layout=tcbf.BLOCKED, variants=v), st, 1),
+            operand_layout=tcbf.BLOCKED, reps=5, warmup=2)
+        tv, tvb = ent["variants"], entb["variants"]
+        ms_d, ms_t, ms_db, ms_tb = time_interleaved(
+            [lambda: tcbf.group_execute(probs, workspace=ws),
+             lambda: tcbf.group_execute(probs, workspace=ws, variants=tv),
+             lambda: tcbf.group_execute(probs_b, workspace=ws, layout=tcbf.BLOCKED),
+             lambda: tcbf.group_execute(probs_b, workspace=ws, layout=tcbf.BLOCKED, variants=tvb)], st, 1)
+        dflt = [tcbf.Plan(1, M, N, K, tcbf.F16).info()["variant"] for (M, N, K) in shapes]
+        dflt_b = [tcbf.Plan(1, M, N, K, tcbf.F16, a_layout=tcbf.BLOCKED).info()["variant"] for (M, N, K) in shapes]
         del probs_b
         tops = ops / (ms_g * 1e-3) / 1e12
-        out.append({"workload": "grouped fp16: " + label, "kernel": "cgemm_f16_group_kernel", "value": round(tops, 1),
+        out.append({"workload": "grouped fp16: " + label,
+                    "kernel": "cgemm_f16_group_kernel + cgemm_f16_pp_group_kernel", "value": round(tops, 1),
                     "unit": "TeraOps/s", "ms_per_launch": round(ms_g, 4),
                     "blocked_weights_tops": round(ops / (ms_gb * 1e-3) / 1e12, 1),
                     "separate_launches_tops": round(ops / (ms_s * 1e-3) / 1e12, 1),
                     "separate_launches_ms": round(ms_s, 4), "dtype": "f16",
+                    "tuned": {"planar": {"default_tops": round(ops / (ms_d * 1e-3) / 1e12, 1),
+                                         "tuned_tops": round(ops / (ms_t * 1e-3) / 1e12, 1),
+                                         "policy": ent["policy"], "tuner_ms": ent["ms"],
+                                         "default_variants": dflt, "tuned_variants": tv},
+                              "blocked": {"default_tops": round(ops / (ms_db * 1e-3) / 1e12, 1),
+                                          "tuned_tops": round(ops / (ms_tb * 1e-3) / 1e12, 1),
+                                          "policy": entb["policy"], "tuner_ms": entb["ms"],
+                                          "default_variants": dflt_b, "tuned_variants": tvb},
+                              "note": "default and tuned timed in alternating rounds after tuning"},
                     "roofline": {"bound": "mfma", "achieved": round(tops, 1), "peak": PEAK_F16_TFLOPS,
                                  "unit": "TFLOP/s", "frac": round(tops / PEAK_F16_TFLOPS, 4)}})
         del probs, plans
@@ -789,15 +831,32 @@ def bench_serving(warmup=1000, measured=10000):
         overlap[load] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in srv.device_overlap().items()}
     r = runs[0.8]
     rnd = lambda d: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()}  # noqa: E731
+    # the same server with the autotuner's per-weight-set fp16 variants:
+    # closed-loop capacity and the 80% run at the default runs' arrival rate
+    t0 = time.perf_counter()
+    srv.tune_weights()
+    tune_s = time.perf_counter() - t0
+    srv.run(srv.make_jobs(warmup // 4, None, seed=101))
+    closed_t = srv.run(srv.make_jobs(measured, None, seed=200))
+    open_t = srv.run(srv.make_jobs(measured, 0.8 * cap, seed=308))
+    srv.use_tuned = False
+    variants = sorted(set(srv.f16_variants.values()))
     return {"workload": "served mixed stream: fp16/fp8/1-bit jobs, 16 resident weight sets per dtype, "
                         "M~U[128,4096] K~U[64,2048] N~U[256,8192], Poisson arrivals at 80% of capacity",
-            "kernel": "cgemm_f16_group_kernel + cgemm_f8_group_kernel + cgemm_1bit_group_kernel",
+            "kernel": "cgemm_f16_group_kernel + cgemm_f16_pp_group_kernel + cgemm_f8_group_kernel + "
+                      "cgemm_1bit_group_kernel",
             "value": round(r["tops"], 1), "unit": "TeraOps/s", "p50_ms": round(r["p50_ms"], 3),
             "p99_ms": round(r["p99_ms"], 3), "capacity_jobs_per_s": round(cap, 1),
             "closed_loop": rnd(closed), "load_0.8": rnd(runs[0.8]), "load_0.5": rnd(runs[0.5]),
             "device_overlap_0.8": overlap[0.8], "device_overlap_0.5": overlap[0.5],
             "device_overlap_note": "batches on different streams in progress at the same device time "
                                    "(timing events around each batch on its own stream)",
+            "tuned": {"closed_loop_tops": round(closed_t["tops"], 1),
+                      "capacity_jobs_per_s": round(measured / closed_t["makespan_s"], 1),
+                      "load_0.8_tops": round(open_t["tops"], 1), "load_0.8_p50_ms": round(open_t["p50_ms"], 3),
+                      "load_0.8_p99_ms": round(open_t["p99_ms"], 3), "variants_used": variants,
+                      "tuning_s": round(tune_s, 2),
+                      "note": "fp16 variants tuned per weight set at N in {256..8192}; same job streams"},
             "completed": r["completed"], "rejected": r["rejected"], "failed": r["failed"],
             "warmup_jobs": warmup, "measured_jobs": measured, "streams": len(srv.streams),
             "budget_bytes": srv.budget}
@@ -815,6 +874,7 @@ def sweep(steps):
                ("roofline-int1-small", tcbf.INT1, 256, 1024, 1024, 256)]
     g = torch.Generator(device="cuda:0")
     g.manual_seed(11)
+    copy_gbs = measure_copy()["gbs"]
     for name, dt, batch, M, N, K in shapes:
         # fp16: receiver-blocked weights (repacked once), planar timed beside
         lay = tcbf.BLOCKED if dt == tcbf.F16 else tcbf.PLANAR
@@ -837,6 +897,21 @@ def sweep(steps):
             ms, ms_p = time_interleaved([lambda: plan.execute(A, B, C), lambda: plan_p.execute(Ap, B, C)],
                                         steps, 2)
             del Ap
+            # the same launches over rotating copies of the inputs (at least
+            # 1.2 GB in all), so that no launch finds its inputs still in the
+            # 256 MB last-level cache from the launch before
+            in_bytes = (A.numel() + B.numel()) * 2
+            sets = int(min(16, max(2, -(-1.2e9 // in_bytes))))
+            As = [A] + [A.clone() for _ in range(sets - 1)]
+            Bs = [B] + [B.clone() for _ in range(sets - 1)]
+            rot = [0]
+
+            def cold():
+                i = rot[0] % sets
+                rot[0] += 1
+                plan.execute(As[i], Bs[i], C)
+            ms_c = time_launches(cold, max(steps, 2 * sets), sets)
+            del As, Bs
         tops = info["useful_ops"] / (ms * 1e-3) / 1e12
         gbs = info["algorithmic_bytes"] / (ms * 1e-3) / 1e9
         ai = info["useful_ops"] / info["algorithmic_bytes"]
@@ -848,7 +923,15 @@ def sweep(steps):
                "tops": round(tops, 1), "gbs_algorithmic": round(gbs, 1), "ops_per_byte": round(ai, 1),
                "bound": bound, "frac_of_bound": round(frac, 4)}
         if ms_p is not None:
-            rec.update({"weights": "blocked", "planar_weights_tops": round(info["useful_ops"] / (ms_p * 1e-3) / 1e12, 1)})
+            gbs_c = info["algorithmic_bytes"] / (ms_c * 1e-3) / 1e9
+            rec.update({"weights": "blocked", "planar_weights_tops": round(info["useful_ops"] / (ms_p * 1e-3) / 1e12, 1),
+                        "input_mb": round(in_bytes / 1e6, 1),
+                        "cold_inputs": {"ms": round(ms_c, 4), "tops": round(info["useful_ops"] / (ms_c * 1e-3) / 1e12, 1),
+                                        "gbs_algorithmic": round(gbs_c, 1), "input_sets": sets,
+                                        "frac_of_measured_copy_rate": round(gbs_c / copy_gbs, 4)},
+                        "measured_copy_gbs": copy_gbs,
+                        "roofline_ms": round(max(info["algorithmic_bytes"] / (PEAK_HBM_GBS * 1e6),
+                                                 info["useful_ops"] / (peak * 1e9)), 4)})
         print(json.dumps(rec), flush=True)
         del A, B, C
         torch.cuda.empty_cache()

@@ -10,7 +10,9 @@ A job asks for B = W . X with one of the resident weight sets (fp16, FP8 or
     the slot count allow (a job's budget is its input and output buffers);
   * launches the admitted jobs as soon as a stream is free: the jobs of a
     batch go into one grouped persistent launch per dtype
-    (tcbf_group_execute), on that stream;
+    (tcbf_group_execute), on that stream, each fp16 job with the kernel
+    variant the autotuner chose for its weight set and sample count once
+    tune_weights() has run (else the library's default for its shape);
   * runs several streams, so a batch formed while others are still on the
     GPU overlaps with them, and frees a job's memory and slot when the host
     sees its batch complete (an event query, no blocking wait);
@@ -158,6 +160,10 @@ class Server:
         self.max_slots = max_slots
         self.plans = {}
         self.batch_log = []
+        # fp16 kernel variants chosen by the autotuner per (weight set, N
+        # bucket); used while use_tuned is set (see tune_weights)
+        self.f16_variants = {}
+        self.use_tuned = False
 
     # -- jobs ---------------------------------------------------------------
     def make_jobs(self, count, rate, seed=1):
@@ -187,15 +193,43 @@ class Server:
             b += 8 * N * (-(-K // 32))
         return b
 
-    def _plan(self, dtype, M, N, K):
-        key = (dtype, M, N, K)
+    def _plan(self, dtype, M, N, K, variant=0):
+        key = (dtype, M, N, K, variant)
         p = self.plans.get(key)
         if p is None:
             lay = PLANAR if dtype == INT1 else BLOCKED   # the resident weights' layout
             p = Plan(1, M, N, K, dtype, a_layout=lay, b_layout=BLOCKED if dtype == F8_E4M3 else PLANAR,
-                     device=self.dev_index)
+                     variant=variant, device=self.dev_index)
             self.plans[key] = p
         return p
+
+    # -- autotuned tile choice ------------------------------------------------
+    N_BUCKETS = (256, 512, 1024, 2048, 4096, 8192)
+
+    def tune_weights(self, cache_path=None, reps=5, warmup=2):
+        """Run the autotuner for every resident fp16 weight set at each
+        representative sample count of N_BUCKETS (receiver-blocked weights,
+        the form kept resident) and use its choices from now on: a job's
+        problem joins the grouped launch with the variant tuned for its
+        weight set at the bucket nearest its N (log scale).  Choices are
+        cached per exact shape under cache_path (no file: this process only)."""
+        from . import tune
+        for (d, wid), ws in self.pool.items():
+            if d != F16:
+                continue
+            for n in self.N_BUCKETS:
+                entry = tune.tune(1, ws.M, n, ws.K, F16, cache_path=cache_path, device=self.dev_index,
+                                  operand_layout=BLOCKED, reps=reps, warmup=warmup)
+                self.f16_variants[(wid, n)] = tune.group_variant(entry)
+        self.use_tuned = True
+
+    def f16_variant(self, job):
+        """The kernel variant of an fp16 job: 0 (the library's default for
+        its shape) unless tuned choices are in use."""
+        if not self.use_tuned:
+            return 0
+        n = min(self.N_BUCKETS, key=lambda b: abs(np.log2(b) - np.log2(max(job.N, 1))))
+        return self.f16_variants.get((job.wid, n), 0)
 
     def validate(self, job):
         """Why `job` can never run here, or None."""
@@ -262,7 +296,7 @@ class Server:
         X = job_input(job, self.data)
         out = torch.empty((1, 2, job.M, job.N), dtype=out_dtype(job.dtype), device=self.device)
         if job.dtype == F16:
-            self._plan(F16, job.M, job.N, job.K).execute(ws.A, X, out)
+            self._plan(F16, job.M, job.N, job.K, self.f16_variant(job)).execute(ws.A, X, out)
         elif job.dtype == F8_E4M3:
             Xq, xs = quantize_e4m3(X, k_major=False, block=0, out_layout=BLOCKED)
             self._plan(F8_E4M3, job.M, job.N, job.K).execute(ws.A, Xq, out, ws.scale, xs)
@@ -288,7 +322,7 @@ class GpuExecutor:
         with torch.cuda.stream(s):
             start = torch.cuda.Event(enable_timing=True)
             start.record(s)
-            f16, f8, i1 = [], [], []
+            f16, f8, i1, f16v = [], [], [], []
             for job in batch:
                 ws = srv.pool[(job.dtype, job.wid)]
                 X = job_input(job, srv.data)
@@ -296,6 +330,7 @@ class GpuExecutor:
                 if job.dtype == F16:
                     job.X = X
                     f16.append((ws.A, X, job.out))
+                    f16v.append(srv.f16_variant(job))
                 elif job.dtype == F8_E4M3:
                     job.X, job.xs = quantize_e4m3(X, k_major=False, block=0, out_layout=BLOCKED)
                     f8.append((ws.A, job.X, job.out, ws.scale, job.xs, job.K))
@@ -307,7 +342,8 @@ class GpuExecutor:
             for dt, probs in ((F16, f16), (F8_E4M3, f8), (INT1, i1)):
                 for i in range(0, len(probs), GROUP_MAX):
                     group_execute(probs[i:i + GROUP_MAX], workspace=srv.workspaces[si], device=srv.dev_index,
-                                  dtype=dt, layout=PLANAR if dt == INT1 else BLOCKED)
+                                  dtype=dt, layout=PLANAR if dt == INT1 else BLOCKED,
+                                  variants=f16v[i:i + GROUP_MAX] if dt == F16 else None)
             ev = torch.cuda.Event(enable_timing=True)
             ev.record(s)
         srv.batch_log.append((si, start, ev))

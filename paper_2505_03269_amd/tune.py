@@ -185,3 +185,101 @@ def tuned_plan(batch, M, N, K, dtype=F16, c_layout=PLANAR, a_shared=False, cache
     al, bl = _layouts(dtype, operand_layout)
     return Plan(batch, M, N, K, dtype, a_layout=al, b_layout=bl, c_layout=c_layout, a_shared=a_shared,
                 variant=entry["variant"], device=device)
+
+
+def group_variant(entry):
+    """The variant a grouped launch runs for a problem whose single-plan
+    tuning gave `entry`: the tuned variant, or, where that is the generic
+    kernel (which has no grouped form), the fastest variant that has one."""
+    if entry["variant"] != 1:
+        return entry["variant"]
+    rest = [(ms, int(v)) for v, ms in entry["ms"].items() if int(v) != 1]
+    if not rest:
+        raise TcbfError(2, "no grouped kernel accepts this problem")
+    return min(rest)[1]
+
+
+def group_variants(shapes, dtype=F16, c_layout=PLANAR, operand_layout=PLANAR, cache_path=None, device=0, **kw):
+    """Per-problem variants for a grouped launch of problems with the given
+    (batch, M, N, K[, a_shared]) shapes: each fp16 problem takes the variant
+    its own tuned plan runs (cached per shape, see tune()); FP8 and 1-bit
+    problems take 0 (their grouped kernels have one tile shape)."""
+    out = []
+    memo = {}
+    for s in shapes:
+        batch, M, N, K = s[:4]
+        a_shared = bool(s[4]) if len(s) > 4 else False
+        if dtype != F16:
+            out.append(0)
+            continue
+        key = (batch, M, N, K, a_shared)
+        if key not in memo:
+            memo[key] = group_variant(tune(batch, M, N, K, dtype, c_layout, a_shared, cache_path=cache_path,
+                                           device=device, operand_layout=operand_layout, **kw))
+        out.append(memo[key])
+    return out
+
+
+def group_cache_key(arch, dtype, shapes, c_layout=PLANAR, operand_layout=PLANAR, kernel_set=None):
+    """Key of a grouped launch's tuned variants: the problems' shapes in
+    order (a problem's position picks its entry in the variant list)."""
+    sig = ",".join("%dx%dx%dx%d%s" % (s[0], s[1], s[2], s[3], "s" if len(s) > 4 and s[4] else "") for s in shapes)
+    return "%s|dtype%d|group[%s]|c%d|op%d|ks%s" % (arch, int(dtype), sig, int(c_layout), int(operand_layout),
+                                                kernel_set if kernel_set is not None else kernel_set_id())
+
+
+def _accepts(s, variant, dtype, c_layout, operand_layout, device):
+    al, bl = _layouts(dtype, operand_layout)
+    try:
+        Plan(s[0], s[1], s[2], s[3], dtype, a_layout=al, b_layout=bl, c_layout=c_layout,
+             a_shared=bool(s[4]) if len(s) > 4 else False, variant=variant, device=device)
+    except TcbfError:
+        return False
+    return True
+
+
+def group_policies(shapes, dtype=F16, c_layout=PLANAR, operand_layout=PLANAR, device=0, cache_path=None, **kw):
+    """Candidate per-problem variant lists for a grouped fp16 launch:
+    "default" (every problem's default plan), "per_problem" (each problem's
+    own tuned plan, see group_variants), "ping_pong" (the 256 x 128
+    persistent tile wherever a problem takes it, else variant 2) and
+    "small_tiles" (the 128 x 128 tile, variant 2, for every problem)."""
+    pp = [9 if _accepts(s, 9, dtype, c_layout, operand_layout, device) else 2 for s in shapes]
+    return {"default": [0] * len(shapes),
+            "per_problem": group_variants(shapes, dtype, c_layout, operand_layout, cache_path, device, **kw),
+            "ping_pong": pp,
+            "small_tiles": [2] * len(shapes)}
+
+
+def tune_group(shapes, measure_fn, dtype=F16, c_layout=PLANAR, operand_layout=PLANAR, cache_path=None, device=0,
+               arch=None, force=False, **kw):
+    """Choose the per-problem variants of a grouped fp16 launch by timing the
+    launch itself: every candidate list of group_policies() is timed with
+    measure_fn(variants) -> ms (the caller's grouped launch on its own
+    buffers) and the fastest is kept, cached under the group's shapes.
+    Returns {"variants": [...], "policy": name, "ms": {name: ms}}.  FP8 and
+    1-bit groups have one tile shape: every variant is 0."""
+    if dtype != F16:
+        return {"variants": [0] * len(shapes), "policy": "default", "ms": {}}
+    if arch is None:
+        import torch
+        arch = torch.cuda.get_device_properties(device).gcnArchName.split(":")[0]
+    key = group_cache_key(arch, dtype, shapes, c_layout, operand_layout)
+    cache = load_cache(cache_path)
+    if key in cache and not force:
+        return cache[key]
+    cands = group_policies(shapes, dtype, c_layout, operand_layout, device, cache_path, **kw)
+    timings, seen = {}, {}
+    for name, variants in cands.items():
+        t = tuple(variants)
+        if t in seen:   # the same lists under two names: timed once
+            timings[name] = timings[seen[t]]
+            continue
+        seen[t] = name
+        timings[name] = round(float(measure_fn(list(variants))), 5)
+    best = min(cands, key=lambda n: timings[n])
+    entry = {"variants": list(cands[best]), "policy": best, "ms": timings}
+    cache = load_cache(cache_path)
+    cache[key] = entry
+    save_cache(cache_path, cache)
+    return entry

@@ -119,3 +119,28 @@ def test_rejected_and_cancelled_jobs_leave_the_rest_intact(server):
     for job in jobs:
         if job.status == serve.DONE:
             assert torch.equal(job.out, server.run_alone(job))
+
+
+def test_tuned_variants_are_served():
+    """With the autotuner's per-weight-set variants in use, every fp16 job
+    runs in the grouped launch with the variant tuned for its weight set and
+    sample count, equals its own plan with that variant bitwise, and one is
+    checked against the oracle."""
+    srv = serve.Server(pool_per_dtype=3, dtypes=(tcbf.F16,), budget_bytes=1 << 33, streams=2, seed=21)
+    srv.tune_weights(reps=2, warmup=1)
+    assert set(srv.f16_variants) == {(w, n) for w in range(3) for n in serve.Server.N_BUCKETS}
+    assert all(v >= 2 for v in srv.f16_variants.values())
+    log("tuned variants %s" % sorted(srv.f16_variants.items()))
+    jobs = srv.make_jobs(16, rate=None, seed=22)
+    summary = srv.run(jobs, keep_outputs=True)
+    assert summary["completed"] == 16
+    for job in jobs:
+        assert srv.f16_variant(job) == srv.f16_variants[(job.wid, min(serve.Server.N_BUCKETS, key=lambda b: abs(
+            np.log2(b) - np.log2(job.N))))]
+        assert torch.equal(job.out, srv.run_alone(job)), "job %d" % job.jid
+    job = jobs[0]
+    W = srv.pool[(job.dtype, job.wid)].source().cpu().numpy().astype(np.float64)
+    X = serve.job_input(job, srv.data).cpu().numpy().astype(np.float64)
+    Wc, Xc = W[:, 0] + 1j * W[:, 1], X[:, 0] + 1j * X[:, 1]
+    got = job.out.cpu().numpy()
+    check_fp_full(got[:, 0] + 1j * got[:, 1], oracle.cgemm(Wc, Xc), np.matmul(np.abs(Wc), np.abs(Xc)), job.K)

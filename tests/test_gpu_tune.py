@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 import workloads as wl
-from gpu_util import to_dev
+from gpu_util import log, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -56,3 +56,44 @@ def test_tune_blocked_operands(tmp_path, dtype):
     plan = tune.tuned_plan(2, 256, 256, 192, dtype, cache_path=path, operand_layout=tcbf.BLOCKED)
     assert plan.a_layout == tcbf.BLOCKED and plan.info()["variant"] == e["variant"]
     assert len(tune.load_cache(path)) == 1
+
+
+def test_tune_group_output_equals_each_tuned_plan(tmp_path):
+    """The grouped launch with the variants tune_group chose (by timing the
+    launch itself) gives every problem the output of its own plan with that
+    variant, bit for bit; the choice is cached under the group's shapes."""
+    shapes = [(1, 300, 264, 576), (2, 128, 128, 64), (8, 1024, 512, 128), (3, 200, 392, 200),
+              (1, 2048, 1024, 256)]
+    cases = []
+    for i, (b, M, N, K) in enumerate(shapes):
+        W, X = wl.random_f16_case(300 + i, b, M, N, K)
+        cases.append((to_dev(W), to_dev(X), torch.empty((b, 2, M, N), device="cuda:0")))
+    ws = torch.zeros(tcbf.GROUP_WORKSPACE_BYTES, dtype=torch.uint8, device="cuda:0")
+
+    def measure(v):
+        for _ in range(2):
+            tcbf.group_execute(cases, workspace=ws, variants=v)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            tcbf.group_execute(cases, workspace=ws, variants=v)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 5
+    path = str(tmp_path / "g.json")
+    ent = tune.tune_group(shapes, measure, cache_path=path, reps=2, warmup=1)
+    log("group tuning: %s" % ent)
+    assert set(ent["ms"]) == {"default", "per_problem", "ping_pong", "small_tiles"}
+    assert ent["ms"][ent["policy"]] == min(ent["ms"].values())
+    assert tune.tune_group(shapes, lambda v: 1 / 0, cache_path=path) == ent
+    for (_, _, C) in cases:
+        C.fill_(float("nan"))
+    tcbf.group_execute(cases, workspace=ws, variants=ent["variants"])
+    torch.cuda.synchronize()
+    for v, (b, M, N, K), (Wd, Xd, C) in zip(ent["variants"], shapes, cases):
+        plan = tcbf.Plan(b, M, N, K, tcbf.F16, variant=v)
+        ref = plan.empty_output()
+        plan.execute(Wd, Xd, ref)
+        torch.cuda.synchronize()
+        assert torch.equal(C, ref), (v, b, M, N, K)
