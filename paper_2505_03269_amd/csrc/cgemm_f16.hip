@@ -1072,8 +1072,25 @@ __global__ __launch_bounds__(512, 1) void cgemm_f16_pp_kernel(const uint16_t *__
     __shared__ __attribute__((aligned(1024))) char lds2[G::STAGE];
 
     const int grid = (int)gridDim.x;
-    const int pos = (int)xcd_remap(blockIdx.x, grid);
-    const int ntiles = (total_tiles - pos + grid - 1) / grid;  // >= 1: grid <= total_tiles
+    // Tile order.  With a grid that is a multiple of the 8 XCDs (workgroup b
+    // runs on XCD b mod 8), each XCD takes a contiguous eighth of the tile
+    // sequence and its workgroups step through it together, so the tiles in
+    // flight on one XCD (one L2) are neighbours: a channel's weights stay in
+    // that L2 while all its tiles pass.  Otherwise workgroup b takes tiles b,
+    // b + grid, ...  Workgroup tiles: first, first + stride, ... (ntiles).
+    int first, stride, ntiles;
+    if (grid % 8 == 0) {
+        const int xcd = (int)blockIdx.x % 8, j = (int)blockIdx.x / 8, per = grid / 8;
+        const int q = total_tiles / 8, rem = total_tiles % 8;
+        const int count = q + (xcd < rem ? 1 : 0);  // >= per: grid <= total_tiles
+        first = xcd * q + min(xcd, rem) + j;
+        stride = per;
+        ntiles = (count - j + per - 1) / per;
+    } else {
+        first = (int)blockIdx.x;
+        stride = grid;
+        ntiles = (total_tiles - first + grid - 1) / grid;  // >= 1: grid <= total_tiles
+    }
     const int nk = (K + 31) / 32;
     const int S = ntiles * nk;  // stages this workgroup runs
     const int per_c = tiles_m * tiles_n;
@@ -1147,7 +1164,7 @@ __global__ __launch_bounds__(512, 1) void cgemm_f16_pp_kernel(const uint16_t *__
     const uint32_t neg_even = (lane & 1) ? 0u : 0x80008000u;  // sign flip of both halves in even lanes
 
     auto tile_of = [&](int round, int &c, int &m0, int &n0) __attribute__((always_inline)) {
-        const int t = round * grid + pos;
+        const int t = first + round * stride;
         c = t / per_c;
         int tm, tn;
         tile_coords(t - c * per_c, tiles_m, tiles_n, tm, tn);
