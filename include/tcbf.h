@@ -37,7 +37,7 @@
 extern "C" {
 #endif
 
-#define TCBF_VERSION 3
+#define TCBF_VERSION 4
 
 typedef enum tcbf_status {
     TCBF_SUCCESS = 0,
@@ -92,6 +92,9 @@ typedef enum tcbf_src_type {
  *                       identical to the planar layout's.
  *   B = X   planar      [batch][2][K][N]   N contiguous
  *           interleaved [batch][K][N][2]
+ *           with b_k_contiguous: planar [batch][2][N][K], interleaved
+ *           [batch][N][K][2] (receivers contiguous for each sample, as
+ *           sensor data often arrives); variant 1 only
  *   C = out planar      [batch][2][M][N]   fp32
  *           interleaved [batch][M][N][2]   fp32
  *
@@ -127,6 +130,13 @@ typedef enum tcbf_src_type {
  *                     never uses
  *
  * a_shared != 0: W holds a single batch entry that every channel uses.
+ * a_batch_stride > 0: batch entry c's W starts a_batch_stride elements of
+ * W's storage type (fp16 values, e4m3 code bytes, packed uint32 words) after
+ * entry c-1's; at least one entry's size in the layout above, and a multiple
+ * of 16 bytes; 0 means entries packed back to back (or the single shared
+ * entry).  FP8 scales stay per entry ([batch][M] or blocked groups) unless
+ * a_shared.  The FP8 and 1-bit X operands are always receiver-contiguous
+ * (codes or packed words); b_k_contiguous may be 0 or 1 for them.
  * C is always overwritten (the output starts from zero, as in Sec. III-B).
  */
 typedef struct tcbf_plan_desc {
@@ -142,6 +152,11 @@ typedef struct tcbf_plan_desc {
     int32_t c_layout;     /* tcbf_layout of the output                         */
     int32_t a_shared;     /* nonzero: one W for all batch entries              */
     int32_t variant;      /* 0 = automatic kernel choice; >0 forces a variant  */
+    /* Fields below are read when struct_size covers them (TCBF_VERSION >= 4);
+     * a shorter descriptor means b_k_contiguous = 0, a_batch_stride = 0. */
+    int32_t b_k_contiguous; /* nonzero: fp16 X receiver-contiguous (see above) */
+    int32_t reserved;       /* must be 0                                       */
+    int64_t a_batch_stride; /* W elements between batch entries; 0 = packed    */
 } tcbf_plan_desc;
 /* Variants.  TCBF_F16: 1 register-staged kernel for any layout and alignment;
  * 2..9 the direct-to-LDS kernels (planar or blocked W, planar X, N a

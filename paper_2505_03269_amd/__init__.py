@@ -52,7 +52,9 @@ class PlanDesc(ctypes.Structure):
                 ("batch", ctypes.c_int64), ("M", ctypes.c_int64), ("N", ctypes.c_int64),
                 ("K", ctypes.c_int64), ("dtype", ctypes.c_int32), ("a_layout", ctypes.c_int32),
                 ("b_layout", ctypes.c_int32), ("c_layout", ctypes.c_int32),
-                ("a_shared", ctypes.c_int32), ("variant", ctypes.c_int32)]
+                ("a_shared", ctypes.c_int32), ("variant", ctypes.c_int32),
+                ("b_k_contiguous", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("a_batch_stride", ctypes.c_int64)]
 
 
 class GroupProblem(ctypes.Structure):
@@ -172,13 +174,19 @@ def _stream_handle(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def _dev_ptr(t, name):
+def _dev_ptr(t, name, batch_stride=0):
+    """Device pointer of a contiguous tensor; with batch_stride > 0, of a
+    tensor whose entries along dim 0 are contiguous and batch_stride
+    elements apart (a view into a larger buffer)."""
     import torch
     if not isinstance(t, torch.Tensor):
         raise TypeError("%s must be a torch tensor" % name)
     if not t.is_cuda:
         raise ValueError("%s must be a device tensor" % name)
-    if not t.is_contiguous():
+    if batch_stride:
+        if t.dim() < 2 or not t[0].is_contiguous() or (t.shape[0] > 1 and t.stride(0) != batch_stride):
+            raise ValueError("%s must have contiguous entries %d elements apart" % (name, batch_stride))
+    elif not t.is_contiguous():
         raise ValueError("%s must be contiguous" % name)
     return ctypes.c_void_p(t.data_ptr())
 
@@ -187,10 +195,14 @@ class Plan:
     """A validated problem (tcbf_plan).  Shapes follow include/tcbf.h."""
 
     def __init__(self, batch, M, N, K, dtype=F16, a_layout=PLANAR, b_layout=PLANAR,
-                 c_layout=PLANAR, a_shared=False, variant=0, device=0):
+                 c_layout=PLANAR, a_shared=False, variant=0, device=0, b_k_contiguous=False, a_batch_stride=0):
+        """b_k_contiguous: fp16 X receiver-contiguous ([batch, 2, N, K] planar,
+        [batch, N, K, 2] interleaved).  a_batch_stride: elements of W's
+        storage type between consecutive batch entries of W (0: packed); W is
+        then passed as a view with that stride along dim 0."""
         d = PlanDesc(ctypes.sizeof(PlanDesc), int(device), int(batch), int(M), int(N), int(K),
                      int(dtype), int(a_layout), int(b_layout), int(c_layout), int(bool(a_shared)),
-                     int(variant))
+                     int(variant), int(bool(b_k_contiguous)), 0, int(a_batch_stride))
         h = ctypes.c_void_p()
         self._h = None
         _check(lib().tcbf_plan(ctypes.byref(d), ctypes.byref(h)), "tcbf_plan")
@@ -200,6 +212,8 @@ class Plan:
         self.dtype, self.a_layout, self.b_layout, self.c_layout = dtype, a_layout, b_layout, c_layout
         self.a_shared = bool(a_shared)
         self.device = int(device)
+        self.b_k_contiguous = bool(b_k_contiguous) and dtype == F16
+        self.a_batch_stride = int(a_batch_stride)
 
     def __del__(self):
         if getattr(self, "_h", None) is not None and _lib is not None:
@@ -230,6 +244,8 @@ class Plan:
             return (self.batch, 2, self.N, (self.K + 31) // 32)
         if _is_f8(self.dtype):
             return f8_codes_shape(self.batch, self.N, self.K, self.b_layout)
+        if self.b_k_contiguous:
+            return (self.batch, 2, self.N, self.K) if self.b_layout == PLANAR else (self.batch, self.N, self.K, 2)
         return (self.batch, 2, self.K, self.N) if self.b_layout == PLANAR else (self.batch, self.K, self.N, 2)
 
     def shape_a_scale(self):
@@ -275,7 +291,7 @@ class Plan:
                 raise ValueError("%s must be %s, got %s" % (nm, dt, t.dtype))
             if tuple(t.shape) != tuple(shp):
                 raise ValueError("%s must have shape %s, got %s" % (nm, shp, tuple(t.shape)))
-        pa, pb, pc = _dev_ptr(A, "A"), _dev_ptr(B, "B"), _dev_ptr(C, "C")
+        pa, pb, pc = _dev_ptr(A, "A", self.a_batch_stride), _dev_ptr(B, "B"), _dev_ptr(C, "C")
         psa = _dev_ptr(a_scale, "a_scale") if a_scale is not None else None
         psb = _dev_ptr(b_scale, "b_scale") if b_scale is not None else None
         _check(lib().tcbf_execute(self._h, pa, pb, pc, psa, psb, _stream_handle(stream)), "tcbf_execute")

@@ -94,7 +94,7 @@ __device__ __forceinline__ i32x4 expand(uint32_t x) {
 template <int CIL>
 __device__ __forceinline__ void int1_tile(const uint32_t *__restrict__ A, const uint32_t *__restrict__ B,
                                           int32_t *__restrict__ C, int64_t M, int64_t N, int64_t K, int64_t kw,
-                                          int a_shared, int64_t c, int tm, int tn, int vec, uint32_t *lds,
+                                          int64_t a_stride, int64_t c, int tm, int tn, int vec, uint32_t *lds,
                                           int (*popA)[U_BM], int (*popB)[U_BN]) {
     const int tid = threadIdx.x;
     const int64_t m0 = (int64_t)tm * U_BM, n0 = (int64_t)tn * U_BN;
@@ -103,7 +103,7 @@ __device__ __forceinline__ void int1_tile(const uint32_t *__restrict__ A, const 
     const int lplane = tid >> 7, lrow = tid & 127;
     const int64_t am = m0 + lrow, bn = n0 + lrow;
     const bool aok = am < M, bok = bn < N;
-    const uint32_t *arow = A + (a_shared ? 0 : c * 2 * M * kw) + (int64_t)lplane * M * kw + (aok ? am : 0) * kw;
+    const uint32_t *arow = A + c * a_stride + (int64_t)lplane * M * kw + (aok ? am : 0) * kw;
     const uint32_t *brow = B + c * 2 * N * kw + (int64_t)lplane * N * kw + (bok ? bn : 0) * kw;
     int pa = 0, pb = 0;
 
@@ -220,7 +220,7 @@ __device__ __forceinline__ void int1_tile(const uint32_t *__restrict__ A, const 
 template <int CIL>
 __global__ __launch_bounds__(U_NT, 2) void cgemm_1bit_mfma_kernel(
     const uint32_t *__restrict__ A, const uint32_t *__restrict__ B, int32_t *__restrict__ C,
-    int64_t M, int64_t N, int64_t K, int64_t kw, int a_shared, int tiles_m, int tiles_n,
+    int64_t M, int64_t N, int64_t K, int64_t kw, int64_t a_stride, int tiles_m, int tiles_n,
     int64_t nblocks, int vec) {
     __shared__ __attribute__((aligned(16))) uint32_t lds[2 * U_STAGE];
     __shared__ int popA[2][U_BM], popB[2][U_BN];
@@ -230,7 +230,7 @@ __global__ __launch_bounds__(U_NT, 2) void cgemm_1bit_mfma_kernel(
     const int rem = (int)(t - c * per_c);
     int tm, tn;
     tile_coords(rem, tiles_m, tiles_n, tm, tn);
-    int1_tile<CIL>(A, B, C, M, N, K, kw, a_shared, c, tm, tn, vec, lds, popA, popB);
+    int1_tile<CIL>(A, B, C, M, N, K, kw, a_stride, c, tm, tn, vec, lds, popA, popB);
 }
 
 // Grouped persistent launch of the int8-MFMA variant: problems of different
@@ -275,7 +275,8 @@ __global__ __launch_bounds__(U_NT, 2) void cgemm_1bit_group_kernel(const Int1Gro
         const int rem = local - c * per_c;
         int tm, tn;
         tile_coords(rem, q.tiles_m, q.tiles_n, tm, tn);
-        int1_tile<CIL>(q.A, q.B, q.C, q.M, q.N, q.K, q.kw, q.a_shared, c, tm, tn, q.vec, lds, popA, popB);
+        int1_tile<CIL>(q.A, q.B, q.C, q.M, q.N, q.K, q.kw, q.a_shared ? 0 : 2 * (int64_t)q.M * q.kw, c, tm, tn, q.vec, lds,
+                       popA, popB);
         // next_tile is rewritten only after the tile's own barriers, which
         // every wave passes after reading it
     }
@@ -293,7 +294,7 @@ constexpr int V_STAGE = 2 * V_BM * V_BKW + 2 * V_BN * V_BKW;
 template <int CIL>
 __global__ __launch_bounds__(V_NT, 2) void cgemm_1bit_valu_kernel(
     const uint32_t *__restrict__ A, const uint32_t *__restrict__ B, int32_t *__restrict__ C,
-    int64_t M, int64_t N, int64_t K, int64_t kw, int a_shared, int tiles_m, int tiles_n,
+    int64_t M, int64_t N, int64_t K, int64_t kw, int64_t a_stride, int tiles_m, int tiles_n,
     int64_t nblocks, int vec) {
     __shared__ __attribute__((aligned(16))) uint32_t lds[2 * V_STAGE];
 
@@ -312,7 +313,7 @@ __global__ __launch_bounds__(V_NT, 2) void cgemm_1bit_valu_kernel(
     const int64_t lr = (isA ? m0 : n0) + lrow;
     const bool lok = lr < (isA ? M : N);
     const uint32_t *src = isA
-        ? A + (a_shared ? 0 : c * 2 * M * kw) + (int64_t)lplane * M * kw + (lok ? lr : 0) * kw
+        ? A + c * a_stride + (int64_t)lplane * M * kw + (lok ? lr : 0) * kw
         : B + c * 2 * N * kw + (int64_t)lplane * N * kw + (lok ? lr : 0) * kw;
     const int loff = (isA ? 0 : 2 * V_BM * V_BKW) + (lplane * 64 + lrow) * V_BKW;
 
@@ -443,7 +444,7 @@ template <int CIL>
 __global__ __launch_bounds__(U_NT, 2) void cgemm_1bit_fp4_kernel(const uint32_t *__restrict__ A,
                                                                  const uint32_t *__restrict__ B,
                                                                  int32_t *__restrict__ C, int M, int N, int K,
-                                                                 int kw, int a_shared, int tiles_m, int tiles_n,
+                                                                 int kw, int64_t a_stride, int tiles_m, int tiles_n,
                                                                  int nblocks) {
     __shared__ __attribute__((aligned(1024))) char lds0[F_STAGE];
     __shared__ __attribute__((aligned(1024))) char lds1[F_STAGE];
@@ -465,7 +466,7 @@ __global__ __launch_bounds__(U_NT, 2) void cgemm_1bit_fp4_kernel(const uint32_t 
     // stored chunk l % 4, which holds global chunk (l % 4) ^ ((row / 4) % 4).
     const int op = wave >> 1, plane = wave & 1;
     const int rows = op ? N : M, r0 = op ? n0 : m0;
-    const uint32_t *base = op ? B + (int64_t)c * 2 * N * kw : A + (a_shared ? (int64_t)0 : (int64_t)c * 2 * M * kw);
+    const uint32_t *base = op ? B + (int64_t)c * 2 * N * kw : A + (int64_t)c * a_stride;
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void *)base, 0, 8 * rows * kw, tile::RSRC_FLAGS);
     const int lrow = lane >> 2;
     const int gch = (lane & 3) ^ ((lane >> 4) & 3);
@@ -663,15 +664,15 @@ hipError_t int1_launch(const Problem &p, const Int1Config &cfg, const uint32_t *
     if (cfg.variant == 3) {
         auto fn = cil ? cgemm_1bit_fp4_kernel<1> : cgemm_1bit_fp4_kernel<0>;
         hipLaunchKernelGGL(fn, dim3((uint32_t)nblocks), dim3(U_NT), 0, stream, A, B, C, (int)p.M, (int)p.N, (int)p.K,
-                           (int)kw, p.a_shared, tiles_m, tiles_n, (int)nblocks);
+                           (int)kw, p.a_stride, tiles_m, tiles_n, (int)nblocks);
     } else if (cfg.variant == 1) {
         auto fn = cil ? cgemm_1bit_mfma_kernel<1> : cgemm_1bit_mfma_kernel<0>;
         hipLaunchKernelGGL(fn, dim3((uint32_t)nblocks), dim3(U_NT), 0, stream, A, B, C, p.M, p.N, p.K,
-                           kw, p.a_shared, tiles_m, tiles_n, nblocks, vec);
+                           kw, p.a_stride, tiles_m, tiles_n, nblocks, vec);
     } else {
         auto fn = cil ? cgemm_1bit_valu_kernel<1> : cgemm_1bit_valu_kernel<0>;
         hipLaunchKernelGGL(fn, dim3((uint32_t)nblocks), dim3(V_NT), 0, stream, A, B, C, p.M, p.N, p.K,
-                           kw, p.a_shared, tiles_m, tiles_n, nblocks, vec);
+                           kw, p.a_stride, tiles_m, tiles_n, nblocks, vec);
     }
     return hipGetLastError();
 }

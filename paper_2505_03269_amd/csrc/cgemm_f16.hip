@@ -267,10 +267,25 @@ struct BLoaderInter {
     }
 };
 
+// X receiver-contiguous, planar [2][N][K] or interleaved [N][K][2]: the
+// same rows as W's (samples in place of beams), staged into the X region,
+// which has W's row layout (the MFMA's B operand is read by sample rows).
+static_assert(BM == BN && PLANE_A == PLANE_B, "X rows stage like W rows");
+template <class L> struct BLoaderKMajor {
+    L l;
+    __device__ void init(const uint16_t *X, int64_t K, int64_t N, int64_t n0, int tid) { l.init(X, N, K, n0, tid); }
+    __device__ void load(u32x4 (&r)[4], int64_t k0, int64_t K, bool vec) { l.load(r, k0, K, vec); }
+    __device__ static void store(uint16_t *st, int tid, const u32x4 (&r)[4]) { L::store(st + 2 * PLANE_A, tid, r); }
+};
+
 template <int AIL> struct ASel { typedef ALoaderPlanar T; };
 template <> struct ASel<1> { typedef ALoaderInter T; };
+// BIL: 0 planar [2][K][N], 1 interleaved [K][N][2], 2 planar [2][N][K],
+// 3 interleaved [N][K][2]
 template <int BIL> struct BSel { typedef BLoaderPlanar T; };
 template <> struct BSel<1> { typedef BLoaderInter T; };
+template <> struct BSel<2> { typedef BLoaderKMajor<ALoaderPlanar> T; };
+template <> struct BSel<3> { typedef BLoaderKMajor<ALoaderInter> T; };
 
 __device__ __forceinline__ half8 lds_frag(const uint16_t *plane, int row, int ch) {
     return *reinterpret_cast<const half8 *>(plane + lds_off(row, ch));
@@ -312,7 +327,7 @@ __device__ __forceinline__ void store4(float *C, int64_t c, int64_t M, int64_t N
 template <int AIL, int BIL, int CIL>
 __global__ __launch_bounds__(NT, 2) void cgemm_f16_kernel(
     const uint16_t *__restrict__ A, const uint16_t *__restrict__ B, float *__restrict__ C,
-    int64_t M, int64_t N, int64_t K, int a_shared, int tiles_m, int tiles_n, int64_t nblocks,
+    int64_t M, int64_t N, int64_t K, int64_t a_stride, int tiles_m, int tiles_n, int64_t nblocks,
     int a_vec, int b_vec) {
     __shared__ __attribute__((aligned(16))) uint16_t lds[2 * STAGE];
 
@@ -325,7 +340,7 @@ __global__ __launch_bounds__(NT, 2) void cgemm_f16_kernel(
     tile_coords(rem, tiles_m, tiles_n, tm, tn);
     const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
 
-    const uint16_t *Wc = A + (a_shared ? 0 : c * 2 * M * K);
+    const uint16_t *Wc = A + c * a_stride;
     const uint16_t *Xc = B + c * 2 * K * N;
 
     typename ASel<AIL>::T al;
@@ -455,9 +470,9 @@ template <int WM, int BK, int NS> struct FastLds {
 // cache lines; with planar W each beam row contributes a 64-byte piece.
 template <int WM, int BK, int NS, int CIL, int AB>
 __device__ __forceinline__ void fast_tile(const uint16_t *__restrict__ A, const uint16_t *__restrict__ B,
-                                          float *__restrict__ C, int M, int N, int K, int a_shared, int c, int tm,
-                                          int tn, char *lds0, char *lds1, char *lds2, char *lds3, char *lds4,
-                                          char *lds5) {
+                                          float *__restrict__ C, int M, int N, int K, int64_t a_stride, int c,
+                                          int tm, int tn, char *lds0, char *lds1, char *lds2, char *lds3,
+                                          char *lds4, char *lds5) {
     typedef FastGeo<WM, BK> G;
     constexpr int TM = G::TM, NW = G::NW;
     static_assert(NS >= 2 && NS <= 6, "ring depth");
@@ -485,7 +500,7 @@ __device__ __forceinline__ void fast_tile(const uint16_t *__restrict__ A, const 
 
     static_assert(!AB || BK == 32, "blocked W holds 32-receiver blocks");
     const int KW = AB ? (K + 31) / 32 * 32 : K;  // receivers per W row as stored (blocked: padded)
-    const uint16_t *Wc = A + (a_shared ? (int64_t)0 : (int64_t)c * 2 * M * KW);
+    const uint16_t *Wc = A + (int64_t)c * a_stride;
     const uint16_t *Xc = B + (int64_t)c * 2 * K * N;
     const __amdgpu_buffer_rsrc_t rw = __builtin_amdgcn_make_buffer_rsrc((void *)Wc, 0, 4 * M * KW, RSRC_FLAGS);
     const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc((void *)Xc, 0, 4 * K * N, RSRC_FLAGS);
@@ -639,7 +654,7 @@ __device__ __forceinline__ void fast_tile(const uint16_t *__restrict__ A, const 
 template <int WM, int BK, int NS, int CIL, int AB>
 __global__ __launch_bounds__(128 * WM, WM == 2 ? 2 : 1) void cgemm_f16_fast_kernel(
     const uint16_t *__restrict__ A, const uint16_t *__restrict__ B, float *__restrict__ C,
-    int M, int N, int K, int a_shared, int tiles_m, int tiles_n, int nblocks) {
+    int M, int N, int K, int64_t a_stride, int tiles_m, int tiles_n, int nblocks) {
     TCBF_FAST_LDS(WM, BK, NS)
     const int t = (int)xcd_remap(blockIdx.x, nblocks);
     const int per_c = tiles_m * tiles_n;
@@ -647,7 +662,7 @@ __global__ __launch_bounds__(128 * WM, WM == 2 ? 2 : 1) void cgemm_f16_fast_kern
     const int rem = t - c * per_c;
     int tm, tn;
     tile_coords(rem, tiles_m, tiles_n, tm, tn);
-    fast_tile<WM, BK, NS, CIL, AB>(A, B, C, M, N, K, a_shared, c, tm, tn, lds0, lds1, lds2, lds3, lds4, lds5);
+    fast_tile<WM, BK, NS, CIL, AB>(A, B, C, M, N, K, a_stride, c, tm, tn, lds0, lds1, lds2, lds3, lds4, lds5);
 }
 
 // ===========================================================================
@@ -671,8 +686,8 @@ __global__ __launch_bounds__(128 * WM, WM == 2 ? 2 : 1) void cgemm_f16_fast_kern
 
 template <int CIL, int AB>
 __device__ __forceinline__ void split_tile(const uint16_t *__restrict__ A, const uint16_t *__restrict__ B,
-                                           float *__restrict__ C, int M, int N, int K, int a_shared, int c, int tm,
-                                           int tn, char *wb0, char *wb1, char *xb0, char *xb1, char *xb2) {
+                                           float *__restrict__ C, int M, int N, int K, int64_t a_stride, int c,
+                                           int tm, int tn, char *wb0, char *wb1, char *xb0, char *xb1, char *xb2) {
     constexpr int WM = 2, BK = 32;
     typedef FastGeo<WM, BK> G;
     constexpr int TM = G::TM, NW = G::NW;
@@ -694,7 +709,7 @@ __device__ __forceinline__ void split_tile(const uint16_t *__restrict__ A, const
     const int hl = lane >> 5, l32 = lane & 31;
 
     const int KW = AB ? (K + 31) / 32 * 32 : K;
-    const uint16_t *Wc = A + (a_shared ? (int64_t)0 : (int64_t)c * 2 * M * KW);
+    const uint16_t *Wc = A + (int64_t)c * a_stride;
     const uint16_t *Xc = B + (int64_t)c * 2 * K * N;
     const __amdgpu_buffer_rsrc_t rw = __builtin_amdgcn_make_buffer_rsrc((void *)Wc, 0, 4 * M * KW, RSRC_FLAGS);
     const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc((void *)Xc, 0, 4 * K * N, RSRC_FLAGS);
@@ -842,7 +857,7 @@ template <int CIL, int AB>
 __global__ __launch_bounds__(256, 2) void cgemm_f16_split_kernel(const uint16_t *__restrict__ A,
                                                                  const uint16_t *__restrict__ B,
                                                                  float *__restrict__ C, int M, int N, int K,
-                                                                 int a_shared, int tiles_m, int tiles_n,
+                                                                 int64_t a_stride, int tiles_m, int tiles_n,
                                                                  int nblocks) {
     TCBF_SPLIT_LDS
     const int t = (int)xcd_remap(blockIdx.x, nblocks);
@@ -851,7 +866,7 @@ __global__ __launch_bounds__(256, 2) void cgemm_f16_split_kernel(const uint16_t 
     const int rem = t - c * per_c;
     int tm, tn;
     tile_coords(rem, tiles_m, tiles_n, tm, tn);
-    split_tile<CIL, AB>(A, B, C, M, N, K, a_shared, c, tm, tn, wb0, wb1, xb0, xb1, xb2);
+    split_tile<CIL, AB>(A, B, C, M, N, K, a_stride, c, tm, tn, wb0, wb1, xb0, xb1, xb2);
 }
 
 // ===========================================================================
@@ -1063,7 +1078,7 @@ template <int CIL, int AB, int BIL>
 __global__ __launch_bounds__(512, 1) void cgemm_f16_pp_kernel(const uint16_t *__restrict__ A,
                                                               const uint16_t *__restrict__ B,
                                                               float *__restrict__ C, int M, int N, int K,
-                                                              int a_shared, int tiles_m, int tiles_n,
+                                                              int64_t a_stride, int tiles_m, int tiles_n,
                                                               int total_tiles) {
     typedef FastGeo<4, 32> G;
     constexpr int TM = G::TM, NW = G::NW;
@@ -1185,7 +1200,7 @@ __global__ __launch_bounds__(512, 1) void cgemm_f16_pp_kernel(const uint16_t *__
         if (l_live) {
             int c, m0, n0;
             tile_of(l_round, c, m0, n0);
-            const uint16_t *Wc = A + (a_shared ? (int64_t)0 : (int64_t)c * 2 * M * KW);
+            const uint16_t *Wc = A + (int64_t)c * a_stride;
             const uint16_t *Xc = B + (int64_t)c * 2 * K * N;
             rw = __builtin_amdgcn_make_buffer_rsrc((void *)Wc, 0, 4 * M * KW, RSRC_FLAGS);
             rx = __builtin_amdgcn_make_buffer_rsrc((void *)Xc, 0, 4 * K * N, RSRC_FLAGS);
@@ -1378,7 +1393,8 @@ __global__ __launch_bounds__(256, 2) void cgemm_f16_group_kernel(const GroupArgs
         const int rem = local - c * per_c;
         int tm, tn;
         tile_coords(rem, q.tiles_m, q.tiles_n, tm, tn);
-        fast_tile<2, 32, 2, CIL, AB>(q.A, q.B, q.C, q.M, q.N, q.K, q.a_shared, c, tm, tn, lds0, lds1, lds2, lds3,
+        const int64_t a_stride = q.a_shared ? 0 : 2 * (int64_t)q.M * (AB ? (q.K + 31) / 32 * 32 : q.K);
+        fast_tile<2, 32, 2, CIL, AB>(q.A, q.B, q.C, q.M, q.N, q.K, a_stride, c, tm, tn, lds0, lds1, lds2, lds3,
                                      lds4, lds5);
         // next_tile is rewritten only after the tile's own barriers, which
         // every wave passes after reading it
@@ -1620,17 +1636,20 @@ __global__ __launch_bounds__(512, 1) void cgemm_f16_pp_group_kernel(const PpGrou
 
 __global__ void group_reset_kernel(unsigned int *counter) { *counter = 0u; }
 
-typedef void (*KernFn)(const uint16_t *, const uint16_t *, float *, int64_t, int64_t, int64_t, int,
+typedef void (*KernFn)(const uint16_t *, const uint16_t *, float *, int64_t, int64_t, int64_t, int64_t,
                        int, int, int64_t, int, int);
-typedef void (*FastFn)(const uint16_t *, const uint16_t *, float *, int, int, int, int, int, int, int);
+typedef void (*FastFn)(const uint16_t *, const uint16_t *, float *, int, int, int, int64_t, int, int, int);
 
+// bil: 0 planar, 1 interleaved, 2 planar receiver-contiguous, 3 interleaved
+// receiver-contiguous
 KernFn pick(int ail, int bil, int cil) {
-    static const KernFn table[8] = {
-        cgemm_f16_kernel<0, 0, 0>, cgemm_f16_kernel<0, 0, 1>, cgemm_f16_kernel<0, 1, 0>,
-        cgemm_f16_kernel<0, 1, 1>, cgemm_f16_kernel<1, 0, 0>, cgemm_f16_kernel<1, 0, 1>,
-        cgemm_f16_kernel<1, 1, 0>, cgemm_f16_kernel<1, 1, 1>,
+    static const KernFn table[16] = {
+        cgemm_f16_kernel<0, 0, 0>, cgemm_f16_kernel<0, 0, 1>, cgemm_f16_kernel<0, 1, 0>, cgemm_f16_kernel<0, 1, 1>,
+        cgemm_f16_kernel<0, 2, 0>, cgemm_f16_kernel<0, 2, 1>, cgemm_f16_kernel<0, 3, 0>, cgemm_f16_kernel<0, 3, 1>,
+        cgemm_f16_kernel<1, 0, 0>, cgemm_f16_kernel<1, 0, 1>, cgemm_f16_kernel<1, 1, 0>, cgemm_f16_kernel<1, 1, 1>,
+        cgemm_f16_kernel<1, 2, 0>, cgemm_f16_kernel<1, 2, 1>, cgemm_f16_kernel<1, 3, 0>, cgemm_f16_kernel<1, 3, 1>,
     };
-    return table[(ail << 2) | (bil << 1) | cil];
+    return table[(ail << 3) | (bil << 1) | cil];
 }
 
 // Fast-kernel configurations (variant: beam waves WM, receivers per stage,
@@ -1689,7 +1708,8 @@ static bool fast_ok(const Problem &p) {
     const int64_t lim = (int64_t)1 << 31;
     const bool ab = p.a_layout == TCBF_BLOCKED;
     const int64_t kw = ab ? (p.K + 31) / 32 * 32 : p.K;
-    return (ab || (p.a_layout == TCBF_PLANAR && p.K % 8 == 0)) && p.b_layout == TCBF_PLANAR && p.N % 8 == 0 &&
+    return (ab || (p.a_layout == TCBF_PLANAR && p.K % 8 == 0)) && p.b_layout == TCBF_PLANAR && !p.b_kmajor &&
+           p.N % 8 == 0 &&
            4 * p.M * kw < lim && 4 * p.K * p.N < lim && 8 * p.M * p.N < lim && p.M < lim && p.N < lim &&
            p.batch * ((p.M + BM - 1) / BM) * ((p.N + BN - 1) / BN) < lim;
 }
@@ -1721,6 +1741,7 @@ static int device_cus(int device) {
 // CU and measured 4-13% faster than variant 2 on such shapes), variant 2 for
 // smaller problems, the generic kernel where the fast ones do not apply.
 static int default_variant(const Problem &p) {
+    if (p.b_kmajor) return 1;  // receiver-contiguous X: the generic kernel
     const int64_t tiles = p.batch * ((p.M + 255) / 256) * ((p.N + BN - 1) / BN);
     const bool big = tiles >= device_cus(p.device) && tiles * ((p.K + 31) / 32) < ((int64_t)1 << 31);
     // interleaved data: the ping-pong kernel (also for fewer tiles than CUs
@@ -1753,7 +1774,9 @@ bool f16_select(const Problem &p, int forced_variant, F16Config *cfg) {
     // 16-byte loads need every row start 16-byte aligned (base pointers are
     // required to be 16-byte aligned by the ABI).
     cfg->a_vec = p.a_layout == TCBF_PLANAR ? (p.K % 8 == 0) : (p.K % 4 == 0);
-    cfg->b_vec = p.b_layout == TCBF_PLANAR ? (p.N % 8 == 0) : (p.N % 4 == 0);
+    // (receiver-contiguous X: rows of K samples' receivers, like W's)
+    const int64_t xrow = p.b_kmajor ? p.K : p.N;
+    cfg->b_vec = p.b_layout == TCBF_PLANAR ? (xrow % 8 == 0) : (xrow % 4 == 0);
     return true;
 }
 
@@ -1783,22 +1806,22 @@ hipError_t f16_launch(const Problem &p, const F16Config &cfg, const void *A, con
         const FastFn fn = pp[(cil << 2) | (ab << 1) | (p.b_layout == TCBF_INTERLEAVED)];
         const int grid = (int)std::min<int64_t>(nblocks, device_cus(p.device));
         hipLaunchKernelGGL(fn, dim3((uint32_t)grid), dim3(cfg.threads), 0, stream, (const uint16_t *)A,
-                           (const uint16_t *)B, (float *)C, (int)p.M, (int)p.N, (int)p.K, p.a_shared, tiles_m,
+                           (const uint16_t *)B, (float *)C, (int)p.M, (int)p.N, (int)p.K, p.a_stride, tiles_m,
                            tiles_n, (int)nblocks);
         return hipGetLastError();
     }
     if (cfg.variant >= kFirstFast) {
         FastFn fn = fast_fn(cfg.variant, p.c_layout == TCBF_INTERLEAVED, p.a_layout == TCBF_BLOCKED);
         hipLaunchKernelGGL(fn, dim3((uint32_t)nblocks), dim3(cfg.threads), 0, stream, (const uint16_t *)A,
-                           (const uint16_t *)B, (float *)C, (int)p.M, (int)p.N, (int)p.K, p.a_shared,
+                           (const uint16_t *)B, (float *)C, (int)p.M, (int)p.N, (int)p.K, p.a_stride,
                            tiles_m, tiles_n, (int)nblocks);
         return hipGetLastError();
     }
-    KernFn fn = pick(p.a_layout == TCBF_INTERLEAVED, p.b_layout == TCBF_INTERLEAVED,
+    KernFn fn = pick(p.a_layout == TCBF_INTERLEAVED, (p.b_layout == TCBF_INTERLEAVED) + 2 * (p.b_kmajor != 0),
                      p.c_layout == TCBF_INTERLEAVED);
     hipLaunchKernelGGL(fn, dim3((uint32_t)nblocks), dim3(NT), 0, stream,
                        (const uint16_t *)A, (const uint16_t *)B, (float *)C, p.M, p.N, p.K,
-                       p.a_shared, tiles_m, tiles_n, nblocks, (int)cfg.a_vec, (int)cfg.b_vec);
+                       p.a_stride, tiles_m, tiles_n, nblocks, (int)cfg.a_vec, (int)cfg.b_vec);
     return hipGetLastError();
 }
 

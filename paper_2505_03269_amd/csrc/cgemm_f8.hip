@@ -94,7 +94,7 @@ __device__ __forceinline__ f32x16 mma(const i32x8 &x, const i32x8 &w, const f32x
 template <int NS, int CIL, int MX, int BL>
 __device__ __forceinline__ void f8_tile(const uint8_t *__restrict__ A, const uint8_t *__restrict__ B,
                                         float *__restrict__ C, const void *__restrict__ a_scale,
-                                        const void *__restrict__ b_scale, int M, int N, int Kp, int a_shared,
+                                        const void *__restrict__ b_scale, int M, int N, int Kp, int64_t a_stride,
                                         int c, int tm, int tn, char *lds0, char *lds1, char *lds2, char *lds3,
                                         char *slabs) {
     static_assert(NS >= 2 && NS <= 4 && NS <= SLAB_STAGES + 1, "ring depth");
@@ -115,9 +115,9 @@ __device__ __forceinline__ void f8_tile(const uint8_t *__restrict__ A, const uin
     const int wm = wave >> 1, wn = wave & 1;
     const int hl = lane >> 5, l32 = lane & 31;
 
-    const int cw = a_shared ? 0 : c;
+    const int cw = a_stride == 0 ? 0 : c;  // scale entry (codes: a_stride bytes apart)
     const int KS = BL ? (Kp + BK - 1) / BK * BK : Kp;  // bytes per row as stored (blocked: whole blocks)
-    const uint8_t *Wc = A + (int64_t)cw * 2 * M * KS;
+    const uint8_t *Wc = A + (int64_t)c * a_stride;
     const uint8_t *Xc = B + (int64_t)c * 2 * N * KS;
     const __amdgpu_buffer_rsrc_t rw = __builtin_amdgcn_make_buffer_rsrc((void *)Wc, 0, 2 * M * KS, RSRC_FLAGS);
     const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc((void *)Xc, 0, 2 * N * KS, RSRC_FLAGS);
@@ -312,7 +312,7 @@ __device__ __forceinline__ void f8_tile(const uint8_t *__restrict__ A, const uin
 template <int NS, int CIL, int MX, int BL>
 __global__ __launch_bounds__(NT, 2) void cgemm_f8_kernel(
     const uint8_t *__restrict__ A, const uint8_t *__restrict__ B, float *__restrict__ C,
-    const void *__restrict__ a_scale, const void *__restrict__ b_scale, int M, int N, int Kp, int a_shared,
+    const void *__restrict__ a_scale, const void *__restrict__ b_scale, int M, int N, int Kp, int64_t a_stride,
     int tiles_m, int tiles_n, int nblocks) {
     TCBF_F8_LDS(NS, MX)
     const int t = (int)xcd_remap(blockIdx.x, nblocks);
@@ -321,7 +321,7 @@ __global__ __launch_bounds__(NT, 2) void cgemm_f8_kernel(
     const int rem = t - c * per_c;
     int tm, tn;
     tile_coords(rem, tiles_m, tiles_n, tm, tn);
-    f8_tile<NS, CIL, MX, BL>(A, B, C, a_scale, b_scale, M, N, Kp, a_shared, c, tm, tn, lds0, lds1, lds2, lds3,
+    f8_tile<NS, CIL, MX, BL>(A, B, C, a_scale, b_scale, M, N, Kp, a_stride, c, tm, tn, lds0, lds1, lds2, lds3,
                              slabs);
 }
 
@@ -369,8 +369,9 @@ __global__ __launch_bounds__(NT, 2) void cgemm_f8_group_kernel(const F8GroupArgs
         const int rem = local - c * per_c;
         int tm, tn;
         tile_coords(rem, q.tiles_m, q.tiles_n, tm, tn);
-        f8_tile<2, CIL, MX, BL>(q.A, q.B, q.C, q.a_scale, q.b_scale, q.M, q.N, q.Kp, q.a_shared, c, tm, tn, lds0, lds1,
-                            lds2, lds3, slabs);
+        const int64_t a_stride = q.a_shared ? 0 : 2 * (int64_t)q.M * (BL ? (q.Kp + BK - 1) / BK * BK : q.Kp);
+        f8_tile<2, CIL, MX, BL>(q.A, q.B, q.C, q.a_scale, q.b_scale, q.M, q.N, q.Kp, a_stride, c, tm, tn, lds0, lds1,
+                                lds2, lds3, slabs);
         // next_tile is rewritten only after the tile's own barriers, which
         // every wave passes after reading it
     }
@@ -378,8 +379,8 @@ __global__ __launch_bounds__(NT, 2) void cgemm_f8_group_kernel(const F8GroupArgs
 
 __global__ void f8_group_reset_kernel(unsigned int *counter) { *counter = 0u; }
 
-typedef void (*F8Fn)(const uint8_t *, const uint8_t *, float *, const void *, const void *, int, int, int, int, int,
-                     int, int);
+typedef void (*F8Fn)(const uint8_t *, const uint8_t *, float *, const void *, const void *, int, int, int, int64_t,
+                     int, int, int);
 
 template <int BL> F8Fn f8_fn_of(int v, bool cil, bool mx) {
     if (mx) {
@@ -425,7 +426,7 @@ hipError_t f8_launch(const Problem &p, const F8Config &cfg, bool mx, const void 
     const int64_t nblocks = p.batch * tiles_m * tiles_n;
     F8Fn fn = f8_fn(cfg.variant, p.c_layout == TCBF_INTERLEAVED, mx, p.a_layout == TCBF_BLOCKED);
     hipLaunchKernelGGL(fn, dim3((uint32_t)nblocks), dim3(NT), 0, stream, (const uint8_t *)A, (const uint8_t *)B,
-                       (float *)C, a_scale, b_scale, (int)p.M, (int)p.N, (int)f8_kp(p.K), p.a_shared, tiles_m,
+                       (float *)C, a_scale, b_scale, (int)p.M, (int)p.N, (int)f8_kp(p.K), p.a_stride, tiles_m,
                        tiles_n, (int)nblocks);
     return hipGetLastError();
 }

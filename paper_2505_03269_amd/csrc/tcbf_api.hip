@@ -6,6 +6,7 @@
 #include <atomic>
 #include <mutex>
 #include <new>
+#include <stddef.h>
 #include <stdio.h>
 #include <string.h>
 
@@ -19,9 +20,21 @@ struct tcbf_plan_s {
     tcbf::F8Config f8;
 };
 
+namespace tcbf {
+int64_t w_entry_elems(int dtype, int a_layout, int64_t M, int64_t K) {
+    if (dtype == TCBF_F16) return 2 * M * (a_layout == TCBF_BLOCKED ? (K + 31) / 32 * 32 : K);
+    if (dtype == TCBF_INT1) return 2 * M * ((K + 31) / 32);
+    const int64_t kp = f8_kp(K);
+    return 2 * M * (a_layout == TCBF_BLOCKED ? (kp + 63) / 64 * 64 : kp);
+}
+}  // namespace tcbf
+
 namespace {
 
-constexpr uint32_t kDescV1 = (uint32_t)sizeof(tcbf_plan_desc);
+// Descriptor sizes: the fields up to `variant` (TCBF_VERSION <= 3), and the
+// whole struct (b_k_contiguous, a_batch_stride).
+constexpr uint32_t kDescV1 = (uint32_t)offsetof(tcbf_plan_desc, b_k_contiguous);
+constexpr uint32_t kDescV2 = (uint32_t)sizeof(tcbf_plan_desc);
 constexpr int64_t kMaxIndex = (int64_t)1 << 31;  // per-launch workgroup limit
 
 bool is_layout(int32_t v) { return v == TCBF_PLANAR || v == TCBF_INTERLEAVED; }
@@ -63,15 +76,42 @@ tcbf_status current_device_is(int device) {
     return cur == device ? TCBF_SUCCESS : TCBF_ERROR_INVALID_VALUE;
 }
 
+// A descriptor of either size as the whole struct (fields a shorter one
+// lacks are zero).
+tcbf_plan_desc full_desc(const tcbf_plan_desc *d) {
+    tcbf_plan_desc r;
+    memset(&r, 0, sizeof(r));
+    memcpy(&r, d, d->struct_size >= kDescV2 ? kDescV2 : kDescV1);
+    r.struct_size = kDescV2;
+    return r;
+}
+
+// Bytes of one element of W's storage type.
+int64_t w_elem_bytes(int32_t dtype) { return dtype == TCBF_F16 ? 2 : dtype == TCBF_INT1 ? 4 : 1; }
+
 // Validate a descriptor without touching the HIP runtime.
-tcbf_status validate_desc(const tcbf_plan_desc *d) {
-    if (d->struct_size < kDescV1) return TCBF_ERROR_INVALID_VALUE;
+tcbf_status validate_desc(const tcbf_plan_desc *dd) {
+    if (dd->struct_size < kDescV1) return TCBF_ERROR_INVALID_VALUE;
+    const tcbf_plan_desc full = full_desc(dd);
+    const tcbf_plan_desc *d = &full;
+    if (d->reserved != 0 || (d->b_k_contiguous != 0 && d->b_k_contiguous != 1)) return TCBF_ERROR_INVALID_VALUE;
+    if (d->a_batch_stride < 0 || (d->a_batch_stride > 0 && d->a_shared != 0)) return TCBF_ERROR_INVALID_VALUE;
     if (d->batch < 1 || d->M < 1 || d->N < 1 || d->K < 1) return TCBF_ERROR_INVALID_VALUE;
     // the receiver-blocked layout: fp16 weights (A), or both FP8 operands
     const bool a_ok = is_layout(d->a_layout) || (d->a_layout == TCBF_BLOCKED && (d->dtype == TCBF_F16 || is_f8(d->dtype)));
     const bool b_ok = is_layout(d->b_layout) || (d->b_layout == TCBF_BLOCKED && is_f8(d->dtype));
     if (!a_ok || !b_ok || !is_layout(d->c_layout)) return TCBF_ERROR_INVALID_VALUE;
     if (d->variant < 0) return TCBF_ERROR_INVALID_VALUE;
+    if (d->a_batch_stride > 0) {
+        // at least one entry, whole 16-byte units, and every entry's start
+        // representable
+        const int64_t eb = w_elem_bytes(d->dtype);
+        if (d->dtype != TCBF_F16 && d->dtype != TCBF_INT1 && !is_f8(d->dtype)) return TCBF_ERROR_INVALID_VALUE;
+        if (d->a_batch_stride < tcbf::w_entry_elems(d->dtype, d->a_layout, d->M, d->K)) return TCBF_ERROR_INVALID_VALUE;
+        if ((d->a_batch_stride * eb) % 16 != 0) return TCBF_ERROR_INVALID_VALUE;
+        if (d->a_batch_stride > ((int64_t)1 << 60) / d->batch / eb) return TCBF_ERROR_NOT_SUPPORTED;
+    }
+    if (d->b_k_contiguous != 0 && d->dtype == TCBF_F16 && !is_layout(d->b_layout)) return TCBF_ERROR_INVALID_VALUE;
     if (d->dtype == TCBF_F16) {
         // every per-channel plane must be indexable with 32-bit element counts
         const int64_t kw = d->a_layout == TCBF_BLOCKED ? (d->K + 31) / 32 * 32 : d->K;
@@ -122,12 +162,14 @@ tcbf_status tcbf_plan(const tcbf_plan_desc *desc, tcbf_plan_t *plan) {
     tcbf_status st = validate_desc(desc);
     if (st != TCBF_SUCCESS) return st;
 
-    tcbf::Problem p{desc->batch, desc->M, desc->N, desc->K,
-                    desc->a_layout, desc->b_layout, desc->c_layout, desc->a_shared != 0, desc->device};
+    const tcbf_plan_desc d = full_desc(desc);
+    const int64_t dense = tcbf::w_entry_elems(d.dtype, d.a_layout, d.M, d.K);
+    tcbf::Problem p{d.batch, d.M, d.N, d.K, d.a_layout, d.b_layout, d.c_layout, d.a_shared != 0, d.device,
+                    d.a_shared != 0 ? 0 : d.a_batch_stride > 0 ? d.a_batch_stride : dense,
+                    d.dtype == TCBF_F16 && d.b_k_contiguous != 0};
     tcbf_plan_s tmp;
     memset(&tmp, 0, sizeof(tmp));
-    memcpy(&tmp.desc, desc, kDescV1);
-    tmp.desc.struct_size = kDescV1;
+    tmp.desc = d;
     tmp.prob = p;
     int64_t wgs = 0;
     if (desc->dtype == TCBF_F16) {
@@ -364,7 +406,8 @@ tcbf_status group_execute(int32_t device, int32_t dtype, int32_t c_layout, const
         if (!aligned16(g.A) || !aligned16(g.B) || !aligned16(g.C)) return TCBF_ERROR_INVALID_VALUE;
         if (g.batch < 1 || g.M < 1 || g.N < 1 || g.K < 1) return TCBF_ERROR_INVALID_VALUE;
         probs[i] = tcbf::Problem{g.batch, g.M, g.N, g.K, layout, (blocked && is_f8(dtype)) ? TCBF_BLOCKED : TCBF_PLANAR,
-                                 c_layout, g.a_shared != 0, device};
+                                 c_layout, g.a_shared != 0, device,
+                                 g.a_shared != 0 ? 0 : tcbf::w_entry_elems(dtype, layout, g.M, g.K), 0};
         if (g.reserved != 0 || g.variant < 0) return TCBF_ERROR_INVALID_VALUE;
         variants[i] = 0;
         if (dtype == TCBF_F16) {

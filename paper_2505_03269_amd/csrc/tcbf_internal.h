@@ -15,7 +15,14 @@ struct Problem {
     int a_layout, b_layout, c_layout;  // tcbf_layout
     int a_shared;
     int device;  // HIP device ordinal the problem runs on
+    // W storage elements (fp16 values, code bytes, packed words) from one
+    // batch entry's W to the next: 0 for a shared W, else at least one
+    // entry (set by the API layer from the descriptor)
+    int64_t a_stride;
+    int b_kmajor;  // fp16 X receiver-contiguous ([N][K] per plane)
 };
+// W storage elements of one batch entry in the given layout.
+int64_t w_entry_elems(int dtype, int a_layout, int64_t M, int64_t K);
 
 // FP16 mode (16-bit in, fp32 out).
 struct F16Config {

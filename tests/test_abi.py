@@ -43,7 +43,7 @@ def test_status_strings_and_version():
     assert tcbf.status_string(1) == "TCBF_ERROR_INVALID_VALUE"
     assert tcbf.status_string(4) == "TCBF_ERROR_DEVICE"
     assert tcbf.status_string(99) == "TCBF_UNKNOWN_STATUS"
-    assert tcbf.lib().tcbf_version() == 3
+    assert tcbf.lib().tcbf_version() == 4
 
 
 def _plan_status(**kw):
@@ -77,9 +77,30 @@ def _plan_status(**kw):
     dict(dtype=tcbf.F8_E4M3, a_layout=tcbf.INTERLEAVED), dict(dtype=tcbf.MXF8_E4M3, b_layout=tcbf.INTERLEAVED),
     dict(dtype=tcbf.F8_E4M3, N=6), dict(dtype=tcbf.MXF8_E4M3, N=1), dict(dtype=tcbf.F8_E4M3, variant=3),
     dict(dtype=4),
+    # receiver-contiguous X and strided W (descriptor fields of version 4)
+    dict(reserved=1), dict(b_k_contiguous=2), dict(a_batch_stride=-8), dict(a_shared=1, a_batch_stride=1024),
+    dict(a_batch_stride=8), dict(a_batch_stride=132), dict(b_k_contiguous=1, variant=2),
+    dict(b_k_contiguous=1, variant=9), dict(b_k_contiguous=1, b_layout=tcbf.BLOCKED),
+    dict(dtype=tcbf.INT1, a_batch_stride=12), dict(dtype=tcbf.F8_E4M3, a_batch_stride=8 * 32),
+    dict(a_layout=tcbf.BLOCKED, a_batch_stride=2 * 8 * 8),
 ])
 def test_bad_descriptors_rejected_without_device(bad):
     assert _plan_status(**bad) == 1
+
+
+def test_version4_fields_accepted_and_short_descriptor_ignores_them():
+    """Valid strides and receiver-contiguous X pass validation (the plan then
+    needs a device); a descriptor whose struct_size ends before the version-4
+    fields is read without them."""
+    for ok in (dict(a_batch_stride=136), dict(a_batch_stride=1 << 20), dict(b_k_contiguous=1),
+               dict(b_k_contiguous=1, b_layout=tcbf.INTERLEAVED, variant=1),
+               dict(dtype=tcbf.INT1, a_batch_stride=16), dict(dtype=tcbf.F8_E4M3, a_batch_stride=2 * 8 * 32),
+               dict(dtype=tcbf.F8_E4M3, b_k_contiguous=1), dict(a_layout=tcbf.BLOCKED, a_batch_stride=2 * 8 * 32)):
+        assert _plan_status(**ok) in (0, 4), ok
+    v3 = tcbf.PlanDesc.b_k_contiguous.offset
+    assert v3 == 64 and ctypes.sizeof(tcbf.PlanDesc) == 80
+    assert _plan_status(struct_size=v3, reserved=7, b_k_contiguous=9, a_batch_stride=-1) in (0, 4)
+    assert _plan_status(struct_size=v3 - 4) == 1
 
 
 def test_oversized_rejected():
