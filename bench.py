@@ -495,6 +495,56 @@ def bench_c2_interleaved(W, X, steps):
                          "frac": round(tops / PEAK_F16_TFLOPS, 4)}}
 
 
+def bench_c2_bf16(W, X, steps, samples):
+    """The radio-astronomy product with bfloat16 operands (the same weights
+    and data rounded to bfloat16 on the device; weights repacked once into the
+    receiver-blocked layout), timed against the fp16 product in alternating
+    rounds; sampled outputs go to the CPU leg's accuracy check."""
+    import torch
+    import paper_2505_03269_amd as tcbf
+    import workloads as wl
+    cfg = wl.WORKLOADS["radio-astro-fp16"]
+    shape = (cfg["batch"], cfg["M"], cfg["N"], cfg["K"])
+    A16 = torch.from_numpy(W).to("cuda:0")
+    Ab16 = tcbf.block_weights(A16)
+    Abf = tcbf.block_weights(A16.to(torch.bfloat16))
+    del A16
+    B16 = torch.from_numpy(X).to("cuda:0")
+    Bbf = B16.to(torch.bfloat16)
+    pb = tcbf.Plan(*shape, tcbf.BF16, a_layout=tcbf.BLOCKED)
+    ph = tcbf.Plan(*shape, tcbf.F16, a_layout=tcbf.BLOCKED)
+    info = pb.info()
+    Cb, Ch = pb.empty_output(), ph.empty_output()
+    ms_b, ms_h = time_interleaved([lambda: pb.execute(Abf, Bbf, Cb), lambda: ph.execute(Ab16, B16, Ch)],
+                                  max(steps // 2, 5), 2)
+    # channel 0, beams 0..63: the GPU rows and the bfloat16-rounded inputs
+    rows = 64
+    samples["bf16"] = {"W": torch.from_numpy(W[0, :, :rows]).to(torch.bfloat16).float().numpy(),
+                       "X": Bbf[0].float().cpu().numpy(), "C": Cb[0, :, :rows].cpu().numpy()}
+    ops = info["useful_ops"]
+    tops = ops / (ms_b * 1e-3) / 1e12
+    del Ab16, Abf, B16, Bbf, Cb, Ch
+    torch.cuda.empty_cache()
+    return {"workload": "radio-astro-bf16: batch=256 M=1024 K=576 N=4096", "kernel": info["kernel_name"],
+            "variant": info["variant"], "value": round(tops, 1), "unit": "TeraOps/s", "ms_per_launch": round(ms_b, 4),
+            "dtype": "bf16", "layout": "W receiver-blocked (repacked once), X planar; the fp16 inputs rounded to bfloat16",
+            "f16_tops": round(ops / (ms_h * 1e-3) / 1e12, 1),
+            "roofline": {"bound": "mfma", "achieved": round(tops, 1), "peak": PEAK_F16_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(tops / PEAK_F16_TFLOPS, 4), "peak_is": "bf16 dense matrix peak (same as fp16)"}}
+
+
+def cpu_leg_bf16(sample):
+    """Accuracy of the bfloat16 line: the FP64 oracle on the bfloat16-rounded
+    inputs (64 beams of channel 0, every sample) against the GPU rows."""
+    import oracle
+    Wz = sample["W"][0].astype(np.float64) + 1j * sample["W"][1].astype(np.float64)
+    Xz = sample["X"][0].astype(np.float64) + 1j * sample["X"][1].astype(np.float64)
+    ref = oracle.cgemm(Wz[None], Xz[None])[0]
+    e = rel_fro(planar_out(sample["C"]), ref)
+    return {"value": e, "tolerance": TOL_F16, "pass": e <= TOL_F16, "entries": int(ref.size),
+            "against": "FP64 oracle on the same bfloat16 inputs (channel 0, beams 0-63)"}
+
+
 def bench_c1_latency(samples, launches=200):
     """The small plain-fp16 case (4 x 128 x 64 x 512): one launch is far too
     short to fill the GPU, so what counts is latency.  Per launch: eager
@@ -1040,6 +1090,7 @@ def main():
     roofline["target_met"] = bool(roofline["frac"] >= TARGET_FRAC_F16)
     samples = {}
     il_line = None if args.no_secondary else bench_c2_interleaved(W, X, args.steps)
+    bf_line = None if args.no_secondary else bench_c2_bf16(W, X, args.steps, samples)
     secondary = [] if args.no_secondary else bench_secondary(
         args.steps, samples, serving=not args.no_serving, copy_gbs=probes["hbm_copy"]["gbs"],
         valu_peak=probes["valu_xor_popc"]["uniform"]["tops"])
@@ -1061,9 +1112,13 @@ def main():
             for key, i in c4["lines"].items():
                 if key in acc:
                     secondary[i]["accuracy"] = acc[key]
+        if "bf16" in samples and bf_line is not None:
+            bf_line["accuracy"] = cpu_leg_bf16(samples["bf16"])
     del W, X, C_head
+    if bf_line is not None:
+        secondary.insert(0, bf_line)  # after the CPU legs, which address lines by index
     if il_line is not None:
-        secondary.insert(0, il_line)  # after the CPU legs, which address lines by index
+        secondary.insert(0, il_line)
     line = {
         "metric": METRIC, "value": round(tops, 2), "unit": "TeraOps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),

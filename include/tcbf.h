@@ -53,7 +53,10 @@ typedef enum tcbf_dtype {
     TCBF_F16 = 0,       /* fp16 in, fp32 accumulate, fp32 complex out            */
     TCBF_INT1 = 1,      /* packed sign bits in, exact int32 complex out          */
     TCBF_F8_E4M3 = 2,   /* e4m3 in with one fp32 scale per row, fp32 out         */
-    TCBF_MXF8_E4M3 = 3  /* e4m3 in with an E8M0 scale per 32-receiver block       */
+    TCBF_MXF8_E4M3 = 3, /* e4m3 in with an E8M0 scale per 32-receiver block       */
+    TCBF_BF16 = 4       /* bfloat16 in, fp32 accumulate, fp32 complex out; the
+                           fp16 layouts (blocked W included), variants 1, 2 and
+                           9 (9 with planar X), not in grouped launches          */
 } tcbf_dtype;
 
 /* Complex storage.  PLANAR keeps a real plane then an imaginary plane for each
@@ -215,13 +218,15 @@ tcbf_status tcbf_execute(tcbf_plan_t plan, const void *A, const void *B, void *C
                          const void *a_scale, const void *b_scale, void *stream);
 
 /*
- * tcbf_block_weights -- repack fp16 weights into the TCBF_BLOCKED layout
+ * tcbf_block_weights -- repack 16-bit weights (fp16 or bfloat16: values are
+ * moved, never interpreted) into the TCBF_BLOCKED layout
  * (Sec. III: the library's transpose kernel tiles the inputs in device memory;
  * here, the receiver axis of W in blocks of 32).
- *   src (device): fp16 W, planar [batch][2][M][K] (src_layout TCBF_PLANAR) or
+ *   src (device): W, planar [batch][2][M][K] (src_layout TCBF_PLANAR) or
  *                 interleaved [batch][M][K][2] (TCBF_INTERLEAVED).
- *   dst (device): fp16 [batch][2][ceil(K/32)][M][32]; receivers k >= K are
- *                 written as +0.  Values are copied bit for bit.
+ *   dst (device): [batch][2][ceil(K/32)][M][32]; receivers k >= K are
+ *                 written as +0 (bits 0, in both formats).  Values are copied
+ *                 bit for bit.
  * src and dst must be 16-byte aligned device pointers that do not overlap.
  * Asynchronous on `stream`, allocation-free.  TCBF_ERROR_INVALID_VALUE for
  * NULL or misaligned pointers, sizes below 1 or a src_layout other than

@@ -12,7 +12,7 @@ import ctypes
 import os
 
 __all__ = [
-    "F16", "INT1", "F8_E4M3", "MXF8_E4M3", "PLANAR", "INTERLEAVED", "BLOCKED", "SRC_I8", "SRC_F16", "SRC_F32",
+    "F16", "INT1", "F8_E4M3", "MXF8_E4M3", "BF16", "PLANAR", "INTERLEAVED", "BLOCKED", "SRC_I8", "SRC_F16", "SRC_F32",
     "TcbfError", "Plan", "block_weights", "blocked_shape", "f8_codes_shape", "pack1bit", "quantize_e4m3", "steering_weights", "group_execute", "group_execute_noalloc", "peak_probe", "f8_kp", "mx_scale_pitch", "mx_scales_to_rows",
     "mx_scales_from_rows", "lib",
     "status_string", "EXPORTS", "GROUP_MAX", "GROUP_WORKSPACE_BYTES", "GROUP_SCRATCH_BYTES",
@@ -21,7 +21,7 @@ __all__ = [
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtcbf.so")
 
-F16, INT1, F8_E4M3, MXF8_E4M3 = 0, 1, 2, 3
+F16, INT1, F8_E4M3, MXF8_E4M3, BF16 = 0, 1, 2, 3, 4
 PLANAR, INTERLEAVED, BLOCKED = 0, 1, 2
 SRC_I8, SRC_F16, SRC_F32 = 0, 1, 2
 
@@ -212,7 +212,7 @@ class Plan:
         self.dtype, self.a_layout, self.b_layout, self.c_layout = dtype, a_layout, b_layout, c_layout
         self.a_shared = bool(a_shared)
         self.device = int(device)
-        self.b_k_contiguous = bool(b_k_contiguous) and dtype == F16
+        self.b_k_contiguous = bool(b_k_contiguous) and dtype in (F16, BF16)
         self.a_batch_stride = int(a_batch_stride)
 
     def __del__(self):
@@ -265,6 +265,8 @@ class Plan:
             return torch.int32, torch.int32, torch.int32  # packed words viewed as int32
         if _is_f8(self.dtype):
             return torch.uint8, torch.uint8, torch.float32  # e4m3 codes
+        if self.dtype == BF16:
+            return torch.bfloat16, torch.bfloat16, torch.float32
         return torch.float16, torch.float16, torch.float32
 
     def empty_output(self):
@@ -304,12 +306,13 @@ def blocked_shape(batch, M, K):
 
 
 def block_weights(W, layout=PLANAR, out=None, stream=None):
-    """Repack fp16 weights (planar [batch, 2, M, K] or interleaved
-    [batch, M, K, 2]) into the receiver-blocked layout (tcbf_block_weights);
-    returns (or fills) float16 [batch, 2, ceil(K/32), M, 32], zero past K."""
+    """Repack 16-bit weights (fp16 or bfloat16; planar [batch, 2, M, K] or
+    interleaved [batch, M, K, 2]) into the receiver-blocked layout
+    (tcbf_block_weights, which moves 16-bit values without reading them);
+    returns (or fills) [batch, 2, ceil(K/32), M, 32] of W's dtype, zero past K."""
     import torch
-    if W.dtype != torch.float16 or W.dim() != 4:
-        raise ValueError("W must be a 4-d float16 tensor")
+    if W.dtype not in (torch.float16, torch.bfloat16) or W.dim() != 4:
+        raise ValueError("W must be a 4-d float16 or bfloat16 tensor")
     if layout == PLANAR:
         if W.shape[1] != 2:
             raise ValueError("planar W needs a plane axis of 2")
@@ -322,9 +325,9 @@ def block_weights(W, layout=PLANAR, out=None, stream=None):
         raise ValueError("source layout must be PLANAR or INTERLEAVED")
     shape = blocked_shape(batch, M, K)
     if out is None:
-        out = torch.empty(shape, dtype=torch.float16, device=W.device)
-    if tuple(out.shape) != shape or out.dtype != torch.float16:
-        raise ValueError("out must be float16 %s" % (shape,))
+        out = torch.empty(shape, dtype=W.dtype, device=W.device)
+    if tuple(out.shape) != shape or out.dtype != W.dtype:
+        raise ValueError("out must be %s %s" % (W.dtype, shape))
     _check(lib().tcbf_block_weights(_dev_ptr(W, "W"), int(layout), int(batch), int(M), int(K),
                                     _dev_ptr(out, "out"), _stream_handle(stream)), "tcbf_block_weights")
     return out

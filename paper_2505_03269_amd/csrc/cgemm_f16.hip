@@ -56,10 +56,24 @@ __device__ __forceinline__ half8 negate(half8 v) {
     return __builtin_bit_cast(half8, u);
 }
 
+// The 32 x 32 x 16 matrix instruction on 16-bit operands held as raw 16-bit
+// patterns: fp16 (BF = 0) or bfloat16 (BF = 1).  Loads, LDS staging and the
+// sign flip of negate() are the same for both formats (bit 15 is the sign).
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+template <int BF>
+__device__ __forceinline__ f32x16 mfma16(const half8 &a, const half8 &b, const f32x16 &c) {
+    if constexpr (BF)
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b),
+                                                       c, 0, 0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0);
+}
+
 // One 16-receiver step.  w*: W fragments (lane l: beam l%32, receivers
 // 8*(l/32) + 0..7); x*: X fragments (lane l: sample l%32, same receivers).
 // X is the matrix unit's first operand, so the result comes out transposed
 // (samples along the accumulator's row index).
+template <int BF = 0>
 __device__ __forceinline__ void mma_step(Acc &a, const half8 (&wr)[2], const half8 (&wi)[2],
                                          const half8 (&xr)[2], const half8 (&xi)[2]) {
     half8 wn[2] = {negate(wi[0]), negate(wi[1])};
@@ -67,10 +81,10 @@ __device__ __forceinline__ void mma_step(Acc &a, const half8 (&wr)[2], const hal
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-            a.re[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(xr[j], wr[i], a.re[i][j], 0, 0, 0);
-            a.im[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(xi[j], wr[i], a.im[i][j], 0, 0, 0);
-            a.re[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(xi[j], wn[i], a.re[i][j], 0, 0, 0);
-            a.im[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(xr[j], wi[i], a.im[i][j], 0, 0, 0);
+            a.re[i][j] = mfma16<BF>(xr[j], wr[i], a.re[i][j]);
+            a.im[i][j] = mfma16<BF>(xi[j], wr[i], a.im[i][j]);
+            a.re[i][j] = mfma16<BF>(xi[j], wn[i], a.re[i][j]);
+            a.im[i][j] = mfma16<BF>(xr[j], wi[i], a.im[i][j]);
         }
 }
 
@@ -324,7 +338,7 @@ __device__ __forceinline__ void store4(float *C, int64_t c, int64_t M, int64_t N
     }
 }
 
-template <int AIL, int BIL, int CIL>
+template <int AIL, int BIL, int CIL, int BF = 0>
 __global__ __launch_bounds__(NT, 2) void cgemm_f16_kernel(
     const uint16_t *__restrict__ A, const uint16_t *__restrict__ B, float *__restrict__ C,
     int64_t M, int64_t N, int64_t K, int64_t a_stride, int tiles_m, int tiles_n, int64_t nblocks,
@@ -386,7 +400,7 @@ __global__ __launch_bounds__(NT, 2) void cgemm_f16_kernel(
                 xr[j] = lds_frag(st + 2 * PLANE_A, col, ch);
                 xi[j] = lds_frag(st + 2 * PLANE_A + PLANE_B, col, ch);
             }
-            mma_step(acc, wr, wi, xr, xi);
+            mma_step<BF>(acc, wr, wi, xr, xi);
         }
         if (more) {
             uint16_t *nx = lds + ((kt + 1) & 1) * STAGE;
@@ -468,7 +482,7 @@ template <int WM, int BK, int NS> struct FastLds {
 // 32 receivers, each block all M beams x 32 receivers), so a stage's W tile
 // is one contiguous run per plane and every load instruction reads whole
 // cache lines; with planar W each beam row contributes a 64-byte piece.
-template <int WM, int BK, int NS, int CIL, int AB>
+template <int WM, int BK, int NS, int CIL, int AB, int BF = 0>
 __device__ __forceinline__ void fast_tile(const uint16_t *__restrict__ A, const uint16_t *__restrict__ B,
                                           float *__restrict__ C, int M, int N, int K, int64_t a_stride, int c,
                                           int tm, int tn, char *lds0, char *lds1, char *lds2, char *lds3,
@@ -593,7 +607,7 @@ __device__ __forceinline__ void fast_tile(const uint16_t *__restrict__ A, const 
                 xr[j] = tr_frag(st, o, o + 4 * 256);
                 xi[j] = tr_frag(st, o + BK * BN * 2, o + BK * BN * 2 + 4 * 256);
             }
-            mma_step(acc, wr, wi, xr, xi);
+            mma_step<BF>(acc, wr, wi, xr, xi);
             // keep one step's fragments live at a time (two workgroups per CU
             // leave 256 registers per lane)
             __builtin_amdgcn_sched_barrier(0);
@@ -651,7 +665,7 @@ __device__ __forceinline__ void fast_tile(const uint16_t *__restrict__ A, const 
     store_tile_staged<WM, CIL>(acc, row_ptr, C + (int64_t)c * 2 * M * N, M, N, m0, n0, wave, lane);
 }
 
-template <int WM, int BK, int NS, int CIL, int AB>
+template <int WM, int BK, int NS, int CIL, int AB, int BF = 0>
 __global__ __launch_bounds__(128 * WM, WM == 2 ? 2 : 1) void cgemm_f16_fast_kernel(
     const uint16_t *__restrict__ A, const uint16_t *__restrict__ B, float *__restrict__ C,
     int M, int N, int K, int64_t a_stride, int tiles_m, int tiles_n, int nblocks) {
@@ -662,7 +676,7 @@ __global__ __launch_bounds__(128 * WM, WM == 2 ? 2 : 1) void cgemm_f16_fast_kern
     const int rem = t - c * per_c;
     int tm, tn;
     tile_coords(rem, tiles_m, tiles_n, tm, tn);
-    fast_tile<WM, BK, NS, CIL, AB>(A, B, C, M, N, K, a_stride, c, tm, tn, lds0, lds1, lds2, lds3, lds4, lds5);
+    fast_tile<WM, BK, NS, CIL, AB, BF>(A, B, C, M, N, K, a_stride, c, tm, tn, lds0, lds1, lds2, lds3, lds4, lds5);
 }
 
 // ===========================================================================
@@ -914,6 +928,7 @@ __global__ __launch_bounds__(256, 2) void cgemm_f16_split_kernel(const uint16_t 
 // the same order per accumulator as mma_step: Re gets Wr.Xr, then (-Wi).Xi;
 // Im gets Wr.Xi, then Wi.Xr).  Element r of lane l of a 32 x 32 sub-tile
 // holds sample l%32 of beam 8*(r/4) + 4*(l/32) + r%4.
+template <int BF = 0>
 __device__ __forceinline__ void mma_step_wx(Acc &a, const half8 (&wr)[2], const half8 (&wi)[2],
                                             const half8 (&xr)[2], const half8 (&xi)[2]) {
     half8 wn[2] = {negate(wi[0]), negate(wi[1])};
@@ -921,10 +936,10 @@ __device__ __forceinline__ void mma_step_wx(Acc &a, const half8 (&wr)[2], const 
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-            a.re[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(wr[i], xr[j], a.re[i][j], 0, 0, 0);
-            a.im[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(wr[i], xi[j], a.im[i][j], 0, 0, 0);
-            a.re[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(wn[i], xi[j], a.re[i][j], 0, 0, 0);
-            a.im[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(wi[i], xr[j], a.im[i][j], 0, 0, 0);
+            a.re[i][j] = mfma16<BF>(wr[i], xr[j], a.re[i][j]);
+            a.im[i][j] = mfma16<BF>(wr[i], xi[j], a.im[i][j]);
+            a.re[i][j] = mfma16<BF>(wn[i], xi[j], a.re[i][j]);
+            a.im[i][j] = mfma16<BF>(wi[i], xr[j], a.im[i][j]);
         }
 }
 
@@ -1074,12 +1089,13 @@ __device__ __forceinline__ void store_block_wx_il(const f32x16 (&a)[2][4], float
         }
 }
 
-template <int CIL, int AB, int BIL>
+template <int CIL, int AB, int BIL, int BF = 0>
 __global__ __launch_bounds__(512, 1) void cgemm_f16_pp_kernel(const uint16_t *__restrict__ A,
                                                               const uint16_t *__restrict__ B,
                                                               float *__restrict__ C, int M, int N, int K,
                                                               int64_t a_stride, int tiles_m, int tiles_n,
                                                               int total_tiles) {
+    static_assert(!(BIL && BF), "interleaved data: fp16 products only");
     typedef FastGeo<4, 32> G;
     constexpr int TM = G::TM, NW = G::NW;
     __shared__ __attribute__((aligned(1024))) char lds0[G::STAGE];
@@ -1314,8 +1330,8 @@ __global__ __launch_bounds__(512, 1) void cgemm_f16_pp_kernel(const uint16_t *__
             mma_step_wx_il(ail, wr[0], wi[0], xc[0], neg_even);
             mma_step_wx_il(ail, wr[1], wi[1], xc[1], neg_even);
         } else {
-            mma_step_wx(acc, wr[0], wi[0], xr[0], xi[0]);
-            mma_step_wx(acc, wr[1], wi[1], xr[1], xi[1]);
+            mma_step_wx<BF>(acc, wr[0], wi[0], xr[0], xi[0]);
+            mma_step_wx<BF>(acc, wr[1], wi[1], xr[1], xi[1]);
         }
         if (++c_kt == nk) {
             c_kt = 0;
@@ -1641,16 +1657,19 @@ typedef void (*KernFn)(const uint16_t *, const uint16_t *, float *, int64_t, int
 typedef void (*FastFn)(const uint16_t *, const uint16_t *, float *, int, int, int, int64_t, int, int, int);
 
 // bil: 0 planar, 1 interleaved, 2 planar receiver-contiguous, 3 interleaved
-// receiver-contiguous
-KernFn pick(int ail, int bil, int cil) {
+// receiver-contiguous; bf: bfloat16 operands
+template <int BF> KernFn pick_of(int ail, int bil, int cil) {
     static const KernFn table[16] = {
-        cgemm_f16_kernel<0, 0, 0>, cgemm_f16_kernel<0, 0, 1>, cgemm_f16_kernel<0, 1, 0>, cgemm_f16_kernel<0, 1, 1>,
-        cgemm_f16_kernel<0, 2, 0>, cgemm_f16_kernel<0, 2, 1>, cgemm_f16_kernel<0, 3, 0>, cgemm_f16_kernel<0, 3, 1>,
-        cgemm_f16_kernel<1, 0, 0>, cgemm_f16_kernel<1, 0, 1>, cgemm_f16_kernel<1, 1, 0>, cgemm_f16_kernel<1, 1, 1>,
-        cgemm_f16_kernel<1, 2, 0>, cgemm_f16_kernel<1, 2, 1>, cgemm_f16_kernel<1, 3, 0>, cgemm_f16_kernel<1, 3, 1>,
+        cgemm_f16_kernel<0, 0, 0, BF>, cgemm_f16_kernel<0, 0, 1, BF>, cgemm_f16_kernel<0, 1, 0, BF>,
+        cgemm_f16_kernel<0, 1, 1, BF>, cgemm_f16_kernel<0, 2, 0, BF>, cgemm_f16_kernel<0, 2, 1, BF>,
+        cgemm_f16_kernel<0, 3, 0, BF>, cgemm_f16_kernel<0, 3, 1, BF>, cgemm_f16_kernel<1, 0, 0, BF>,
+        cgemm_f16_kernel<1, 0, 1, BF>, cgemm_f16_kernel<1, 1, 0, BF>, cgemm_f16_kernel<1, 1, 1, BF>,
+        cgemm_f16_kernel<1, 2, 0, BF>, cgemm_f16_kernel<1, 2, 1, BF>, cgemm_f16_kernel<1, 3, 0, BF>,
+        cgemm_f16_kernel<1, 3, 1, BF>,
     };
     return table[(ail << 3) | (bil << 1) | cil];
 }
+KernFn pick(int ail, int bil, int cil, bool bf) { return bf ? pick_of<1>(ail, bil, cil) : pick_of<0>(ail, bil, cil); }
 
 // Fast-kernel configurations (variant: beam waves WM, receivers per stage,
 // ring depth):  2: 2, 32, 2   3: 2, 16, 4   4: 2, 16, 5   5: 2, 32, 3
@@ -1740,7 +1759,7 @@ static int device_cus(int device) {
 // least a 256 x 128 tile for every compute unit (it runs one workgroup per
 // CU and measured 4-13% faster than variant 2 on such shapes), variant 2 for
 // smaller problems, the generic kernel where the fast ones do not apply.
-static int default_variant(const Problem &p) {
+static int default_variant_f16(const Problem &p) {
     if (p.b_kmajor) return 1;  // receiver-contiguous X: the generic kernel
     const int64_t tiles = p.batch * ((p.M + 255) / 256) * ((p.N + BN - 1) / BN);
     const bool big = tiles >= device_cus(p.device) && tiles * ((p.K + 31) / 32) < ((int64_t)1 << 31);
@@ -1754,11 +1773,22 @@ static int default_variant(const Problem &p) {
     return big ? kPingPong : kDefaultFast;
 }
 
+// bfloat16 operands run in variants 1, 2 and 9 (planar X for 9).
+static bool bf16_variant(const Problem &p, int v) {
+    return v == 1 || v == 2 || (v == kPingPong && p.b_layout == TCBF_PLANAR);
+}
+
+static int default_variant(const Problem &p) {
+    const int v = default_variant_f16(p);
+    return !p.bf16 || bf16_variant(p, v) ? v : 1;
+}
+
 bool f16_select(const Problem &p, int forced_variant, F16Config *cfg) {
     const bool ab = p.a_layout == TCBF_BLOCKED;
     int v = forced_variant;
     if (v == 0) v = default_variant(p);
     if (v < 1 || v >= kFirstFast + kNumFast) return false;
+    if (p.bf16 && !bf16_variant(p, v)) return false;
     if (v >= kFirstFast && !(v == kPingPong ? pp_ok(p) : fast_ok(p))) return false;
     if (ab && !reads_blocked(v)) return false;
     if (v == kPingPong) {
@@ -1803,7 +1833,9 @@ hipError_t f16_launch(const Problem &p, const F16Config &cfg, const void *A, con
                                      cgemm_f16_pp_kernel<0, 1, 0>, cgemm_f16_pp_kernel<0, 1, 1>,
                                      cgemm_f16_pp_kernel<1, 0, 0>, cgemm_f16_pp_kernel<1, 0, 1>,
                                      cgemm_f16_pp_kernel<1, 1, 0>, cgemm_f16_pp_kernel<1, 1, 1>};
-        const FastFn fn = pp[(cil << 2) | (ab << 1) | (p.b_layout == TCBF_INTERLEAVED)];
+        static const FastFn pp_bf[4] = {cgemm_f16_pp_kernel<0, 0, 0, 1>, cgemm_f16_pp_kernel<0, 1, 0, 1>,
+                                        cgemm_f16_pp_kernel<1, 0, 0, 1>, cgemm_f16_pp_kernel<1, 1, 0, 1>};
+        const FastFn fn = p.bf16 ? pp_bf[(cil << 1) | ab] : pp[(cil << 2) | (ab << 1) | (p.b_layout == TCBF_INTERLEAVED)];
         const int grid = (int)std::min<int64_t>(nblocks, device_cus(p.device));
         hipLaunchKernelGGL(fn, dim3((uint32_t)grid), dim3(cfg.threads), 0, stream, (const uint16_t *)A,
                            (const uint16_t *)B, (float *)C, (int)p.M, (int)p.N, (int)p.K, p.a_stride, tiles_m,
@@ -1811,14 +1843,17 @@ hipError_t f16_launch(const Problem &p, const F16Config &cfg, const void *A, con
         return hipGetLastError();
     }
     if (cfg.variant >= kFirstFast) {
-        FastFn fn = fast_fn(cfg.variant, p.c_layout == TCBF_INTERLEAVED, p.a_layout == TCBF_BLOCKED);
+        const bool cil = p.c_layout == TCBF_INTERLEAVED, ab = p.a_layout == TCBF_BLOCKED;
+        static const FastFn v2_bf[4] = {cgemm_f16_fast_kernel<2, 32, 2, 0, 0, 1>, cgemm_f16_fast_kernel<2, 32, 2, 0, 1, 1>,
+                                        cgemm_f16_fast_kernel<2, 32, 2, 1, 0, 1>, cgemm_f16_fast_kernel<2, 32, 2, 1, 1, 1>};
+        FastFn fn = p.bf16 ? v2_bf[(cil << 1) | ab] : fast_fn(cfg.variant, cil, ab);
         hipLaunchKernelGGL(fn, dim3((uint32_t)nblocks), dim3(cfg.threads), 0, stream, (const uint16_t *)A,
                            (const uint16_t *)B, (float *)C, (int)p.M, (int)p.N, (int)p.K, p.a_stride,
                            tiles_m, tiles_n, (int)nblocks);
         return hipGetLastError();
     }
     KernFn fn = pick(p.a_layout == TCBF_INTERLEAVED, (p.b_layout == TCBF_INTERLEAVED) + 2 * (p.b_kmajor != 0),
-                     p.c_layout == TCBF_INTERLEAVED);
+                     p.c_layout == TCBF_INTERLEAVED, p.bf16 != 0);
     hipLaunchKernelGGL(fn, dim3((uint32_t)nblocks), dim3(NT), 0, stream,
                        (const uint16_t *)A, (const uint16_t *)B, (float *)C, p.M, p.N, p.K,
                        p.a_stride, tiles_m, tiles_n, nblocks, (int)cfg.a_vec, (int)cfg.b_vec);

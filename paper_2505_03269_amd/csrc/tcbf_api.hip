@@ -22,7 +22,7 @@ struct tcbf_plan_s {
 
 namespace tcbf {
 int64_t w_entry_elems(int dtype, int a_layout, int64_t M, int64_t K) {
-    if (dtype == TCBF_F16) return 2 * M * (a_layout == TCBF_BLOCKED ? (K + 31) / 32 * 32 : K);
+    if (dtype == TCBF_F16 || dtype == TCBF_BF16) return 2 * M * (a_layout == TCBF_BLOCKED ? (K + 31) / 32 * 32 : K);
     if (dtype == TCBF_INT1) return 2 * M * ((K + 31) / 32);
     const int64_t kp = f8_kp(K);
     return 2 * M * (a_layout == TCBF_BLOCKED ? (kp + 63) / 64 * 64 : kp);
@@ -41,6 +41,8 @@ bool is_layout(int32_t v) { return v == TCBF_PLANAR || v == TCBF_INTERLEAVED; }
 bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 bool aligned8(const void *p) { return ((uintptr_t)p & 7u) == 0; }
 bool is_f8(int32_t dtype) { return dtype == TCBF_F8_E4M3 || dtype == TCBF_MXF8_E4M3; }
+// 16-bit float operands (fp16 or bfloat16): the same layouts and kernels
+bool is_f16like(int32_t dtype) { return dtype == TCBF_F16 || dtype == TCBF_BF16; }
 bool is_src_type(int32_t t) { return t == TCBF_SRC_I8 || t == TCBF_SRC_F16 || t == TCBF_SRC_F32; }
 
 // Architecture check per device, remembered once it succeeded (plans are
@@ -87,7 +89,7 @@ tcbf_plan_desc full_desc(const tcbf_plan_desc *d) {
 }
 
 // Bytes of one element of W's storage type.
-int64_t w_elem_bytes(int32_t dtype) { return dtype == TCBF_F16 ? 2 : dtype == TCBF_INT1 ? 4 : 1; }
+int64_t w_elem_bytes(int32_t dtype) { return is_f16like(dtype) ? 2 : dtype == TCBF_INT1 ? 4 : 1; }
 
 // Validate a descriptor without touching the HIP runtime.
 tcbf_status validate_desc(const tcbf_plan_desc *dd) {
@@ -98,7 +100,7 @@ tcbf_status validate_desc(const tcbf_plan_desc *dd) {
     if (d->a_batch_stride < 0 || (d->a_batch_stride > 0 && d->a_shared != 0)) return TCBF_ERROR_INVALID_VALUE;
     if (d->batch < 1 || d->M < 1 || d->N < 1 || d->K < 1) return TCBF_ERROR_INVALID_VALUE;
     // the receiver-blocked layout: fp16 weights (A), or both FP8 operands
-    const bool a_ok = is_layout(d->a_layout) || (d->a_layout == TCBF_BLOCKED && (d->dtype == TCBF_F16 || is_f8(d->dtype)));
+    const bool a_ok = is_layout(d->a_layout) || (d->a_layout == TCBF_BLOCKED && (is_f16like(d->dtype) || is_f8(d->dtype)));
     const bool b_ok = is_layout(d->b_layout) || (d->b_layout == TCBF_BLOCKED && is_f8(d->dtype));
     if (!a_ok || !b_ok || !is_layout(d->c_layout)) return TCBF_ERROR_INVALID_VALUE;
     if (d->variant < 0) return TCBF_ERROR_INVALID_VALUE;
@@ -106,13 +108,13 @@ tcbf_status validate_desc(const tcbf_plan_desc *dd) {
         // at least one entry, whole 16-byte units, and every entry's start
         // representable
         const int64_t eb = w_elem_bytes(d->dtype);
-        if (d->dtype != TCBF_F16 && d->dtype != TCBF_INT1 && !is_f8(d->dtype)) return TCBF_ERROR_INVALID_VALUE;
+        if (!is_f16like(d->dtype) && d->dtype != TCBF_INT1 && !is_f8(d->dtype)) return TCBF_ERROR_INVALID_VALUE;
         if (d->a_batch_stride < tcbf::w_entry_elems(d->dtype, d->a_layout, d->M, d->K)) return TCBF_ERROR_INVALID_VALUE;
         if ((d->a_batch_stride * eb) % 16 != 0) return TCBF_ERROR_INVALID_VALUE;
         if (d->a_batch_stride > ((int64_t)1 << 60) / d->batch / eb) return TCBF_ERROR_NOT_SUPPORTED;
     }
-    if (d->b_k_contiguous != 0 && d->dtype == TCBF_F16 && !is_layout(d->b_layout)) return TCBF_ERROR_INVALID_VALUE;
-    if (d->dtype == TCBF_F16) {
+    if (d->b_k_contiguous != 0 && is_f16like(d->dtype) && !is_layout(d->b_layout)) return TCBF_ERROR_INVALID_VALUE;
+    if (is_f16like(d->dtype)) {
         // every per-channel plane must be indexable with 32-bit element counts
         const int64_t kw = d->a_layout == TCBF_BLOCKED ? (d->K + 31) / 32 * 32 : d->K;
         if (2 * d->M * kw >= kMaxIndex || 2 * d->K * d->N >= kMaxIndex || 2 * d->M * d->N >= kMaxIndex)
@@ -166,13 +168,13 @@ tcbf_status tcbf_plan(const tcbf_plan_desc *desc, tcbf_plan_t *plan) {
     const int64_t dense = tcbf::w_entry_elems(d.dtype, d.a_layout, d.M, d.K);
     tcbf::Problem p{d.batch, d.M, d.N, d.K, d.a_layout, d.b_layout, d.c_layout, d.a_shared != 0, d.device,
                     d.a_shared != 0 ? 0 : d.a_batch_stride > 0 ? d.a_batch_stride : dense,
-                    d.dtype == TCBF_F16 && d.b_k_contiguous != 0};
+                    is_f16like(d.dtype) && d.b_k_contiguous != 0, d.dtype == TCBF_BF16};
     tcbf_plan_s tmp;
     memset(&tmp, 0, sizeof(tmp));
     tmp.desc = d;
     tmp.prob = p;
     int64_t wgs = 0;
-    if (desc->dtype == TCBF_F16) {
+    if (is_f16like(desc->dtype)) {
         if (!tcbf::f16_select(p, desc->variant, &tmp.f16)) return TCBF_ERROR_INVALID_VALUE;
         wgs = tcbf::f16_workgroups(p, tmp.f16);
     } else if (is_f8(desc->dtype)) {
@@ -208,7 +210,7 @@ tcbf_status tcbf_plan_query(tcbf_plan_t plan, tcbf_plan_info *info) {
     const double cm = (double)p.batch * p.M * p.N * p.K;
     r.useful_ops = 8.0 * cm;
     const double nw = p.a_shared ? 1.0 : (double)p.batch;
-    if (plan->desc.dtype == TCBF_F16) {
+    if (is_f16like(plan->desc.dtype)) {
         r.variant = plan->f16.variant;
         r.tile_m = plan->f16.tile_m;
         r.tile_n = plan->f16.tile_n;
@@ -258,7 +260,7 @@ tcbf_status tcbf_execute(tcbf_plan_t plan, const void *A, const void *B, void *C
     tcbf_status st = current_device_is(plan->desc.device);
     if (st != TCBF_SUCCESS) return st;
     hipError_t e;
-    if (plan->desc.dtype == TCBF_F16) {
+    if (is_f16like(plan->desc.dtype)) {
         e = tcbf::f16_launch(plan->prob, plan->f16, A, B, C, (hipStream_t)stream);
     } else if (f8) {
         e = tcbf::f8_launch(plan->prob, plan->f8, plan->desc.dtype == TCBF_MXF8_E4M3, A, B, C, a_scale, b_scale,
@@ -407,7 +409,7 @@ tcbf_status group_execute(int32_t device, int32_t dtype, int32_t c_layout, const
         if (g.batch < 1 || g.M < 1 || g.N < 1 || g.K < 1) return TCBF_ERROR_INVALID_VALUE;
         probs[i] = tcbf::Problem{g.batch, g.M, g.N, g.K, layout, (blocked && is_f8(dtype)) ? TCBF_BLOCKED : TCBF_PLANAR,
                                  c_layout, g.a_shared != 0, device,
-                                 g.a_shared != 0 ? 0 : tcbf::w_entry_elems(dtype, layout, g.M, g.K), 0};
+                                 g.a_shared != 0 ? 0 : tcbf::w_entry_elems(dtype, layout, g.M, g.K), 0, 0};
         if (g.reserved != 0 || g.variant < 0) return TCBF_ERROR_INVALID_VALUE;
         variants[i] = 0;
         if (dtype == TCBF_F16) {

@@ -20,6 +20,7 @@ struct Problem {
     // entry (set by the API layer from the descriptor)
     int64_t a_stride;
     int b_kmajor;  // fp16 X receiver-contiguous ([N][K] per plane)
+    int bf16;      // 16-bit operands are bfloat16 (TCBF_BF16), not fp16
 };
 // W storage elements of one batch entry in the given layout.
 int64_t w_entry_elems(int dtype, int a_layout, int64_t M, int64_t K);

@@ -76,7 +76,10 @@ def _plan_status(**kw):
     dict(dtype=tcbf.INT1, variant=7),
     dict(dtype=tcbf.F8_E4M3, a_layout=tcbf.INTERLEAVED), dict(dtype=tcbf.MXF8_E4M3, b_layout=tcbf.INTERLEAVED),
     dict(dtype=tcbf.F8_E4M3, N=6), dict(dtype=tcbf.MXF8_E4M3, N=1), dict(dtype=tcbf.F8_E4M3, variant=3),
-    dict(dtype=4),
+    dict(dtype=5),
+    # bfloat16: variants 1, 2 and 9 only (9 with planar X), not in grouped launches
+    dict(dtype=tcbf.BF16, variant=3), dict(dtype=tcbf.BF16, variant=6), dict(dtype=tcbf.BF16, variant=8),
+    dict(dtype=tcbf.BF16, b_layout=tcbf.INTERLEAVED, variant=9), dict(dtype=tcbf.BF16, a_layout=tcbf.BLOCKED, variant=1),
     # receiver-contiguous X and strided W (descriptor fields of version 4)
     dict(reserved=1), dict(b_k_contiguous=2), dict(a_batch_stride=-8), dict(a_shared=1, a_batch_stride=1024),
     dict(a_batch_stride=8), dict(a_batch_stride=132), dict(b_k_contiguous=1, variant=2),
@@ -228,6 +231,7 @@ def test_group_argument_checks():
     assert L.tcbf_group_execute(0, tcbf.F16, 0, one, 0, p, None) == 1                  # count 0
     assert L.tcbf_group_execute(0, tcbf.F16, 0, one, tcbf.GROUP_MAX + 1, p, None) == 1
     assert L.tcbf_group_execute(0, 9, 0, one, 1, p, None) == 1                         # unknown dtype
+    assert L.tcbf_group_execute(0, tcbf.BF16, 0, one, 1, p, None) == 1                 # no grouped bfloat16
     int1 = dict(A=addr, B=addr, C=addr, batch=1, M=8, N=8, K=8, a_shared=0, layout=0)
     for bad, want in ((dict(a_scale=addr), 1), (dict(K=(1 << 26) + 1), 2), (dict(M=1 << 16, N=1 << 15), 2)):
         d = dict(int1)
