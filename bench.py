@@ -111,6 +111,37 @@ def time_launches(fn, steps, warmup):
     return start.elapsed_time(stop) / steps  # ms per launch
 
 
+def time_graph(fn, per_graph=20, replays=5):
+    """Milliseconds per call of `fn` captured `per_graph` times in one HIP
+    graph (on a side stream) and replayed: the device time without the host's
+    per-call enqueue cost.  Median over `replays` replays."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            for _ in range(per_graph):
+                fn()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    ms = []
+    stream = torch.cuda.current_stream()
+    for _ in range(replays):
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0.record(stream)
+        g.replay()
+        t1.record(stream)
+        torch.cuda.synchronize()
+        ms.append(t0.elapsed_time(t1) / per_graph)
+    del g
+    return float(np.median(ms))
+
+
 def time_interleaved(fns, steps, warmup, rounds=3):
     """Median ms per launch of each callable, timed in alternating rounds (so a
     clock swing during the measurement does not favour whichever goes first)."""
@@ -789,16 +820,35 @@ def bench_secondary(steps, samples, serving=True, copy_gbs=None, valu_peak=None)
              lambda: tcbf.group_execute(probs, workspace=ws, variants=tv),
              lambda: tcbf.group_execute(probs_b, workspace=ws, layout=tcbf.BLOCKED),
              lambda: tcbf.group_execute(probs_b, workspace=ws, layout=tcbf.BLOCKED, variants=tvb)], st, 1)
+        # the grouped call prepared once (table built at construction), and
+        # the grouped call and the separate launches replayed from HIP graphs
+        gc = tcbf.GroupCall(probs, workspace=ws)
+        ms_gp = time_launches(gc, st, 1)
+        ms_gg = time_graph(lambda: tcbf.group_execute(probs, workspace=ws))
+        ms_sg = time_graph(each)
         dflt = [tcbf.Plan(1, M, N, K, tcbf.F16).info()["variant"] for (M, N, K) in shapes]
         dflt_b = [tcbf.Plan(1, M, N, K, tcbf.F16, a_layout=tcbf.BLOCKED).info()["variant"] for (M, N, K) in shapes]
         del probs_b
-        tops = ops / (ms_g * 1e-3) / 1e12
+        # value: the prepared call (what a loop over the same buffers runs);
+        # group_execute, which checks the tuples and builds the table on
+        # every call, beside it
+        tops = ops / (ms_gp * 1e-3) / 1e12
         out.append({"workload": "grouped fp16: " + label,
                     "kernel": "cgemm_f16_group_kernel + cgemm_f16_pp_group_kernel", "value": round(tops, 1),
-                    "unit": "TeraOps/s", "ms_per_launch": round(ms_g, 4),
+                    "unit": "TeraOps/s", "ms_per_launch": round(ms_gp, 4),
+                    "group_execute_tops": round(ops / (ms_g * 1e-3) / 1e12, 1),
+                    "group_execute_ms": round(ms_g, 4),
                     "blocked_weights_tops": round(ops / (ms_gb * 1e-3) / 1e12, 1),
                     "separate_launches_tops": round(ops / (ms_s * 1e-3) / 1e12, 1),
                     "separate_launches_ms": round(ms_s, 4), "dtype": "f16",
+                    "prepared_call": {"ms_per_call": round(ms_gp, 4),
+                                      "tops": round(ops / (ms_gp * 1e-3) / 1e12, 1),
+                                      "note": "GroupCall: the problem table built once, each call passes it"},
+                    "graph_replay": {"ms_per_call": round(ms_gg, 4), "tops": round(ops / (ms_gg * 1e-3) / 1e12, 1),
+                                     "separate_launches_ms": round(ms_sg, 4),
+                                     "separate_launches_tops": round(ops / (ms_sg * 1e-3) / 1e12, 1),
+                                     "note": "the calls captured in a HIP graph and replayed: device time "
+                                             "without the host's per-call enqueue"},
                     "tuned": {"planar": {"default_tops": round(ops / (ms_d * 1e-3) / 1e12, 1),
                                          "tuned_tops": round(ops / (ms_t * 1e-3) / 1e12, 1),
                                          "policy": ent["policy"], "tuner_ms": ent["ms"],
@@ -828,11 +878,20 @@ def bench_secondary(steps, samples, serving=True, copy_gbs=None, valu_peak=None)
         for pl, (Wq, Xq, Cg, Ws, Xs) in zip(plans, probs):
             pl.execute(Wq, Xq, Cg, Ws, Xs)
     ms_s = time_launches(each8, st, 1)
-    tops = ops / (ms_g * 1e-3) / 1e12
+    gc = tcbf.GroupCall(probs, workspace=ws, dtype=tcbf.F8_E4M3)
+    ms_gp = time_launches(gc, st, 1)
+    ms_gg = time_graph(lambda: tcbf.group_execute(probs, workspace=ws, dtype=tcbf.F8_E4M3))
+    ms_sg = time_graph(each8)
+    tops = ops / (ms_gp * 1e-3) / 1e12
     out.append({"workload": "grouped fp8 per-row: 32 small jobs, M~U[128,512] N~U[256,1024] K~U[64,512]",
                 "kernel": "cgemm_f8_group_kernel", "value": round(tops, 1), "unit": "TeraOps/s",
-                "ms_per_launch": round(ms_g, 4), "separate_launches_tops": round(ops / (ms_s * 1e-3) / 1e12, 1),
+                "ms_per_launch": round(ms_gp, 4), "group_execute_tops": round(ops / (ms_g * 1e-3) / 1e12, 1),
+                "group_execute_ms": round(ms_g, 4), "separate_launches_tops": round(ops / (ms_s * 1e-3) / 1e12, 1),
                 "separate_launches_ms": round(ms_s, 4), "dtype": "e4m3",
+                "prepared_call": {"ms_per_call": round(ms_gp, 4), "tops": round(ops / (ms_gp * 1e-3) / 1e12, 1)},
+                "graph_replay": {"ms_per_call": round(ms_gg, 4), "tops": round(ops / (ms_gg * 1e-3) / 1e12, 1),
+                                 "separate_launches_ms": round(ms_sg, 4),
+                                 "separate_launches_tops": round(ops / (ms_sg * 1e-3) / 1e12, 1)},
                 "roofline": {"bound": "mfma", "achieved": round(tops, 1), "peak": PEAK_F8_TFLOPS,
                              "unit": "TFLOP/s", "frac": round(tops / PEAK_F8_TFLOPS, 4)}})
     del probs, plans

@@ -13,7 +13,7 @@ import os
 
 __all__ = [
     "F16", "INT1", "F8_E4M3", "MXF8_E4M3", "BF16", "PLANAR", "INTERLEAVED", "BLOCKED", "SRC_I8", "SRC_F16", "SRC_F32",
-    "TcbfError", "Plan", "block_weights", "blocked_shape", "f8_codes_shape", "pack1bit", "quantize_e4m3", "steering_weights", "group_execute", "group_execute_noalloc", "peak_probe", "f8_kp", "mx_scale_pitch", "mx_scales_to_rows",
+    "TcbfError", "Plan", "block_weights", "blocked_shape", "f8_codes_shape", "pack1bit", "quantize_e4m3", "steering_weights", "group_execute", "group_execute_noalloc", "GroupCall", "peak_probe", "f8_kp", "mx_scale_pitch", "mx_scales_to_rows",
     "mx_scales_from_rows", "lib",
     "status_string", "EXPORTS", "GROUP_MAX", "GROUP_WORKSPACE_BYTES", "GROUP_SCRATCH_BYTES",
 ]
@@ -524,6 +524,35 @@ def group_execute(problems, c_layout=PLANAR, workspace=None, device=0, stream=No
                                     _dev_ptr(workspace, "workspace"), _stream_handle(stream)),
            "tcbf_group_execute")
     return [pr[2] for pr in problems]
+
+
+class GroupCall:
+    """A grouped launch prepared once and issued many times: the problem
+    tuples are checked and the C problem table built at construction (the
+    same arguments as group_execute), so each call only passes the table, the
+    workspace and the stream to tcbf_group_execute.  For a serving or
+    streaming loop that runs the same buffers again and again; the tensors
+    are kept alive by the object."""
+
+    def __init__(self, problems, c_layout=PLANAR, workspace=None, device=0, dtype=F16, layout=PLANAR,
+                 variants=None):
+        import torch
+        self._arr = _group_table(problems, c_layout, dtype, layout, variants)
+        if workspace is None:
+            workspace = torch.empty(GROUP_WORKSPACE_BYTES, dtype=torch.uint8, device="cuda:%d" % device)
+        if workspace.numel() * workspace.element_size() < GROUP_WORKSPACE_BYTES:
+            raise ValueError("workspace too small")
+        self._ws = workspace
+        self._ws_ptr = _dev_ptr(workspace, "workspace")
+        self._problems = list(problems)
+        self._args = (int(device), int(dtype), int(c_layout))
+        self._fn = lib().tcbf_group_execute
+
+    def __call__(self, stream=None):
+        d, t, c = self._args
+        _check(self._fn(d, t, c, self._arr, len(self._problems), self._ws_ptr, _stream_handle(stream)),
+               "tcbf_group_execute")
+        return [pr[2] for pr in self._problems]
 
 
 def group_execute_noalloc(problems, c_layout=PLANAR, device=0, stream=None, dtype=F16, layout=PLANAR,

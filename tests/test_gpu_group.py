@@ -420,3 +420,26 @@ def test_group_rejects_variants_a_problem_cannot_take():
         tcbf.group_execute([(Wd, Xd, C)], variants=[1])            # the generic kernel is not grouped
     with pytest.raises(tcbf.TcbfError):
         tcbf.group_execute([(tcbf.block_weights(Wd), Xd, C)], layout=tcbf.BLOCKED, variants=[3])
+
+
+def test_prepared_group_call_equals_group_execute():
+    """GroupCall builds the problem table once; each call launches it again
+    and gives group_execute's results bit for bit, also after the inputs
+    change in place between calls."""
+    cases = [make(180 + i, b, M, N, K) for i, (b, M, N, K) in enumerate(MIX[:5])]
+    probs = [(c[2], c[3], c[4]) for c in cases]
+    call = tcbf.GroupCall(probs)
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(9)
+    for rep in range(3):
+        for c in cases:
+            c[4].fill_(float("nan"))
+        call()
+        torch.cuda.synchronize()
+        got = [c[4].clone() for c in cases]
+        tcbf.group_execute(probs)
+        torch.cuda.synchronize()
+        for g, c in zip(got, cases):
+            assert not torch.isnan(g).any() and torch.equal(g, c[4]), "call %d" % rep
+        for c in cases:
+            c[3].copy_(torch.randint(-127, 128, c[3].shape, device="cuda:0", generator=gen).half())
