@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 import workloads as wl
-from gpu_util import (c_inter_to_complex, c_planar_to_complex, check_fp_entries, check_fp_full, log,
+from gpu_util import (c_inter_to_complex, c_planar_to_complex, check_fp_entries, check_fp_full, gamma, log,
                       to_dev)
 
 pytestmark = pytest.mark.gpu
@@ -184,6 +184,41 @@ def test_c2_full_size_sampled():
     del A, B
     got, ref = _sampled_parity(W, X, C, cfg["K"])
     log("c2 sampled rel Frobenius %.3e" % (np.linalg.norm(got - ref) / np.linalg.norm(ref)))
+    _full_output_sums(W, X, C, cfg["K"])
+
+
+def _full_output_sums(W, X, C, K):
+    """Every output entry, through two exact identities: the sum of a beam's
+    row over all samples is W times the row sums of X, and the sum of a
+    sample's column over all beams is the column sums of W times X (FP64
+    oracle on the summed operands, which are exact in FP64).  The GPU sums
+    are taken in FP64 on the device; the bound is the per-element fp32 bound
+    summed over the row or column; a second, statistical gate takes 1e-6 of
+    the sum's scale sum |w||x| (the worst-case bound is about 1e-4 of it and
+    far from what rounding reaches: observed errors are below 1e-9 of the
+    scale), so one output entry off by more than about a tenth of its own
+    magnitude also shows.  Channel by channel on the host."""
+    bound_f = 2.0 * gamma(2 * K)
+    rows = C.sum(dim=3, dtype=torch.float64).cpu().numpy()       # [batch, 2, M]
+    cols = C.sum(dim=2, dtype=torch.float64).cpu().numpy()       # [batch, 2, N]
+    worst = {"row": 0.0, "column": 0.0}
+    for c in range(W.shape[0]):
+        Wc = W[c, 0].astype(np.float64) + 1j * W[c, 1].astype(np.float64)     # [M, K]
+        Xc = X[c, 0].astype(np.float64) + 1j * X[c, 1].astype(np.float64)     # [K, N]
+        aW, aX = np.abs(Wc), np.abs(Xc)
+        ref_r = oracle.cgemm(Wc[None], Xc.sum(axis=1)[None, :, None])[0, :, 0]
+        ref_c = oracle.cgemm(Wc.sum(axis=0)[None, None, :], Xc[None])[0, 0]
+        bnd_r = bound_f * (aW @ aX.sum(axis=1))
+        bnd_c = bound_f * (aW.sum(axis=0) @ aX)
+        for got, ref, bnd, what in ((rows[c], ref_r, bnd_r, "row"), (cols[c], ref_c, bnd_c, "column")):
+            err = np.maximum(np.abs(got[0] - ref.real), np.abs(got[1] - ref.imag))
+            bad = err > bnd + 1e-9
+            assert not bad.any(), "channel %d %s sums: %d outside the bound, worst %.3e vs %.3e" % (
+                c, what, int(bad.sum()), float(err[bad].max()), float(bnd[bad].max()))
+            scale = bnd / bound_f
+            assert np.all(err <= 1e-6 * scale), "channel %d %s sums beyond 1e-6 of their scale" % (c, what)
+            worst[what] = max(worst[what], float((err / scale).max()))
+    log("c2 full-output sums: worst error / sum |w||x| %s" % worst)
 
 
 def test_c4_full_size_sampled():
