@@ -417,14 +417,19 @@ typedef int i32x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16v __attribute__((ext_vector_type(16)));
 
 // Four dwords of e2m1 codes from one word: +1 (0x2) for a set bit, -1 (0xA)
-// for a clear one; code i of dword d takes bit 4i + d.
+// for a clear one; code i of dword d takes bit 4i + d.  Bit 3 of a code (the
+// sign) is the complement of its sample bit, so each dword is
+// (~(x << (3 - d)) & 0x88888888) | 0x22222222: one shift and one three-input
+// bit operation (truth table 0xAE = (~a & b) | c, indexed by the bits
+// (a, b, c) from the most significant).
 __device__ __forceinline__ i32x8 e2m1_expand(uint32_t x) {
-    const uint32_t n = ~x;  // bit 3 of a code is the sign: set for a clear bit
+    constexpr uint32_t kSign = 0x88888888u, kOne = 0x22222222u;
+    constexpr unsigned kNotAAndBOrC = 0xAE;
     i32x8 v;
-    v[0] = (int)(((n << 3) & 0x88888888u) | 0x22222222u);
-    v[1] = (int)(((n << 2) & 0x88888888u) | 0x22222222u);
-    v[2] = (int)(((n << 1) & 0x88888888u) | 0x22222222u);
-    v[3] = (int)((n & 0x88888888u) | 0x22222222u);
+    v[0] = (int)__builtin_amdgcn_bitop3_b32(x << 3, kSign, kOne, kNotAAndBOrC);
+    v[1] = (int)__builtin_amdgcn_bitop3_b32(x << 2, kSign, kOne, kNotAAndBOrC);
+    v[2] = (int)__builtin_amdgcn_bitop3_b32(x << 1, kSign, kOne, kNotAAndBOrC);
+    v[3] = (int)__builtin_amdgcn_bitop3_b32(x, kSign, kOne, kNotAAndBOrC);
     v[4] = v[5] = v[6] = v[7] = 0;
     return v;
 }
