@@ -7,6 +7,7 @@ shared library next to this file.
 """
 import concurrent.futures as cf
 import glob
+import hashlib
 import os
 import subprocess
 import sys
@@ -18,6 +19,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtcbf.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+# identity of the sources a library was built from, written beside it
+SOURCES_ID = os.path.join(HERE, "libtcbf.sources")
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
@@ -41,6 +44,19 @@ def _compile(src, verbose):
     return obj
 
 
+def sources_id():
+    """sha256 over the library's sources (csrc/*.hip, csrc/*.h, the public
+    header) and the compiler flags: what a built libtcbf.so must match."""
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.h")))
+    for f in files + [os.path.join(INCLUDE, "tcbf.h")]:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    h.update(" ".join(FLAGS[:-2]).encode())  # the flags, without this checkout's include paths
+    return h.hexdigest()
+
+
 def build(verbose=False):
     os.makedirs(BUILD, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
@@ -52,6 +68,8 @@ def build(verbose=False):
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
+    with open(SOURCES_ID, "w") as f:
+        f.write(sources_id() + "\n")
     return LIB
 
 

@@ -310,3 +310,12 @@ def test_no_undefined_internal_symbols():
     out = subprocess.run(["nm", "-D", "--undefined-only", tcbf.LIB_PATH], capture_output=True, text=True).stdout
     missing = [l.split()[-1] for l in out.splitlines() if "tcbf" in l]
     assert not missing, missing
+
+
+def test_built_library_matches_the_sources():
+    """The library was built from the sources in this tree (build writes their
+    identity beside it): a stale libtcbf.so would test and measure old code."""
+    from paper_2505_03269_amd import build as libbuild
+    assert os.path.exists(libbuild.SOURCES_ID), "libtcbf.so has no source identity: rebuild it"
+    assert open(libbuild.SOURCES_ID).read().strip() == libbuild.sources_id(), \
+        "libtcbf.so was built from other sources: rebuild it (python -m paper_2505_03269_amd.build)"

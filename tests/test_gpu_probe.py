@@ -3,6 +3,8 @@ ends at a closed-form count, which shows that every instruction of every
 round ran; the VALU kind is checked against its xor/popcount sum computed
 here; the clock marks are ordered; random operands give finite, repeatable
 results that differ from lane to lane."""
+import os
+
 import numpy as np
 import pytest
 
@@ -69,3 +71,10 @@ def test_probe_rejects_small_sink():
     sink = torch.empty(100, dtype=torch.uint8, device="cuda:0")
     with pytest.raises(ValueError):
         tcbf.peak_probe(tcbf.PROBE_F16, 1, 1, sink=sink)
+
+
+def test_library_on_the_device_matches_the_sources():
+    """The library these GPU tests load was built from the sources beside it."""
+    from paper_2505_03269_amd import build as libbuild
+    assert os.path.exists(libbuild.SOURCES_ID) and \
+        open(libbuild.SOURCES_ID).read().strip() == libbuild.sources_id(), "stale libtcbf.so: rebuild it"
