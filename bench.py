@@ -37,6 +37,13 @@ PEAK_HBM_GBS = 8000.0
 # The line's peak is the rate the peak probe sustains on the part (it issues
 # faster than this count assumes); the estimate is the fallback without it.
 PEAK_VALU_1BIT_TOPS = 256 * 64 * 2.4e9 * 32 / 1e12
+# Steering weights are bound by vector arithmetic (FP64 phase, sin/cos): the
+# kernel issues about 120 lane operations per complex weight (vector
+# instructions x 64 lanes / weights, from a counter run of the fp16 planar
+# output), against the fp32 vector lane rate of 256 CUs x 128 lanes x 2.4 GHz
+STEER_LANE_OPS_PER_WEIGHT = 120
+STEER_PEAK_GWS = 256 * 128 * 2.4 / STEER_LANE_OPS_PER_WEIGHT  # Gweights/s
+
 # the throughput goal for the radio-astronomy fp16 shape, as a fraction of
 # the published fp16 dense peak
 TARGET_FRAC_F16 = 0.70
@@ -662,6 +669,7 @@ def bench_secondary(steps, samples, serving=True, copy_gbs=None, valu_peak=None)
     ms = time_launches(lambda: tcbf.steering_weights(pos, dirs, freqs, wl.C0, out=Wst), st, 1)
     nbytes = Wst.numel() * 2 + (pos.numel() + dirs.numel() + freqs.numel()) * 8
     gbs = nbytes / (ms * 1e-3) / 1e9
+    gws = Wst.numel() / 2 / (ms * 1e-3) / 1e9
     # the same weights written straight into the blocked layout the product reads
     Wbl = torch.empty(tcbf.blocked_shape(256, 1024, 576), dtype=torch.float16, device="cuda:0")
     ms_bl = time_launches(lambda: tcbf.steering_weights(pos, dirs, freqs, wl.C0, out=Wbl, out_layout=tcbf.BLOCKED),
@@ -671,8 +679,13 @@ def bench_secondary(steps, samples, serving=True, copy_gbs=None, valu_peak=None)
                 "kernel": "steering_kernel", "value": round(gbs, 1), "unit": "GB/s", "ms_per_launch": round(ms, 4),
                 "blocked_output_ms_per_launch": round(ms_bl, 4),
                 "weights_per_s": round(Wst.numel() / 2 / (ms * 1e-3), 1),
-                "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                             "frac": round(gbs / PEAK_HBM_GBS, 4)}})
+                "roofline": {"bound": "alu", "achieved": round(gws, 1), "peak": round(STEER_PEAK_GWS, 1),
+                             "unit": "Gweights/s", "frac": round(gws / STEER_PEAK_GWS, 4),
+                             "peak_is": "fp32 vector lane rate (78.6e12 lane operations/s) / %d lane operations "
+                                        "per weight (kernel's vector instructions, counter run)"
+                                        % STEER_LANE_OPS_PER_WEIGHT},
+                "hbm": {"achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                        "frac": round(gbs / PEAK_HBM_GBS, 4)}})
     del Wst, pos, dirs, freqs
     # sign packing of int8 interleaved data shaped like the 1-bit X: [64][8192][8192][2]
     g = torch.Generator(device="cuda:0")
