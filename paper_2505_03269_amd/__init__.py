@@ -510,7 +510,7 @@ def group_execute(problems, c_layout=PLANAR, workspace=None, device=0, stream=No
     workspace: uint8 device tensor of GROUP_WORKSPACE_BYTES (allocated here
     if None; pass one to stay allocation-free).
     variants: fp16 only, one kernel variant per problem (0 = the plan's
-    default; e.g. the autotuner's choice, tune.tuned_variant); problems with
+    default; e.g. the autotuner's choice, tune.tune_group); problems with
     256-beam-tile variants (6, 7, 9) run in a grouped ping-pong launch, the
     rest in the grouped 128 x 128 launch.
     """
