@@ -1744,9 +1744,9 @@ static bool pp_ok(const Problem &p) {
     return fast_ok(q);
 }
 
-// Compute units of `device` (the persistent kernel runs one workgroup on
+// Compute units of `device` (the persistent kernels run one workgroup on
 // each); 256, the MI355X's count, when the runtime cannot say (no device).
-static int device_cus(int device) {
+int device_cus(int device) {
     int n = 0;
     if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) {
         (void)hipGetLastError();   // a planning query: leave no error for the caller's next check

@@ -178,7 +178,7 @@ tcbf_status tcbf_plan(const tcbf_plan_desc *desc, tcbf_plan_t *plan) {
         if (!tcbf::f16_select(p, desc->variant, &tmp.f16)) return TCBF_ERROR_INVALID_VALUE;
         wgs = tcbf::f16_workgroups(p, tmp.f16);
     } else if (is_f8(desc->dtype)) {
-        if (!tcbf::f8_select(p, desc->variant, &tmp.f8)) return TCBF_ERROR_INVALID_VALUE;
+        if (!tcbf::f8_select(p, d.dtype == TCBF_MXF8_E4M3, desc->variant, &tmp.f8)) return TCBF_ERROR_INVALID_VALUE;
         wgs = tcbf::f8_workgroups(p, tmp.f8);
     } else {
         if (!tcbf::int1_select(p, desc->variant, &tmp.int1)) return TCBF_ERROR_INVALID_VALUE;

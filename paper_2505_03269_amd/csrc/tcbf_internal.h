@@ -9,6 +9,10 @@
 
 namespace tcbf {
 
+// Compute units of a device (the persistent kernels run one workgroup on
+// each); 256, the MI355X's count, when the runtime cannot say.
+int device_cus(int device);
+
 // Geometry a launcher needs; filled by the plan from the public descriptor.
 struct Problem {
     int64_t batch, M, N, K;
@@ -52,7 +56,7 @@ hipError_t f16_group_launch(const Problem *probs, const void *const *A, const vo
 // FP8 modes (e4m3 codes in, fp32 out): per-row fp32 scales or per-32-block
 // E8M0 scales (mx).  Operands are receiver-contiguous with row pitch f8_kp(K).
 struct F8Config {
-    int variant;  // 1 = two-stage ring, 2 = three-stage ring
+    int variant;  // 1 = two-stage ring, 2 = three-stage ring, 3 = ping-pong persistent
     int tile_m, tile_n, tile_k, threads;
 };
 int64_t f8_kp(int64_t K);
@@ -61,7 +65,7 @@ int64_t f8_kp(int64_t K);
 // stored in groups of 16 codes per row, [Ks / 16][rows][16], so the product
 // kernel moves one group of consecutive rows with contiguous loads).
 __host__ __device__ inline int64_t mx_scale_pitch(int64_t kp) { return (kp / 32 + 15) / 16 * 16; }
-bool f8_select(const Problem &p, int forced_variant, F8Config *cfg);
+bool f8_select(const Problem &p, bool mx, int forced_variant, F8Config *cfg);
 int64_t f8_workgroups(const Problem &p, const F8Config &cfg);
 const char *f8_kernel_name(const F8Config &cfg);
 // Grouped FP8 launch (per-row or per-block scales, one kind per launch).

@@ -29,8 +29,8 @@ def _layouts(dtype, operand_layout):
 # candidate variants per dtype, seed first
 CANDIDATES = {
     F16: [2, 9, 8, 6, 3, 4, 5, 7, 1],   # 2: Table 3's MI300X point (128 x 128 tile, 2 x 2 waves of 64 x 64)
-    F8_E4M3: [1, 2],
-    MXF8_E4M3: [1, 2],
+    F8_E4M3: [1, 3, 2],   # 3: the 256 x 128 ping-pong persistent kernel
+    MXF8_E4M3: [1, 3, 2],
     INT1: [1, 3, 2],
 }
 

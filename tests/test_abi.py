@@ -75,7 +75,10 @@ def _plan_status(**kw):
     dict(dtype=tcbf.INT1, a_layout=tcbf.INTERLEAVED), dict(dtype=tcbf.INT1, b_layout=tcbf.INTERLEAVED),
     dict(dtype=tcbf.INT1, variant=7),
     dict(dtype=tcbf.F8_E4M3, a_layout=tcbf.INTERLEAVED), dict(dtype=tcbf.MXF8_E4M3, b_layout=tcbf.INTERLEAVED),
-    dict(dtype=tcbf.F8_E4M3, N=6), dict(dtype=tcbf.MXF8_E4M3, N=1), dict(dtype=tcbf.F8_E4M3, variant=3),
+    dict(dtype=tcbf.F8_E4M3, N=6), dict(dtype=tcbf.MXF8_E4M3, N=1), dict(dtype=tcbf.F8_E4M3, variant=4),
+    # FP8 ping-pong with per-block scales: every 8-stage scale group spans two stages or more
+    dict(dtype=tcbf.MXF8_E4M3, variant=3, K=576), dict(dtype=tcbf.MXF8_E4M3, variant=3, K=1),
+    dict(dtype=tcbf.MXF8_E4M3, a_layout=tcbf.BLOCKED, b_layout=tcbf.BLOCKED, variant=3, K=2049),
     dict(dtype=5),
     # bfloat16: variants 1, 2 and 9 only (9 with planar X), not in grouped launches
     dict(dtype=tcbf.BF16, variant=3), dict(dtype=tcbf.BF16, variant=6), dict(dtype=tcbf.BF16, variant=8),
