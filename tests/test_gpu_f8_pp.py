@@ -139,3 +139,37 @@ def test_pp_ultrasound_shape_full_output(dtype):
     ref = execute(v1, A, B, sa, sb)
     assert not torch.isnan(got).any()
     assert torch.equal(got, ref)
+
+
+@pytest.mark.parametrize("dtype", [tcbf.F8_E4M3, tcbf.MXF8_E4M3])
+def test_pp_graph_replays_match_eager(dtype):
+    """The ping-pong plan captured in a HIP graph and replayed with new X
+    codes quantised eagerly between replays equals variant 1 every time."""
+    block = 0 if dtype == tcbf.F8_E4M3 else 32
+    batch, M, N, K = 2, 520, 264, 1024
+    kw = dict(a_layout=tcbf.BLOCKED, b_layout=tcbf.BLOCKED)
+    Wq, Ws, Xq, Xs = quantised(80, batch, M, N, K, block, tcbf.BLOCKED)
+    pp = tcbf.Plan(batch, M, N, K, dtype, variant=PP, **kw)
+    v1 = tcbf.Plan(batch, M, N, K, dtype, variant=1, **kw)
+    C = pp.empty_output()
+    pp.execute(Wq, Xq, C, Ws, Xs)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            pp.execute(Wq, Xq, C, Ws, Xs)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    gen = torch.Generator(device="cuda:0")
+    gen.manual_seed(9)
+    for rep in range(3):
+        X = torch.randint(-127, 128, (batch, 2, K, N), device="cuda:0", generator=gen).half()
+        tcbf.quantize_e4m3(X, k_major=False, block=block, out=Xq, scales=Xs, out_layout=tcbf.BLOCKED)
+        C.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        ref = execute(v1, Wq, Xq, Ws, Xs)
+        assert torch.equal(C, ref), "replay %d" % rep
