@@ -169,7 +169,8 @@ typedef struct tcbf_plan_desc {
  * rings for W (two deep) and X (three deep); 9 a persistent 256 x 128 tile
  * whose two wave groups alternate matrix and data phases (one workgroup per
  * CU).  The default is 9 for problems with at least as many 256 x 128 tiles
- * as the device has CUs, else 2.  TCBF_F8_E4M3 / TCBF_MXF8_E4M3: 1 (default)
+ * as the device has CUs and K > 32 (2 or more stages of 32 receivers per
+ * tile), else 2.  TCBF_F8_E4M3 / TCBF_MXF8_E4M3: 1 (default)
  * 128 x 128 tile, two-deep ring, 2 three-deep, 3 the persistent 256 x 128
  * ping-pong tile (TCBF_MXF8_E4M3 only where ceil(Kp / 64) % 8 != 1).  TCBF_INT1: 1 int8 matrix instructions on
  * +-1 expanded to {0, 1}, 2 XOR + popcount on the vector ALU, 3 e2m1 (4-bit

@@ -1757,8 +1757,13 @@ int device_cus(int device) {
 
 // Default choice: the persistent ping-pong kernel once the problem has at
 // least a 256 x 128 tile for every compute unit (it runs one workgroup per
-// CU and measured 4-13% faster than variant 2 on such shapes), variant 2 for
-// smaller problems, the generic kernel where the fast ones do not apply.
+// CU and measured 4-13% faster than variant 2 on such shapes) and a tile
+// runs at least 2 stages of 32 receivers; variant 2 for smaller problems and
+// for one-stage tiles (there the ping-pong kernel's end-of-tile stores
+// dominate, while variant 2's second workgroup on the CU multiplies during
+// them: 256 x 1024 x 1024 x K, K = 8..32, 4-9% faster with inputs streamed
+// from memory; from K = 48 the ping-pong kernel is 7-19% faster so), the
+// generic kernel where the fast ones do not apply.
 static int default_variant_f16(const Problem &p) {
     if (p.b_kmajor) return 1;  // receiver-contiguous X: the generic kernel
     const int64_t tiles = p.batch * ((p.M + 255) / 256) * ((p.N + BN - 1) / BN);
@@ -1770,7 +1775,8 @@ static int default_variant_f16(const Problem &p) {
                    ? kPingPong
                    : 1;
     if (!fast_ok(p)) return 1;
-    return big ? kPingPong : kDefaultFast;
+    const bool deep = (p.K + 31) / 32 >= 2;  // stages per tile
+    return big && deep ? kPingPong : kDefaultFast;
 }
 
 // bfloat16 operands run in variants 1, 2 and 9 (planar X for 9).
