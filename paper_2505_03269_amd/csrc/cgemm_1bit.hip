@@ -190,16 +190,21 @@ __device__ __forceinline__ void int1_tile(const uint32_t *__restrict__ A, const 
 
     const bool full = (m0 + U_BM <= M) && (n0 + U_BN <= N);
     const int K2 = (int)(2 * K);
+    // the lane's row and column offsets, opaque to the compiler: in the
+    // grouped persistent kernel it would otherwise hoist the 32 row offsets
+    // below out of the tile loop and spill them
+    int hl_e = hl, l32_e = l32;
+    asm volatile("" : "+v"(hl_e), "+v"(l32_e));
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) {
-            const int lc = wn * 64 + j * 32 + l32;
+            const int lc = wn * 64 + j * 32 + l32_e;
             const int64_t col = n0 + lc;
             const int bsr = popB[0][lc], bsi = popB[1][lc];
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                const int lr = wm * 64 + i * 32 + (r >> 2) * 8 + hl * 4 + (r & 3);
+                const int lr = wm * 64 + i * 32 + (r >> 2) * 8 + hl_e * 4 + (r & 3);
                 const int64_t row = m0 + lr;
                 if (full || (row < M && col < N)) {
                     const int asum = popA[0][lr] + popA[1][lr];

@@ -17,8 +17,7 @@ results, which no parity test notices; the kernel descriptors in the generated
 code say it directly.  Known users, all off the default paths: the fast-kernel
 variants with more than two stage buffers in their epilogue staging (3, 4, 6,
 7) and the split ring (8), whose staged-row selects become a scratch table of
-LDS pointers, and the 1-bit int8-MFMA grouped kernel, which spills a few
-hoisted row offsets.
+LDS pointers.
 """
 import os
 import re
@@ -125,8 +124,7 @@ def _all_generated():
 
 
 # kernels allowed to use scratch (see the module note): mangled-name fragments
-KNOWN_SCRATCH = ("cgemm_f16_fast_kernelILi2ELi16E", "cgemm_f16_fast_kernelILi4E", "cgemm_f16_split_kernel",
-                 "cgemm_1bit_group_kernel")
+KNOWN_SCRATCH = ("cgemm_f16_fast_kernelILi2ELi16E", "cgemm_f16_fast_kernelILi4E", "cgemm_f16_split_kernel")
 
 
 @pytest.mark.skipif(not os.path.exists(libbuild.HIPCC) and shutil.which("hipcc") is None, reason="no hipcc")
