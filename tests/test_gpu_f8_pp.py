@@ -173,3 +173,29 @@ def test_pp_graph_replays_match_eager(dtype):
         torch.cuda.synchronize()
         ref = execute(v1, Wq, Xq, Ws, Xs)
         assert torch.equal(C, ref), "replay %d" % rep
+
+
+def test_pp_seeded_random_shapes():
+    """Forty seeded shapes (batch 1-6, M 1-1100, N a multiple of 4 up to 700,
+    K 1-3000), each dtype and code layout: variant 3 equals variant 1 bit for
+    bit wherever the plan accepts it, and refuses per-block scales exactly
+    where an 8-stage scale group would span one stage."""
+    rng = np.random.default_rng(2025)
+    for i in range(40):
+        batch = int(rng.integers(1, 7))
+        M = int(rng.integers(1, 1101))
+        N = 4 * int(rng.integers(1, 176))
+        K = int(rng.integers(1, 3001))
+        dtype = tcbf.F8_E4M3 if i % 2 == 0 else tcbf.MXF8_E4M3
+        layout = tcbf.PLANAR if (i // 2) % 2 == 0 else tcbf.BLOCKED
+        block = 0 if dtype == tcbf.F8_E4M3 else 32
+        kw = dict(a_layout=layout, b_layout=layout)
+        if block and nk_of(K) % 8 == 1:
+            with pytest.raises(tcbf.TcbfError):
+                tcbf.Plan(batch, M, N, K, dtype, variant=PP, **kw)
+            continue
+        log("f8 pp random %d: dtype=%d %d x %d x %d x %d layout %d" % (i, dtype, batch, M, N, K, layout))
+        Wq, Ws, Xq, Xs = quantised(500 + i, batch, M, N, K, block, layout)
+        got = execute(tcbf.Plan(batch, M, N, K, dtype, variant=PP, **kw), Wq, Xq, Ws, Xs)
+        ref = execute(tcbf.Plan(batch, M, N, K, dtype, variant=1, **kw), Wq, Xq, Ws, Xs)
+        assert torch.equal(got, ref), "shape %d" % i
