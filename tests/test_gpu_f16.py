@@ -387,3 +387,32 @@ def test_c2_full_size_interleaved_equals_planar():
     pi.execute(Ab, Bi, Ci)
     torch.cuda.synchronize()
     assert torch.equal(Cp, Ci.permute(0, 3, 1, 2))
+
+
+def test_seeded_random_shapes_default_plan_and_variants():
+    """Thirty seeded shapes (batch 1-5, M 1-700, N a multiple of 8 up to 520,
+    K 1-1200; K a multiple of 8 in every other one so the fast kernels take
+    them): the default plan (whichever kernel its rule picks) is within the
+    gate against the oracle, and every variant that accepts the shape gives
+    the default plan's output bit for bit."""
+    rng = np.random.default_rng(77)
+    for i in range(30):
+        batch = int(rng.integers(1, 6))
+        M = int(rng.integers(1, 701))
+        N = 8 * int(rng.integers(1, 66))
+        K = int(rng.integers(1, 1201))
+        if i % 2 == 0:
+            K = 8 * ((K + 7) // 8)
+        W, X = wl.random_f16_case(1000 + i, batch, M, N, K)
+        plan = tcbf.Plan(batch, M, N, K, tcbf.F16)
+        log("random shape %d: %d x %d x %d x %d, default variant %d" % (i, batch, M, N, K, plan.info()["variant"]))
+        got, _ = run_f16(W, X)
+        ref, absdot = oracle_ref(W, X)
+        check_fp_full(got, ref, absdot, K)
+        for v in [1] + FAST_VARIANTS:
+            try:
+                tcbf.Plan(batch, M, N, K, tcbf.F16, variant=v)
+            except tcbf.TcbfError:
+                continue
+            out, _ = run_f16(W, X, variant=v)
+            assert np.array_equal(out, got), "shape %d: variant %d differs from the default plan" % (i, v)
