@@ -113,14 +113,15 @@ __global__ __launch_bounds__(NT) void pack_nmajor_kernel(const T *__restrict__ s
 // 8 bytes of each plane); a wave load covers 64 * 8 consecutive row bytes per
 // plane.  Needs rows % R == 0.
 //
-// Receivers go in rounds of 8 with all 8 loads issued before any is used, so
-// every thread keeps 8 loads in flight.  The sign bits of a round are
-// gathered without per-element work: shifting receiver u's dword right by
-// (element width - 1 - u) puts each element's sign bit at bit u of that
-// element's field, so OR-ing the 8 masked dwords collects, per element, its 8
-// receivers' signs in the low byte of its field; one complement turns sign
-// bits into the +1 bits, and each byte lands in its row's word at the
-// round's bit offset.
+// Receivers go in rounds of 16 with all 16 loads issued before any is used,
+// so every thread keeps 16 loads in flight (2% faster than rounds of 8 on
+// int8 [16][8192][8192][2]; a 32-bit word's tail takes rounds of 8 and 1).
+// The sign bits of each group of 8 receivers are gathered without
+// per-element work: shifting receiver u's dword right by (element width - 1
+// - u) puts each element's sign bit at bit u of that element's field, so
+// OR-ing the 8 masked dwords collects, per element, its 8 receivers' signs
+// in the low byte of its field; one complement turns sign bits into the +1
+// bits, and each byte lands in its row's word at the group's bit offset.
 template <int IL> struct RawRows;
 template <> struct RawRows<1> {
     static __device__ __forceinline__ u32x4 load(const void *p, int64_t) {
@@ -178,6 +179,27 @@ __global__ __launch_bounds__(VNT) void pack_nmajor_vec_kernel(const T *__restric
         if (32 * q >= n) break;
         const int m = n - 32 * q < 32 ? n - 32 * q : 32;
         int b = 0;
+        // rounds of 16 receivers (16 loads in flight), gathered as two groups of 8
+        for (; b + 16 <= m; b += 16) {
+            u32x4 d[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) d[u] = RawRows<IL>::load(base + (int64_t)(32 * q + b + u) * kstep, plane_bytes);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                u32x4 t = (u32x4){0u, 0u, 0u, 0u};
+#pragma unroll
+                for (int u = 0; u < 8; ++u) t |= (d[8 * h + u] >> (uint32_t)(W - 1 - u)) & (LOW << u);
+                t = ~t;
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    int pl, row;
+                    place(e, pl, row);
+                    const uint32_t byte = (t[e / EPD] >> (W * (e % EPD))) & 0xffu;
+                    if (pl) wi[row][q] |= byte << (b + 8 * h);
+                    else wr[row][q] |= byte << (b + 8 * h);
+                }
+            }
+        }
         for (; b + 8 <= m; b += 8) {
             u32x4 d[8];
 #pragma unroll
